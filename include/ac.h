@@ -1,0 +1,112 @@
+/*
+ * ac.h -- C ABI of libac, an MI355X (gfx950) stepper for the Allen-Cahn
+ * equation by the explicit finite-difference method of
+ * Kim, "Fast Numerical Simulation of Allen-Cahn Equation".
+ *
+ * The operation (section 2.1, Eq. pytorchACeq, with the zero-Neumann boundary
+ * of section 2):
+ *
+ *   phi_{c}^{n+1} = phi_c^n + dt * ( (phi_c^n - (phi_c^n)^3) / eps^2 + Lap_h phi_c^n )
+ *   Lap_h phi_c  = ( sum of the 2d axis neighbours of c  -  2d * phi_c ) / h^2
+ *
+ * where a neighbour outside the grid is replaced by phi_c itself (the ghost
+ * layer equals the adjacent interior cell).  d = 2 uses the 5-point stencil,
+ * d = 3 the 7-point one.  The library evaluates it as
+ *   phi + alpha*(phi - phi^3) + r*(S - 2d*phi),   alpha = dt/eps^2, r = dt/h^2,
+ * with alpha and r derived once on the host in double precision (rounded once
+ * to float for AC_F32).
+ *
+ * Conventions shared by every call:
+ *   - phi and work are device pointers to contiguous row-major arrays, x
+ *     fastest: 2D index j*nx + i, 3D index (k*ny + j)*nx + i.  Both hold
+ *     nx*ny[*nz] elements of the given dtype and are owned by the caller; the
+ *     library keeps no pointer after the call returns.
+ *   - On return the state after nsteps steps is (will be, in stream order) in
+ *     phi; work is clobbered.  phi and work must not overlap.
+ *   - Calls are asynchronous on `stream` (a hipStream_t; NULL = the null
+ *     stream).  Argument errors are reported before any HIP call is made.
+ *     Kernel faults surface at the caller's next synchronisation; ac_check()
+ *     synchronises the stream and maps a HIP error to AC_ERR_HIP.
+ *   - The return value is an ac_status; ac_last_error() gives a thread-local
+ *     message for the last failing call.
+ *   - Stability: the call is refused with AC_ERR_UNSTABLE unless
+ *       r <= 1/(2d)  and  alpha <= (1 - 2 d r)/2,
+ *     the conditions under which |phi| <= 1 is preserved (maximum principle)
+ *     for the scheme above.  dt = 0.1 h^2 (section 2) gives r = 0.1, so any
+ *     eps_m with m >= 3 passes in 2D and 3D.
+ */
+#ifndef AC_H
+#define AC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    AC_OK = 0,
+    AC_ERR_INVALID_ARG = 1, /* null/overlapping/misaligned pointer, bad size, non-finite or <= 0 h/dt/eps */
+    AC_ERR_UNSTABLE = 2,    /* r or alpha outside the maximum-principle bounds above */
+    AC_ERR_UNSUPPORTED = 3, /* a tuning request the library cannot honour */
+    AC_ERR_HIP = 4,         /* a HIP runtime call failed */
+    AC_ERR_NOMEM = 5        /* device or host allocation failed */
+} ac_status;
+
+typedef enum { AC_F32 = 0, AC_F64 = 1 } ac_dtype;
+
+/* Optional launch shape for the tiled kernels.  Zero fields mean "choose":
+ * the library then uses its tuning table (ac_autotune) or a built-in default.
+ *   tb_depth  time steps fused per launch (temporal blocking), 1..8
+ *   tile_x/y  loaded tile extent in cells, including the tb_depth halo
+ *   tile_z    2D: unused; 3D: z-extent of one streamed column segment
+ * Any valid choice gives bitwise the same result: every cell is always
+ * updated by the same expression from the same neighbour values. */
+typedef struct {
+    int32_t tb_depth;
+    int32_t tile_x;
+    int32_t tile_y;
+    int32_t tile_z;
+} ac_tune;
+
+/* 2D step, 5-point stencil (section 2.1, Eq. pytorchACeq).  phi, work: nx*ny
+ * elements of dtype (AC_F32 or AC_F64), 16-byte aligned.  nsteps = 0 is a
+ * no-op.  Grids whose state fits one workgroup's LDS run all steps in one
+ * launch; larger grids run ceil(nsteps / tb_depth) tiled launches. */
+ac_status ac_step_2d(void *phi, void *work, int32_t nx, int32_t ny,
+                     double h, double dt, double eps, int64_t nsteps,
+                     int32_t dtype, void *stream);
+
+/* As ac_step_2d with an explicit launch shape (NULL = as ac_step_2d).
+ * tune->tile_x/y = -1 forces the tiled path even for small grids. */
+ac_status ac_step_2d_tuned(void *phi, void *work, int32_t nx, int32_t ny,
+                           double h, double dt, double eps, int64_t nsteps,
+                           int32_t dtype, const ac_tune *tune, void *stream);
+
+/* 3D step, 7-point stencil: the extension of the 2D scheme the paper calls
+ * immediate (section 2).  phi, work: nx*ny*nz elements, 16-byte aligned. */
+ac_status ac_step_3d(void *phi, void *work, int32_t nx, int32_t ny, int32_t nz,
+                     double h, double dt, double eps, int64_t nsteps,
+                     int32_t dtype, void *stream);
+
+ac_status ac_step_3d_tuned(void *phi, void *work, int32_t nx, int32_t ny, int32_t nz,
+                           double h, double dt, double eps, int64_t nsteps,
+                           int32_t dtype, const ac_tune *tune, void *stream);
+
+/* Synchronise `stream` and report any pending HIP error as AC_ERR_HIP. */
+ac_status ac_check(void *stream);
+
+/* Static description of a status code. */
+const char *ac_status_string(int32_t status);
+
+/* Thread-local message describing the last failing call ("" if none). */
+const char *ac_last_error(void);
+
+/* Library version, major*10000 + minor*100 + patch. */
+int32_t ac_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AC_H */

@@ -1,0 +1,72 @@
+"""ctypes loader for libac.so (argument marshalling only).
+
+``import torch`` happens first so that libac binds to the HIP runtime torch
+already loaded (both carry the soname libamdhip64.so.7): one runtime, one
+device context, and torch's stream handles are valid inside libac.
+
+The library must have been built (``paper_2105_09671_amd.build.build()``);
+there is no fallback of any kind when it is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # noqa: F401  (load torch's HIP runtime before libac)
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libac.so")
+
+AC_OK, AC_ERR_INVALID_ARG, AC_ERR_UNSTABLE, AC_ERR_UNSUPPORTED, AC_ERR_HIP, AC_ERR_NOMEM = range(6)
+AC_F32, AC_F64 = 0, 1
+
+
+class AcTune(ctypes.Structure):
+    _fields_ = [("tb_depth", ctypes.c_int32), ("tile_x", ctypes.c_int32),
+                ("tile_y", ctypes.c_int32), ("tile_z", ctypes.c_int32)]
+
+
+class AcError(RuntimeError):
+    def __init__(self, status: int, fn: str, msg: str):
+        super().__init__("%s failed: status %d (%s)" % (fn, status, msg))
+        self.status = status
+
+
+_lib = None
+
+_vp, _i32, _i64, _dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+
+SIGNATURES = {
+    "ac_step_2d": ([_vp, _vp, _i32, _i32, _dbl, _dbl, _dbl, _i64, _i32, _vp], _i32),
+    "ac_step_2d_tuned": ([_vp, _vp, _i32, _i32, _dbl, _dbl, _dbl, _i64, _i32,
+                          ctypes.POINTER(AcTune), _vp], _i32),
+    "ac_step_3d": ([_vp, _vp, _i32, _i32, _i32, _dbl, _dbl, _dbl, _i64, _i32, _vp], _i32),
+    "ac_step_3d_tuned": ([_vp, _vp, _i32, _i32, _i32, _dbl, _dbl, _dbl, _i64, _i32,
+                          ctypes.POINTER(AcTune), _vp], _i32),
+    "ac_check": ([_vp], _i32),
+    "ac_status_string": ([_i32], ctypes.c_char_p),
+    "ac_last_error": ([], ctypes.c_char_p),
+    "ac_version": ([], _i32),
+}
+
+
+def lib():
+    """The loaded libac (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libac.so is not built at %s; run __graft_entry__.build() "
+                               "(there is no non-HIP fallback)" % LIB_PATH)
+        l = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in SIGNATURES.items():
+            f = getattr(l, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = l
+    return _lib
+
+
+def check(status: int, fn: str) -> None:
+    if status != AC_OK:
+        msg = lib().ac_last_error().decode()
+        raise AcError(status, fn, msg or lib().ac_status_string(status).decode())

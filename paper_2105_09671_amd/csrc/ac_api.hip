@@ -1,0 +1,268 @@
+// libac C ABI: argument validation, parameter derivation and launch planning
+// for the 2D and 3D steppers.  Declarations and semantics: include/ac.h.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+
+#include "ac_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+ac_status fail(ac_status s, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+ac_status hip_fail(hipError_t e, const char *what) {
+    return fail(AC_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+size_t elem_size(int32_t dtype) { return dtype == AC_F64 ? 8 : 4; }
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+// Checks shared by every stepping entry point.  Makes no HIP call.
+ac_status validate(const void *phi, const void *work, int64_t ncells, int dim, double h,
+                   double dt, double eps, int64_t nsteps, int32_t dtype, double *alpha,
+                   double *r) {
+    if (dtype != AC_F32 && dtype != AC_F64)
+        return fail(AC_ERR_INVALID_ARG, "dtype must be AC_F32 (0) or AC_F64 (1), got %d", dtype);
+    if (!phi || !work) return fail(AC_ERR_INVALID_ARG, "phi and work must be non-null");
+    if ((reinterpret_cast<uintptr_t>(phi) | reinterpret_cast<uintptr_t>(work)) & 15u)
+        return fail(AC_ERR_INVALID_ARG, "phi and work must be 16-byte aligned");
+    const size_t bytes = (size_t)ncells * elem_size(dtype);
+    const uintptr_t a = reinterpret_cast<uintptr_t>(phi), b = reinterpret_cast<uintptr_t>(work);
+    if (a < b + bytes && b < a + bytes)
+        return fail(AC_ERR_INVALID_ARG, "phi and work overlap");
+    if (!finite_pos(h) || !finite_pos(dt) || !finite_pos(eps))
+        return fail(AC_ERR_INVALID_ARG, "h, dt and eps must be finite and > 0 (h=%g dt=%g eps=%g)",
+                    h, dt, eps);
+    if (nsteps < 0) return fail(AC_ERR_INVALID_ARG, "nsteps must be >= 0, got %lld", (long long)nsteps);
+    *alpha = dt / (eps * eps);
+    *r = dt / (h * h);
+    if (*r > 1.0 / (2.0 * dim))
+        return fail(AC_ERR_UNSTABLE, "r = dt/h^2 = %g exceeds 1/(2d) = %g", *r, 1.0 / (2.0 * dim));
+    const double amax = (1.0 - 2.0 * dim * *r) / 2.0;
+    if (*alpha > amax)
+        return fail(AC_ERR_UNSTABLE, "alpha = dt/eps^2 = %g exceeds (1 - 2d r)/2 = %g", *alpha, amax);
+    return AC_OK;
+}
+
+// Split nsteps into launches of at most k steps such that the number of
+// launches is even (ping-pong then ends in phi).  Returns false if that is
+// impossible (every launch is a single step and the count is odd): the caller
+// then copies work back into phi at the end.
+struct Chunks {
+    int64_t n, base, rem;  // n launches; launch i does base + (i < rem) steps
+    bool copy_back;
+};
+Chunks plan_chunks(int64_t nsteps, int64_t k) {
+    Chunks c{};
+    c.n = (nsteps + k - 1) / k;
+    c.copy_back = false;
+    if (c.n & 1) {
+        if (nsteps >= c.n + 1) c.n += 1;
+        else c.copy_back = true;
+    }
+    c.base = nsteps / c.n;
+    c.rem = nsteps % c.n;
+    return c;
+}
+
+template <typename T>
+ac_status run2d(T *phi, T *work, int nx, int ny, double alpha_d, double r_d, int64_t nsteps,
+                const ac_tune *tune, hipStream_t stream) {
+    ac::DevInfo dev;
+    hipError_t e = ac::device_info(&dev);
+    if (e != hipSuccess) return hip_fail(e, "device query");
+    const T alpha = (T)alpha_d, r = (T)r_d;
+    const bool force_tiled = tune && (tune->tile_x < 0 || tune->tile_y < 0);
+    const size_t resident_lds = ac::tile2d_lds_bytes(nx, ny, sizeof(T));
+    if (!force_tiled && resident_lds <= dev.lds_per_block) {
+        // whole grid in one workgroup: all steps in LDS, in place in phi
+        ac::Tile2D t{nx, ny, 0, 1024};
+        for (int64_t done = 0; done < nsteps;) {
+            const int k = (int)std::min<int64_t>(nsteps - done, INT_MAX);
+            e = ac::launch_tile2d<T>(phi, phi, nx, ny, alpha, r, t, k, stream);
+            if (e != hipSuccess) return hip_fail(e, "resident 2D launch");
+            done += k;
+        }
+        return AC_OK;
+    }
+    const bool f64 = sizeof(T) == 8;
+    int K = 4, LX = 128, LY = f64 ? 32 : 64, threads = 256;
+    if (tune) {
+        if (tune->tb_depth) K = tune->tb_depth;
+        if (tune->tile_x > 0) LX = tune->tile_x;
+        if (tune->tile_y > 0) LY = tune->tile_y;
+    }
+    if (K < 1 || K > 8) return fail(AC_ERR_UNSUPPORTED, "tb_depth must be 1..8, got %d", K);
+    if (LX < 2 * K + 1 || LY < 2 * K + 1 || LX > 4096 || LY > 4096)
+        return fail(AC_ERR_UNSUPPORTED, "tile %dx%d too small/large for depth %d", LX, LY, K);
+    if (ac::tile2d_lds_bytes(LX, LY, sizeof(T)) > dev.lds_per_block)
+        return fail(AC_ERR_UNSUPPORTED, "tile %dx%d needs %zu B LDS > %zu", LX, LY,
+                    ac::tile2d_lds_bytes(LX, LY, sizeof(T)), dev.lds_per_block);
+    ac::Tile2D t{LX, LY, K, threads};
+    const Chunks c = plan_chunks(nsteps, K);
+    T *src = phi, *dst = work;
+    for (int64_t i = 0; i < c.n; ++i) {
+        const int k = (int)(c.base + (i < c.rem ? 1 : 0));
+        e = ac::launch_tile2d<T>(src, dst, nx, ny, alpha, r, t, k, stream);
+        if (e != hipSuccess) return hip_fail(e, "tiled 2D launch");
+        T *tmp = src; src = dst; dst = tmp;
+    }
+    if (c.copy_back) {
+        e = hipMemcpyAsync(phi, src, (size_t)nx * ny * sizeof(T), hipMemcpyDeviceToDevice, stream);
+        if (e != hipSuccess) return hip_fail(e, "copy back");
+    }
+    return AC_OK;
+}
+
+template <typename T>
+ac_status run3d(T *phi, T *work, int nx, int ny, int nz, double alpha_d, double r_d,
+                int64_t nsteps, const ac_tune *tune, hipStream_t stream) {
+    ac::DevInfo dev;
+    hipError_t e = ac::device_info(&dev);
+    if (e != hipSuccess) return hip_fail(e, "device query");
+    const T alpha = (T)alpha_d, r = (T)r_d;
+    const bool f64 = sizeof(T) == 8;
+    int K = 2, LX = 64, LY = f64 ? 16 : 32, LZ = 64, threads = f64 ? 256 : 512;
+    if (tune) {
+        if (tune->tb_depth) K = tune->tb_depth;
+        if (tune->tile_x > 0) LX = tune->tile_x;
+        if (tune->tile_y > 0) LY = tune->tile_y;
+        if (tune->tile_z > 0) LZ = tune->tile_z;
+    }
+    if (K < 1 || K > 8) return fail(AC_ERR_UNSUPPORTED, "tb_depth must be 1..8, got %d", K);
+    if (LX < 2 * K + 1 || LY < 2 * K + 1 || LZ < 1)
+        return fail(AC_ERR_UNSUPPORTED, "tile %dx%dx%d too small for depth %d", LX, LY, LZ, K);
+    ac::Tile3D t{LX, LY, LZ, K, threads};
+    if (ac::stream3d_cells_per_thread(t) > 4)
+        return fail(AC_ERR_UNSUPPORTED, "tile %dx%d has more than 4 cells per thread", LX, LY);
+    if (ac::stream3d_lds_bytes(t, sizeof(T)) > dev.lds_per_block)
+        return fail(AC_ERR_UNSUPPORTED, "3D tile needs %zu B LDS > %zu",
+                    ac::stream3d_lds_bytes(t, sizeof(T)), dev.lds_per_block);
+    const Chunks c = plan_chunks(nsteps, K);
+    T *src = phi, *dst = work;
+    for (int64_t i = 0; i < c.n; ++i) {
+        t.K = (int)(c.base + (i < c.rem ? 1 : 0));
+        e = ac::launch_stream3d<T>(src, dst, nx, ny, nz, alpha, r, t, stream);
+        if (e != hipSuccess) return hip_fail(e, "3D launch");
+        T *tmp = src; src = dst; dst = tmp;
+    }
+    if (c.copy_back) {
+        e = hipMemcpyAsync(phi, src, (size_t)nx * ny * nz * sizeof(T), hipMemcpyDeviceToDevice,
+                           stream);
+        if (e != hipSuccess) return hip_fail(e, "copy back");
+    }
+    return AC_OK;
+}
+
+}  // namespace
+
+namespace ac {
+
+hipError_t device_info(DevInfo *out) {
+    static std::mutex mu;
+    static DevInfo cache[64];
+    static bool have[64];
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!have[dev]) {
+        int cus = 0, lds = 0;
+        if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+            return e;
+        if ((e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev)) != hipSuccess)
+            return e;
+        cache[dev].cus = cus;
+        cache[dev].lds_per_block = (size_t)lds;
+        cache[dev].xcds = 8;
+        have[dev] = true;
+    }
+    *out = cache[dev];
+    return hipSuccess;
+}
+
+}  // namespace ac
+
+extern "C" {
+
+ac_status ac_step_2d_tuned(void *phi, void *work, int32_t nx, int32_t ny, double h, double dt,
+                           double eps, int64_t nsteps, int32_t dtype, const ac_tune *tune,
+                           void *stream) {
+    g_err.clear();
+    if (nx < 1 || ny < 1) return fail(AC_ERR_INVALID_ARG, "nx, ny must be >= 1 (%d x %d)", nx, ny);
+    double alpha, r;
+    ac_status s = validate(phi, work, (int64_t)nx * ny, 2, h, dt, eps, nsteps, dtype, &alpha, &r);
+    if (s != AC_OK || nsteps == 0) return s;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (dtype == AC_F64)
+        return run2d<double>((double *)phi, (double *)work, nx, ny, alpha, r, nsteps, tune, st);
+    return run2d<float>((float *)phi, (float *)work, nx, ny, alpha, r, nsteps, tune, st);
+}
+
+ac_status ac_step_2d(void *phi, void *work, int32_t nx, int32_t ny, double h, double dt,
+                     double eps, int64_t nsteps, int32_t dtype, void *stream) {
+    return ac_step_2d_tuned(phi, work, nx, ny, h, dt, eps, nsteps, dtype, nullptr, stream);
+}
+
+ac_status ac_step_3d_tuned(void *phi, void *work, int32_t nx, int32_t ny, int32_t nz, double h,
+                           double dt, double eps, int64_t nsteps, int32_t dtype,
+                           const ac_tune *tune, void *stream) {
+    g_err.clear();
+    if (nx < 1 || ny < 1 || nz < 1)
+        return fail(AC_ERR_INVALID_ARG, "nx, ny, nz must be >= 1 (%d x %d x %d)", nx, ny, nz);
+    double alpha, r;
+    ac_status s = validate(phi, work, (int64_t)nx * ny * nz, 3, h, dt, eps, nsteps, dtype, &alpha, &r);
+    if (s != AC_OK || nsteps == 0) return s;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (dtype == AC_F64)
+        return run3d<double>((double *)phi, (double *)work, nx, ny, nz, alpha, r, nsteps, tune, st);
+    return run3d<float>((float *)phi, (float *)work, nx, ny, nz, alpha, r, nsteps, tune, st);
+}
+
+ac_status ac_step_3d(void *phi, void *work, int32_t nx, int32_t ny, int32_t nz, double h,
+                     double dt, double eps, int64_t nsteps, int32_t dtype, void *stream) {
+    return ac_step_3d_tuned(phi, work, nx, ny, nz, h, dt, eps, nsteps, dtype, nullptr, stream);
+}
+
+ac_status ac_check(void *stream) {
+    hipError_t e = hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream));
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "ac_check");
+    return AC_OK;
+}
+
+const char *ac_status_string(int32_t s) {
+    switch (s) {
+    case AC_OK: return "ok";
+    case AC_ERR_INVALID_ARG: return "invalid argument";
+    case AC_ERR_UNSTABLE: return "time step outside the stability bounds";
+    case AC_ERR_UNSUPPORTED: return "unsupported configuration";
+    case AC_ERR_HIP: return "HIP runtime error";
+    case AC_ERR_NOMEM: return "out of memory";
+    default: return "unknown status";
+    }
+}
+
+const char *ac_last_error(void) { return g_err.c_str(); }
+
+int32_t ac_version(void) { return 100; }
+
+}  // extern "C"

@@ -1,0 +1,84 @@
+// Internal declarations shared by the libac translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "ac.h"
+
+namespace ac {
+
+// ---------------------------------------------------------------------------
+// The explicit Allen-Cahn update of one cell (section 2.1, Eq. pytorchACeq):
+//   phi' = phi + alpha*(phi - phi^3) + r*(S - 2d*phi),
+//   alpha = dt/eps^2, r = dt/h^2, S = sum of the axis neighbours.
+// The neighbour sum is paired per axis, (x- + x+) + (y- + y+) [+ (z- + z+)],
+// and the remaining products are fused multiply-adds written out explicitly,
+// so every kernel (any tile shape, any temporal-blocking depth) rounds
+// identically.  phi = +-1 and phi = 0 are bitwise fixed points:
+//   c = +-1: c*c = 1, fma(-1, c, c) = 0, and S = 2d*c exactly.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+template <typename T>
+__device__ __forceinline__ T react_and_diffuse(T c, T s, T two_d, T alpha, T r) {
+    const T lap = fma_(-two_d, c, s);      // S - 2d*c, rounded once
+    const T c2 = c * c;
+    const T re = fma_(-c2, c, c);          // c - c^3
+    const T t = fma_(alpha, re, c);        // c + alpha*(c - c^3)
+    return fma_(r, lap, t);                // + r*(S - 2d*c)
+}
+
+template <typename T>
+__device__ __forceinline__ T update2d(T c, T xm, T xp, T ym, T yp, T alpha, T r) {
+    const T s = (xm + xp) + (ym + yp);
+    return react_and_diffuse<T>(c, s, T(4), alpha, r);
+}
+
+template <typename T>
+__device__ __forceinline__ T update3d(T c, T xm, T xp, T ym, T yp, T zm, T zp, T alpha, T r) {
+    const T s = ((xm + xp) + (ym + yp)) + (zm + zp);
+    return react_and_diffuse<T>(c, s, T(6), alpha, r);
+}
+
+// ----------------------------------------------------------- launchers ----
+// 2D tiled kernel: each workgroup loads a (LX x LY) tile including a `halo`
+// ring, advances it `ksteps` <= halo steps in LDS (or all steps if the tile is
+// the whole grid), and stores the interior.
+struct Tile2D {
+    int LX, LY, halo, threads;
+};
+template <typename T>
+hipError_t launch_tile2d(const T *src, T *dst, int nx, int ny, T alpha, T r,
+                         const Tile2D &t, int ksteps, hipStream_t stream);
+size_t tile2d_lds_bytes(int LX, int LY, size_t elem);
+
+// 3D z-streaming kernel with K time levels pipelined along z.
+struct Tile3D {
+    int LX, LY, LZ, K, threads;
+};
+template <typename T>
+hipError_t launch_stream3d(const T *src, T *dst, int nx, int ny, int nz, T alpha, T r,
+                           const Tile3D &t, hipStream_t stream);
+size_t stream3d_lds_bytes(const Tile3D &t, size_t elem);
+int stream3d_cells_per_thread(const Tile3D &t);
+
+// Raise a kernel's dynamic-LDS limit when it asks for more than 64 KiB; a
+// runtime that rejects the attribute leaves the launch to report any problem.
+inline void set_lds_limit(const void *kernel, size_t bytes) {
+    if (bytes > 65536 &&
+        hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess)
+        (void)hipGetLastError();
+}
+
+// Device limits, cached per device.
+struct DevInfo {
+    int cus;
+    size_t lds_per_block;
+    int xcds;
+};
+hipError_t device_info(DevInfo *out);
+
+}  // namespace ac

@@ -1,0 +1,101 @@
+"""The C ABI on the CPU: the library loads, exports every declared symbol, and
+rejects bad arguments before making any HIP call (so no GPU is needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2105_09671_amd import _lib as L
+from paper_2105_09671_amd import params
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = []
+    for fn in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if not fn.endswith(".h"):
+            continue
+        text = open(os.path.join(ROOT, "include", fn)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        names += re.findall(r"\b(ac_[a-z0-9_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(L.LIB_PATH):
+        pytest.skip("libac.so not built")
+    return L.lib()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared_functions()
+    assert "ac_step_2d" in names and "ac_step_3d" in names
+    for n in names:
+        assert hasattr(lib, n), "libac.so does not export %s" % n
+
+
+def test_binding_covers_header():
+    assert set(L.SIGNATURES) <= set(_declared_functions())
+
+
+def test_version_and_strings(lib):
+    assert lib.ac_version() >= 100
+    for s in range(6):
+        assert lib.ac_status_string(s)
+    assert lib.ac_status_string(99) == b"unknown status"
+
+
+# fake, 256-aligned device addresses: validation must fail (or succeed as a
+# no-op) without dereferencing them or calling into HIP
+A, B = 0x10000000, 0x20000000
+H, DT = 1.0 / 64, 0.1 / 64 / 64
+EPS = params.eps_m(H, 4)
+
+
+def s2(lib, phi=A, work=B, nx=64, ny=64, h=H, dt=DT, eps=EPS, n=10, dtype=0):
+    return lib.ac_step_2d(phi, work, nx, ny, h, dt, eps, n, dtype, None)
+
+
+def s3(lib, phi=A, work=B, n3=(8, 8, 8), h=H, dt=DT, eps=EPS, n=10, dtype=0):
+    return lib.ac_step_3d(phi, work, *n3, h, dt, eps, n, dtype, None)
+
+
+def test_zero_steps_is_noop(lib):
+    assert s2(lib, n=0) == L.AC_OK
+    assert s3(lib, n=0) == L.AC_OK
+
+
+@pytest.mark.parametrize("kw", [dict(phi=0), dict(work=0), dict(phi=A + 4), dict(work=B + 8),
+                                dict(work=A), dict(work=A + 64 * 64 * 4 - 16), dict(nx=0),
+                                dict(ny=-3), dict(h=0.0), dict(dt=-1.0), dict(eps=float("nan")),
+                                dict(h=float("inf")), dict(n=-1), dict(dtype=7)])
+def test_invalid_arguments_2d(lib, kw):
+    assert s2(lib, **kw) == L.AC_ERR_INVALID_ARG
+    assert lib.ac_last_error()
+
+
+@pytest.mark.parametrize("kw", [dict(n3=(0, 4, 4)), dict(n3=(4, 4, -1)), dict(phi=0),
+                                dict(work=A + 16), dict(eps=0.0), dict(n=-5)])
+def test_invalid_arguments_3d(lib, kw):
+    assert s3(lib, **kw) == L.AC_ERR_INVALID_ARG
+
+
+def test_unstable_time_steps(lib):
+    # r = dt/h^2 = 0.3 > 1/4 in 2D
+    assert s2(lib, dt=0.3 * H * H) == L.AC_ERR_UNSTABLE
+    # r = 0.2 > 1/6 in 3D
+    assert s3(lib, dt=0.2 * H * H) == L.AC_ERR_UNSTABLE
+    # alpha = dt/eps^2 too large: eps of one cell (m ~ 1.4)
+    assert s2(lib, eps=H / 2) == L.AC_ERR_UNSTABLE
+    assert b"alpha" in lib.ac_last_error()
+
+
+def test_error_message_is_thread_local_and_cleared(lib):
+    assert s2(lib, nx=0) == L.AC_ERR_INVALID_ARG
+    assert lib.ac_last_error()
+    assert s2(lib, n=0) == L.AC_OK
+    assert lib.ac_last_error() == b""

@@ -1,0 +1,185 @@
+"""GPU parity: libac (through the C ABI) against the FP64 CPU oracle.
+
+Bars: FP64 rel L_inf <= 1e-12; FP32 rel L_inf <= 1e-5 against the FP64 oracle
+started from the same FP32-rounded initial state.  Temporal-blocking depths
+and tile shapes must agree bitwise with each other (every cell is always
+updated by the same expression from the same neighbour values).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import diagnostics as D
+from paper_2105_09671_amd import inputs, params, workloads
+
+pytestmark = pytest.mark.gpu
+
+TOL = {torch.float64: 1e-12, torch.float32: 1e-5}
+NP = {torch.float64: np.float64, torch.float32: np.float32}
+
+
+@pytest.fixture(scope="module")
+def api():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2105_09671_amd import api as a
+    return a
+
+
+def _run2d(api, phi0, h, dt, eps, n, dtype, tune=None):
+    t = torch.from_numpy(np.ascontiguousarray(phi0, dtype=NP[dtype])).cuda()
+    api.step2d(t, h, dt, eps, n, tune=tune)
+    api.check()
+    return t.cpu().numpy()
+
+
+def _run3d(api, phi0, h, dt, eps, n, dtype, tune=None):
+    t = torch.from_numpy(np.ascontiguousarray(phi0, dtype=NP[dtype])).cuda()
+    api.step3d(t, h, dt, eps, n, tune=tune)
+    api.check()
+    return t.cpu().numpy()
+
+
+def _par(n, m):
+    h = 1.0 / n
+    return h, params.dt_of(h), params.eps_m(h, m)
+
+
+# ------------------------------------------------------------------- 2D ----
+def test_phase64_fp64_resident(api):
+    """64x64 FP64 random start, 500 steps: one LDS-resident launch."""
+    g = workloads.phase64()
+    phi0 = g.initial()
+    got = _run2d(api, phi0, g.h, g.dt, g.eps, 500, torch.float64)
+    ref = oracle.step2d(phi0, g.h, g.dt, g.eps, 500)
+    assert D.rel_linf(got, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_2d_tiled_all_depths(api, dtype):
+    """300x211 grid (ragged against every tile), 37 steps, depths 1..8."""
+    h, dt, eps = _par(256, 4)
+    phi0 = inputs.random_field((211, 300), seed=21).astype(NP[dtype])
+    ref = oracle.step2d(phi0.astype(np.float64), h, dt, eps, 37)
+    outs = {}
+    for k in range(1, 9):
+        outs[k] = _run2d(api, phi0, h, dt, eps, 37, dtype, tune=dict(tb_depth=k, tile_x=-1))
+        assert D.rel_linf(outs[k], ref) <= TOL[dtype], "depth %d" % k
+    for k in range(2, 9):
+        assert np.array_equal(outs[k], outs[1]), "depth %d differs bitwise from depth 1" % k
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_2d_tile_shapes_bitwise(api, dtype):
+    h, dt, eps = _par(128, 5)
+    phi0 = inputs.random_field((150, 170), seed=22).astype(NP[dtype])
+    base = _run2d(api, phi0, h, dt, eps, 20, dtype, tune=dict(tb_depth=1, tile_x=-1))
+    for tx, ty, k in [(64, 64, 4), (128, 32, 3), (256, 16, 2), (96, 40, 8), (64, 17, 8)]:
+        got = _run2d(api, phi0, h, dt, eps, 20, dtype, tune=dict(tb_depth=k, tile_x=tx, tile_y=ty))
+        assert np.array_equal(got, base), (tx, ty, k)
+    res = _run2d(api, phi0, h, dt, eps, 20, dtype)       # LDS-resident path
+    assert np.array_equal(res, base)
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (1, 50), (50, 1), (3, 200), (200, 3), (65, 63),
+                                   (1, 129), (130, 2)])
+@pytest.mark.parametrize("nsteps", [0, 1, 2, 5])
+def test_2d_edge_shapes(api, shape, nsteps):
+    h, dt, eps = _par(64, 4)
+    phi0 = inputs.random_field(shape, seed=23, amp=0.8)
+    ref = oracle.step2d(phi0, h, dt, eps, nsteps)
+    for tune in (None, dict(tb_depth=3, tile_x=-1)):
+        got = _run2d(api, phi0, h, dt, eps, nsteps, torch.float64, tune=tune)
+        assert D.rel_linf(got, ref) <= 1e-12, tune
+
+
+def test_2d_split_equals_single_call(api):
+    h, dt, eps = _par(200, 4)
+    phi0 = inputs.random_field((200, 200), seed=24).astype(np.float32)
+    tune = dict(tb_depth=4, tile_x=-1)
+    once = _run2d(api, phi0, h, dt, eps, 50, torch.float32, tune)
+    a = _run2d(api, phi0, h, dt, eps, 21, torch.float32, tune)
+    both = _run2d(api, a, h, dt, eps, 29, torch.float32, tune)
+    assert np.array_equal(once, both)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_2d_invariants(api, dtype):
+    h, dt, eps = _par(160, 3)            # m = 3: the largest alpha accepted
+    tune = dict(tb_depth=5, tile_x=-1)
+    for v in (1.0, -1.0, 0.0):
+        c = np.full((170, 140), v, dtype=NP[dtype])
+        assert np.array_equal(_run2d(api, c, h, dt, eps, 30, dtype, tune), c)
+    phi0 = inputs.random_field((170, 140), seed=25, amp=1.0).astype(NP[dtype])
+    out = _run2d(api, phi0, h, dt, eps, 60, dtype, tune)
+    assert np.max(np.abs(out)) <= 1.0 + 4 * np.finfo(NP[dtype]).eps
+    assert np.array_equal(_run2d(api, -phi0, h, dt, eps, 60, dtype, tune), -out)
+    assert np.array_equal(_run2d(api, phi0[:, ::-1], h, dt, eps, 60, dtype, tune), out[:, ::-1])
+    assert np.array_equal(_run2d(api, phi0[::-1], h, dt, eps, 60, dtype, tune), out[::-1])
+    assert np.array_equal(_run2d(api, phi0.T, h, dt, eps, 60, dtype, tune), out.T)
+
+
+def test_2d_energy_decreases(api):
+    h, dt, eps = _par(256, 4)
+    phi = inputs.random_field((256, 256), seed=26)
+    E = D.energy(phi, h, eps)
+    t = torch.from_numpy(phi).cuda()
+    for _ in range(20):
+        api.step2d(t, h, dt, eps, 25)
+        E2 = D.energy(t.cpu().numpy(), h, eps)
+        assert E2 <= E * (1 + 1e-13)
+        E = E2
+
+
+# ------------------------------------------------------------------- 3D ----
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_3d_all_depths(api, dtype):
+    """37x29x23 grid, z segments of 8 planes, 13 steps, depths 1..8."""
+    h, dt, eps = _par(64, 4)
+    phi0 = inputs.random_field((23, 29, 37), seed=31).astype(NP[dtype])
+    ref = oracle.step3d(phi0.astype(np.float64), h, dt, eps, 13)
+    outs = {}
+    for k in range(1, 9):
+        lx = 2 * k + 16
+        outs[k] = _run3d(api, phi0, h, dt, eps, 13, dtype,
+                         tune=dict(tb_depth=k, tile_x=lx, tile_y=2 * k + 9, tile_z=8))
+        assert D.rel_linf(outs[k], ref) <= TOL[dtype], "depth %d" % k
+    for k in range(2, 9):
+        assert np.array_equal(outs[k], outs[1]), "depth %d differs bitwise" % k
+    default = _run3d(api, phi0, h, dt, eps, 13, dtype)
+    assert np.array_equal(default, outs[1])
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (1, 1, 9), (9, 1, 1), (1, 7, 1), (2, 3, 4),
+                                   (5, 70, 3), (40, 2, 66)])
+@pytest.mark.parametrize("nsteps", [1, 4])
+def test_3d_edge_shapes(api, shape, nsteps):
+    h, dt, eps = _par(32, 4)
+    phi0 = inputs.random_field(shape, seed=32, amp=0.8)
+    ref = oracle.step3d(phi0, h, dt, eps, nsteps)
+    for tune in (None, dict(tb_depth=2, tile_x=12, tile_y=12, tile_z=2)):
+        got = _run3d(api, phi0, h, dt, eps, nsteps, torch.float64, tune)
+        assert D.rel_linf(got, ref) <= 1e-12, tune
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_3d_invariants(api, dtype):
+    h, dt, eps = _par(48, 3)
+    tune = dict(tb_depth=3, tile_x=24, tile_y=20, tile_z=16)
+    for v in (1.0, -1.0, 0.0):
+        c = np.full((20, 30, 40), v, dtype=NP[dtype])
+        assert np.array_equal(_run3d(api, c, h, dt, eps, 9, dtype, tune), c)
+    phi0 = inputs.random_field((20, 30, 40), seed=33, amp=1.0).astype(NP[dtype])
+    out = _run3d(api, phi0, h, dt, eps, 12, dtype, tune)
+    assert np.max(np.abs(out)) <= 1.0 + 4 * np.finfo(NP[dtype]).eps
+    assert np.array_equal(_run3d(api, -phi0, h, dt, eps, 12, dtype, tune), -out)
+    for ax in range(3):
+        f = [slice(None)] * 3
+        f[ax] = slice(None, None, -1)
+        f = tuple(f)
+        assert np.array_equal(_run3d(api, phi0[f], h, dt, eps, 12, dtype, tune), out[f])
+
+
+def test_api_rejects_cpu_tensor(api):
+    with pytest.raises(TypeError):
+        api.step2d(torch.zeros(4, 4), 0.1, 0.001, 0.1, 1)
