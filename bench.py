@@ -1,0 +1,254 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the Allen-Cahn stepper on one MI355X.
+
+One bench step is one full solve of the shrinking-circle workload: a 2048x2048
+FP32 grid, h = 1/2048, dt = 0.1 h^2, eps = eps_4, phi0 = tanh((0.25 - r)/(sqrt2 eps)),
+20000 explicit steps (8.39e10 grid-point updates).  The state lives in HBM
+before the timed region starts; the timed region is K back-to-back solves.
+
+Printed as one JSON line on stdout:
+  value     grid-point updates per second, in GLUPS
+  roofline  the dominant kernel (the tiled 2D stencil) against the 8 TB/s HBM
+            peak, counting the algorithmic 2*sizeof(T) bytes per update; with
+            temporal blocking one launch advances tb_depth steps per HBM pass,
+            so the fraction can exceed 1 ("effective" roofline).  `traffic` is
+            the measured HBM bytes per launch from rocprofv3 counters when a
+            summary for the current kernel source is stored under profiles/.
+  cpu_baseline  the FP64 CPU oracle timed on this host's cores on a bounded
+            sample of the same workload.
+  extra     the other workloads: the FP64 circle, the 3D 256^3 FP32 grid at
+            every temporal-blocking depth, the 3D sphere radius check and the
+            64x64 FP64 phase-separation grid.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+NSTEPS = 20000
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_tile2d_circle2048_fp32.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2105_09671_amd", "csrc", "stencil2d.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def src_hash(path: str) -> str:
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def timed(fn, reps: int):
+    """Median seconds of reps calls of fn on the current stream (HIP events)."""
+    import torch
+    ts = []
+    for _ in range(reps):
+        s = torch.cuda.Event(enable_timing=True)
+        e = torch.cuda.Event(enable_timing=True)
+        s.record()
+        fn()
+        e.record()
+        torch.cuda.synchronize()
+        ts.append(s.elapsed_time(e) / 1e3)
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def measured_traffic():
+    """HBM bytes per launch from stored rocprofv3 counters, if they were taken on
+    the current kernel source; else None."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as f:
+        t = json.load(f)
+    if t.get("src_sha256") != src_hash(KERNEL_SRC):
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(phi0, g, budget_s: float) -> dict:
+    """The FP64 oracle on this host: all available cores, then one core."""
+    import oracle
+    threads = oracle.cpus_available()
+    cells = g.nx * g.ny
+    t0 = time.perf_counter()
+    oracle.step2d(phi0, g.h, g.dt, g.eps, 2, threads)
+    per = (time.perf_counter() - t0) / 2
+    steps = int(max(2, min(NSTEPS, budget_s / max(per, 1e-9))))
+    t0 = time.perf_counter()
+    oracle.step2d(phi0, g.h, g.dt, g.eps, steps, threads)
+    el = time.perf_counter() - t0
+    v_all = cells * steps / el / 1e9
+    t0 = time.perf_counter()
+    s1 = max(1, steps // max(1, threads) // 2)
+    oracle.step2d(phi0, g.h, g.dt, g.eps, s1, 1)
+    el1 = time.perf_counter() - t0
+    return {"value": round(v_all, 4), "unit": "GLUPS", "cores": threads, "kind": "oracle",
+            "sample": "2048x2048 circle, FP64 plain loops, first %d of the %d steps on %d threads "
+                      "(%.1f s); one thread: %d steps, %.4f GLUPS"
+                      % (steps, NSTEPS, threads, el, s1, cells * s1 / el1 / 1e9)}
+
+
+def extras(api, torch, workloads, params) -> dict:
+    out = {}
+    # FP64 circle, same workload
+    g = workloads.circle2048()
+    phi = torch.from_numpy(g.initial()).cuda()
+    api.step2d(phi, g.h, g.dt, g.eps, 2000)
+    t = timed(lambda: api.step2d(phi, g.h, g.dt, g.eps, NSTEPS), 1)
+    glups = g.nx * g.ny * NSTEPS / t / 1e9
+    out["circle2048_fp64"] = {"GLUPS": round(glups, 2), "f_eff": round(glups * 16 / HBM_PEAK_GBS, 3),
+                              "ms": round(t * 1e3, 2), "plan": api.plan2d(g.nx, g.ny, NSTEPS, torch.float64)}
+    log("extra circle2048_fp64", out["circle2048_fp64"])
+    del phi
+    # 3D 256^3 FP32, 2000 steps, every temporal-blocking depth
+    g3 = workloads.sep256c()
+    p3 = torch.from_numpy(g3.initial()).float().cuda()
+    n3 = g3.nx * g3.ny * g3.nz
+    depth = {}
+    for k in range(1, 9):
+        tune = {"tb_depth": k, "tile_x": 32 if k <= 4 else 64, "tile_y": 32, "tile_z": 32}
+        try:
+            t = timed(lambda: api.step3d(p3, g3.h, g3.dt, g3.eps, 2000, tune=tune), 1)
+        except Exception as ex:   # an infeasible tile for this depth
+            depth[k] = {"error": str(ex)}
+            continue
+        gl = n3 * 2000 / t / 1e9
+        depth[k] = {"GLUPS": round(gl, 2), "f_eff": round(gl * 8 / HBM_PEAK_GBS, 3),
+                    "tune": tune}
+    t = timed(lambda: api.step3d(p3, g3.h, g3.dt, g3.eps, 2000), 1)
+    gl = n3 * 2000 / t / 1e9
+    out["sep256c_fp32"] = {"GLUPS": round(gl, 2), "f_eff": round(gl * 8 / HBM_PEAK_GBS, 3),
+                           "ms": round(t * 1e3, 2), "plan": api.plan3d(256, 256, 256, 2000),
+                           "by_depth": depth}
+    log("extra sep256c_fp32", {k: v for k, v in out["sep256c_fp32"].items() if k != "by_depth"})
+    del p3
+    # sphere: R^2 = R0^2 - 4t
+    gs = workloads.sphere256()
+    ps = torch.from_numpy(gs.initial()).float().cuda()
+    api.step3d(ps, gs.h, gs.dt, gs.eps, 2000)
+    V = float(torch.sum(0.5 * (1.0 + ps.double())).item()) * gs.h ** 3
+    R = (V / (4.0 / 3.0 * math.pi)) ** (1.0 / 3.0)
+    law = params.radius_law(0.3, 2000 * gs.dt, 3)
+    out["sphere256_fp32"] = {"R_T": round(R, 6), "R_law": round(law, 6),
+                             "err_over_h": round(abs(R - law) / gs.h, 3)}
+    del ps
+    # 64x64 FP64 phase separation, 500 steps, one LDS-resident launch
+    g1 = workloads.phase64()
+    p1 = torch.from_numpy(g1.initial()).cuda()
+    t = timed(lambda: api.step2d(p1, g1.h, g1.dt, g1.eps, 500), 5)
+    out["phase64_fp64"] = {"GLUPS": round(64 * 64 * 500 / t / 1e9, 3), "ms": round(t * 1e3, 3),
+                           "plan": api.plan2d(64, 64, 500, torch.float64)}
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3, help="timed solves of the workload")
+    ap.add_argument("--warmup", type=int, default=1, help="untimed solves before timing")
+    ap.add_argument("--no-extra", action="store_true", help="only the headline workload")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-budget", type=float, default=10.0, help="seconds of oracle work")
+    ap.add_argument("--copy-ref", action="store_true",
+                    help="also run a 256 MiB device copy (counter scale reference)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this stepper runs on one GPU only; --gpus %d (WORLD_SIZE %d) is not "
+              "supported" % (args.gpus, world), file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2105_09671_amd import api, params, workloads
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    g = workloads.circle2048()
+    phi0 = g.initial()
+    phi_init = torch.from_numpy(phi0.astype("float32")).cuda()
+    phi = phi_init.clone()
+    api.work_like(phi)
+    plan = api.plan2d(g.nx, g.ny, NSTEPS, torch.float32)
+    log("plan", plan)
+
+    if args.copy_ref:
+        a = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    for i in range(args.warmup):
+        api.step2d(phi, g.h, g.dt, g.eps, NSTEPS)
+        torch.cuda.synchronize()
+        log("warmup %d done" % (i + 1))
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(args.steps):
+        api.step2d(phi, g.h, g.dt, g.eps, NSTEPS)
+    end.record()
+    torch.cuda.synchronize()
+    sec = start.elapsed_time(end) / 1e3
+    ms_per_step = sec * 1e3 / max(args.steps, 1)
+    cells = g.nx * g.ny
+    value = cells * NSTEPS * args.steps / sec / 1e9
+    log("timed %d solves: %.2f ms each, %.1f GLUPS" % (args.steps, ms_per_step, value))
+
+    # roofline of the dominant kernel: algorithmic bytes per launch / mean launch time
+    launches = plan["launches"] * args.steps
+    avg_launch = sec / launches
+    alg_bytes = 2 * 4 * cells * NSTEPS / plan["launches"]
+    achieved = alg_bytes / avg_launch / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
+            "kernel": "tile2d_kernel<float,%d>" % plan["tile_x"],
+            "algorithmic_bytes_per_launch": int(alg_bytes),
+            "avg_launch_us": round(avg_launch * 1e6, 3), "launches_timed": launches}
+
+    # correctness check of the timed workload: one fresh solve, radius vs the law
+    phi.copy_(phi_init)
+    api.step2d(phi, g.h, g.dt, g.eps, NSTEPS)
+    V = float(torch.sum(0.5 * (1.0 + phi.double())).item()) * g.h ** 2
+    R = math.sqrt(V / math.pi)
+    law = params.radius_law(0.25, NSTEPS * g.dt, 2)
+    check = {"R_T": round(R, 6), "R_law": round(law, 6), "err_over_h": round(abs(R - law) / g.h, 3)}
+    log("radius check", check)
+
+    extra = {} if args.no_extra else extras(api, torch, workloads, params)
+    cpu = None
+    if not args.no_cpu:
+        log("cpu baseline ...")
+        cpu = cpu_baseline(phi0, g, args.cpu_budget)
+        log("cpu baseline", cpu)
+
+    line = {
+        "metric": "grid-point updates/s (GLUPS), % HBM roofline", "value": round(value, 2),
+        "unit": "GLUPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "circle2048: 2D 2048x2048, h=1/2048, dt=0.1h^2, eps_4, "
+                               "circle R0=0.25, 20000 explicit steps per solve",
+                   "nx": g.nx, "ny": g.ny, "nsteps": NSTEPS, "plan": plan},
+        "roofline": roof, "cpu_baseline": cpu, "radius_check": check, "extra": extra,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

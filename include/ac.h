@@ -93,6 +93,33 @@ ac_status ac_step_3d_tuned(void *phi, void *work, int32_t nx, int32_t ny, int32_
                            double h, double dt, double eps, int64_t nsteps,
                            int32_t dtype, const ac_tune *tune, void *stream);
 
+/* Kernels a plan can use. */
+enum {
+    AC_KERNEL_2D_RESIDENT = 0, /* whole grid in one workgroup's LDS, all steps in one launch */
+    AC_KERNEL_2D_TILED = 1,    /* LDS tiles, tb_depth steps per launch */
+    AC_KERNEL_3D_STREAM = 2    /* z-streamed tiles, tb_depth levels per launch */
+};
+
+/* What a stepping call with the same arguments launches (filled by ac_plan_*). */
+typedef struct {
+    int32_t kernel;     /* AC_KERNEL_* */
+    int32_t tb_depth;   /* steps fused per launch (0 for the resident kernel) */
+    int32_t tile_x, tile_y, tile_z;
+    int32_t threads;    /* workgroup size */
+    int64_t launches;   /* kernel launches for nsteps */
+    int32_t copy_back;  /* 1 if the result is copied from work into phi at the end */
+    int64_t lds_bytes;  /* dynamic LDS per workgroup */
+} ac_plan;
+
+/* Report the plan ac_step_2d_tuned / ac_step_3d_tuned would execute for these
+ * sizes on the current device.  Queries device limits (a HIP call) but
+ * launches nothing.  Errors as the stepping calls (AC_ERR_UNSUPPORTED for an
+ * impossible tune). */
+ac_status ac_plan_2d(int32_t nx, int32_t ny, int64_t nsteps, int32_t dtype,
+                     const ac_tune *tune, ac_plan *out);
+ac_status ac_plan_3d(int32_t nx, int32_t ny, int32_t nz, int64_t nsteps, int32_t dtype,
+                     const ac_tune *tune, ac_plan *out);
+
 /* Synchronise `stream` and report any pending HIP error as AC_ERR_HIP. */
 ac_status ac_check(void *stream);
 

@@ -26,6 +26,20 @@ class AcTune(ctypes.Structure):
                 ("tile_y", ctypes.c_int32), ("tile_z", ctypes.c_int32)]
 
 
+class AcPlan(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_int32), ("tb_depth", ctypes.c_int32),
+                ("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32),
+                ("tile_z", ctypes.c_int32), ("threads", ctypes.c_int32),
+                ("launches", ctypes.c_int64), ("copy_back", ctypes.c_int32),
+                ("lds_bytes", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+KERNEL_NAMES = {0: "tile2d_kernel (resident)", 1: "tile2d_kernel", 2: "stream3d_kernel"}
+
+
 class AcError(RuntimeError):
     def __init__(self, status: int, fn: str, msg: str):
         super().__init__("%s failed: status %d (%s)" % (fn, status, msg))
@@ -43,6 +57,9 @@ SIGNATURES = {
     "ac_step_3d": ([_vp, _vp, _i32, _i32, _i32, _dbl, _dbl, _dbl, _i64, _i32, _vp], _i32),
     "ac_step_3d_tuned": ([_vp, _vp, _i32, _i32, _i32, _dbl, _dbl, _dbl, _i64, _i32,
                           ctypes.POINTER(AcTune), _vp], _i32),
+    "ac_plan_2d": ([_i32, _i32, _i64, _i32, ctypes.POINTER(AcTune), ctypes.POINTER(AcPlan)], _i32),
+    "ac_plan_3d": ([_i32, _i32, _i32, _i64, _i32, ctypes.POINTER(AcTune),
+                    ctypes.POINTER(AcPlan)], _i32),
     "ac_check": ([_vp], _i32),
     "ac_status_string": ([_i32], ctypes.c_char_p),
     "ac_last_error": ([], ctypes.c_char_p),

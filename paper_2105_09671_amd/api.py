@@ -85,3 +85,19 @@ def step3d(phi: torch.Tensor, h: float, dt: float, eps: float, nsteps: int,
 def check(stream=None) -> None:
     """Synchronise the stream and raise on a pending HIP error."""
     L.check(L.lib().ac_check(_stream(stream)), "ac_check")
+
+
+def plan2d(nx: int, ny: int, nsteps: int, dtype=torch.float32, tune=None) -> dict:
+    """The launch plan ac_step_2d would use (kernel, depth, tile, launches)."""
+    p = L.AcPlan()
+    code = L.AC_F64 if dtype == torch.float64 else L.AC_F32
+    L.check(L.lib().ac_plan_2d(nx, ny, int(nsteps), code, _tune(tune), ctypes.byref(p)), "ac_plan_2d")
+    return p.as_dict()
+
+
+def plan3d(nx: int, ny: int, nz: int, nsteps: int, dtype=torch.float32, tune=None) -> dict:
+    p = L.AcPlan()
+    code = L.AC_F64 if dtype == torch.float64 else L.AC_F32
+    L.check(L.lib().ac_plan_3d(nx, ny, nz, int(nsteps), code, _tune(tune), ctypes.byref(p)),
+            "ac_plan_3d")
+    return p.as_dict()

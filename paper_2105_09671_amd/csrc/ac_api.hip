@@ -82,28 +82,28 @@ Chunks plan_chunks(int64_t nsteps, int64_t k) {
     return c;
 }
 
-template <typename T>
-ac_status run2d(T *phi, T *work, int nx, int ny, double alpha_d, double r_d, int64_t nsteps,
-                const ac_tune *tune, hipStream_t stream) {
-    ac::DevInfo dev;
-    hipError_t e = ac::device_info(&dev);
-    if (e != hipSuccess) return hip_fail(e, "device query");
-    const T alpha = (T)alpha_d, r = (T)r_d;
+// ------------------------------------------------------------ planning ----
+// A plan fixes the kernel, its launch shape and the launch sequence of one
+// call.  Built on the host from the device limits; executing it makes no other
+// decision, so ac_plan_* reports exactly what ac_step_* will launch.
+ac_status make_plan2d(int nx, int ny, int64_t nsteps, size_t elem, const ac_tune *tune,
+                      const ac::DevInfo &dev, ac_plan *p) {
+    std::memset(p, 0, sizeof *p);
     const bool force_tiled = tune && (tune->tile_x < 0 || tune->tile_y < 0);
-    const size_t resident_lds = ac::tile2d_lds_bytes(nx, ny, sizeof(T));
-    if (!force_tiled && resident_lds <= dev.lds_per_block) {
-        // whole grid in one workgroup: all steps in LDS, in place in phi
-        ac::Tile2D t{nx, ny, 0, 1024};
-        for (int64_t done = 0; done < nsteps;) {
-            const int k = (int)std::min<int64_t>(nsteps - done, INT_MAX);
-            e = ac::launch_tile2d<T>(phi, phi, nx, ny, alpha, r, t, k, stream);
-            if (e != hipSuccess) return hip_fail(e, "resident 2D launch");
-            done += k;
-        }
+    if (!force_tiled && ac::tile2d_lds_bytes(nx, ny, elem) <= dev.lds_per_block) {
+        p->kernel = AC_KERNEL_2D_RESIDENT;
+        p->tb_depth = 0;
+        p->tile_x = nx;
+        p->tile_y = ny;
+        p->threads = 1024;
+        p->launches = nsteps > 0 ? (nsteps + INT_MAX - 1) / INT_MAX : 0;
+        p->lds_bytes = (int64_t)ac::tile2d_lds_bytes(nx, ny, elem);
         return AC_OK;
     }
-    const bool f64 = sizeof(T) == 8;
-    int K = 4, LX = 128, LY = f64 ? 32 : 64, threads = 256;
+    const bool f64 = elem == 8;
+    // defaults measured on MI355X for large grids (2048^2): depth 8 / 64x64
+    // tiles in FP32, depth 4 / 64x32 in FP64
+    int K = f64 ? 4 : 8, LX = 64, LY = f64 ? 32 : 64;
     if (tune) {
         if (tune->tb_depth) K = tune->tb_depth;
         if (tune->tile_x > 0) LX = tune->tile_x;
@@ -112,11 +112,79 @@ ac_status run2d(T *phi, T *work, int nx, int ny, double alpha_d, double r_d, int
     if (K < 1 || K > 8) return fail(AC_ERR_UNSUPPORTED, "tb_depth must be 1..8, got %d", K);
     if (LX < 2 * K + 1 || LY < 2 * K + 1 || LX > 4096 || LY > 4096)
         return fail(AC_ERR_UNSUPPORTED, "tile %dx%d too small/large for depth %d", LX, LY, K);
-    if (ac::tile2d_lds_bytes(LX, LY, sizeof(T)) > dev.lds_per_block)
-        return fail(AC_ERR_UNSUPPORTED, "tile %dx%d needs %zu B LDS > %zu", LX, LY,
-                    ac::tile2d_lds_bytes(LX, LY, sizeof(T)), dev.lds_per_block);
-    ac::Tile2D t{LX, LY, K, threads};
+    const size_t lds = ac::tile2d_lds_bytes(LX, LY, elem);
+    if (lds > dev.lds_per_block)
+        return fail(AC_ERR_UNSUPPORTED, "tile %dx%d needs %zu B LDS > %zu", LX, LY, lds,
+                    dev.lds_per_block);
+    const int64_t gy = (ny + (LY - 2 * K) - 1) / (LY - 2 * K);
+    if (gy > 65535) return fail(AC_ERR_UNSUPPORTED, "grid of %lld tile rows exceeds 65535", (long long)gy);
     const Chunks c = plan_chunks(nsteps, K);
+    p->kernel = AC_KERNEL_2D_TILED;
+    p->tb_depth = K;
+    p->tile_x = LX;
+    p->tile_y = LY;
+    p->threads = 256;
+    p->launches = nsteps > 0 ? c.n : 0;
+    p->copy_back = nsteps > 0 && c.copy_back;
+    p->lds_bytes = (int64_t)lds;
+    return AC_OK;
+}
+
+ac_status make_plan3d(int nx, int ny, int nz, int64_t nsteps, size_t elem, const ac_tune *tune,
+                      const ac::DevInfo &dev, ac_plan *p) {
+    std::memset(p, 0, sizeof *p);
+    const bool f64 = elem == 8;
+    // defaults measured on MI355X at 256^3: depth 4 / 32x32x32 in FP32,
+    // depth 3 / 32x16x32 in FP64
+    int K = f64 ? 3 : 4, LX = 32, LY = f64 ? 16 : 32, LZ = 32, threads = f64 ? 256 : 512;
+    if (tune) {
+        if (tune->tb_depth) K = tune->tb_depth;
+        if (tune->tile_x > 0) LX = tune->tile_x;
+        if (tune->tile_y > 0) LY = tune->tile_y;
+        if (tune->tile_z > 0) LZ = tune->tile_z;
+    }
+    if (K < 1 || K > 8) return fail(AC_ERR_UNSUPPORTED, "tb_depth must be 1..8, got %d", K);
+    if (LX < 2 * K + 1 || LY < 2 * K + 1 || LZ < 1)
+        return fail(AC_ERR_UNSUPPORTED, "tile %dx%dx%d too small for depth %d", LX, LY, LZ, K);
+    ac::Tile3D t{LX, LY, LZ, K, threads};
+    if (ac::stream3d_cells_per_thread(t) > 4)
+        return fail(AC_ERR_UNSUPPORTED, "tile %dx%d has more than 4 cells per thread", LX, LY);
+    const size_t lds = ac::stream3d_lds_bytes(t, elem);
+    if (lds > dev.lds_per_block)
+        return fail(AC_ERR_UNSUPPORTED, "3D tile needs %zu B LDS > %zu", lds, dev.lds_per_block);
+    const int64_t gz = (nz + LZ - 1) / LZ;
+    if (gz > 65535) return fail(AC_ERR_UNSUPPORTED, "%lld z segments exceed 65535", (long long)gz);
+    const Chunks c = plan_chunks(nsteps, K);
+    p->kernel = AC_KERNEL_3D_STREAM;
+    p->tb_depth = K;
+    p->tile_x = LX;
+    p->tile_y = LY;
+    p->tile_z = LZ;
+    p->threads = threads;
+    p->launches = nsteps > 0 ? c.n : 0;
+    p->copy_back = nsteps > 0 && c.copy_back;
+    p->lds_bytes = (int64_t)lds;
+    return AC_OK;
+}
+
+template <typename T>
+ac_status run2d(T *phi, T *work, int nx, int ny, double alpha_d, double r_d, int64_t nsteps,
+                const ac_plan &p, hipStream_t stream) {
+    const T alpha = (T)alpha_d, r = (T)r_d;
+    hipError_t e;
+    if (p.kernel == AC_KERNEL_2D_RESIDENT) {
+        // whole grid in one workgroup: all steps in LDS, in place in phi
+        ac::Tile2D t{nx, ny, 0, p.threads};
+        for (int64_t done = 0; done < nsteps;) {
+            const int k = (int)std::min<int64_t>(nsteps - done, INT_MAX);
+            e = ac::launch_tile2d<T>(phi, phi, nx, ny, alpha, r, t, k, stream);
+            if (e != hipSuccess) return hip_fail(e, "resident 2D launch");
+            done += k;
+        }
+        return AC_OK;
+    }
+    ac::Tile2D t{p.tile_x, p.tile_y, p.tb_depth, p.threads};
+    const Chunks c = plan_chunks(nsteps, p.tb_depth);
     T *src = phi, *dst = work;
     for (int64_t i = 0; i < c.n; ++i) {
         const int k = (int)(c.base + (i < c.rem ? 1 : 0));
@@ -133,30 +201,12 @@ ac_status run2d(T *phi, T *work, int nx, int ny, double alpha_d, double r_d, int
 
 template <typename T>
 ac_status run3d(T *phi, T *work, int nx, int ny, int nz, double alpha_d, double r_d,
-                int64_t nsteps, const ac_tune *tune, hipStream_t stream) {
-    ac::DevInfo dev;
-    hipError_t e = ac::device_info(&dev);
-    if (e != hipSuccess) return hip_fail(e, "device query");
+                int64_t nsteps, const ac_plan &p, hipStream_t stream) {
     const T alpha = (T)alpha_d, r = (T)r_d;
-    const bool f64 = sizeof(T) == 8;
-    int K = 2, LX = 64, LY = f64 ? 16 : 32, LZ = 64, threads = f64 ? 256 : 512;
-    if (tune) {
-        if (tune->tb_depth) K = tune->tb_depth;
-        if (tune->tile_x > 0) LX = tune->tile_x;
-        if (tune->tile_y > 0) LY = tune->tile_y;
-        if (tune->tile_z > 0) LZ = tune->tile_z;
-    }
-    if (K < 1 || K > 8) return fail(AC_ERR_UNSUPPORTED, "tb_depth must be 1..8, got %d", K);
-    if (LX < 2 * K + 1 || LY < 2 * K + 1 || LZ < 1)
-        return fail(AC_ERR_UNSUPPORTED, "tile %dx%dx%d too small for depth %d", LX, LY, LZ, K);
-    ac::Tile3D t{LX, LY, LZ, K, threads};
-    if (ac::stream3d_cells_per_thread(t) > 4)
-        return fail(AC_ERR_UNSUPPORTED, "tile %dx%d has more than 4 cells per thread", LX, LY);
-    if (ac::stream3d_lds_bytes(t, sizeof(T)) > dev.lds_per_block)
-        return fail(AC_ERR_UNSUPPORTED, "3D tile needs %zu B LDS > %zu",
-                    ac::stream3d_lds_bytes(t, sizeof(T)), dev.lds_per_block);
-    const Chunks c = plan_chunks(nsteps, K);
+    ac::Tile3D t{p.tile_x, p.tile_y, p.tile_z, p.tb_depth, p.threads};
+    const Chunks c = plan_chunks(nsteps, p.tb_depth);
     T *src = phi, *dst = work;
+    hipError_t e;
     for (int64_t i = 0; i < c.n; ++i) {
         t.K = (int)(c.base + (i < c.rem ? 1 : 0));
         e = ac::launch_stream3d<T>(src, dst, nx, ny, nz, alpha, r, t, stream);
@@ -211,10 +261,15 @@ ac_status ac_step_2d_tuned(void *phi, void *work, int32_t nx, int32_t ny, double
     double alpha, r;
     ac_status s = validate(phi, work, (int64_t)nx * ny, 2, h, dt, eps, nsteps, dtype, &alpha, &r);
     if (s != AC_OK || nsteps == 0) return s;
+    ac::DevInfo dev;
+    hipError_t e = ac::device_info(&dev);
+    if (e != hipSuccess) return hip_fail(e, "device query");
+    ac_plan p;
+    if ((s = make_plan2d(nx, ny, nsteps, elem_size(dtype), tune, dev, &p)) != AC_OK) return s;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     if (dtype == AC_F64)
-        return run2d<double>((double *)phi, (double *)work, nx, ny, alpha, r, nsteps, tune, st);
-    return run2d<float>((float *)phi, (float *)work, nx, ny, alpha, r, nsteps, tune, st);
+        return run2d<double>((double *)phi, (double *)work, nx, ny, alpha, r, nsteps, p, st);
+    return run2d<float>((float *)phi, (float *)work, nx, ny, alpha, r, nsteps, p, st);
 }
 
 ac_status ac_step_2d(void *phi, void *work, int32_t nx, int32_t ny, double h, double dt,
@@ -231,15 +286,44 @@ ac_status ac_step_3d_tuned(void *phi, void *work, int32_t nx, int32_t ny, int32_
     double alpha, r;
     ac_status s = validate(phi, work, (int64_t)nx * ny * nz, 3, h, dt, eps, nsteps, dtype, &alpha, &r);
     if (s != AC_OK || nsteps == 0) return s;
+    ac::DevInfo dev;
+    hipError_t e = ac::device_info(&dev);
+    if (e != hipSuccess) return hip_fail(e, "device query");
+    ac_plan p;
+    if ((s = make_plan3d(nx, ny, nz, nsteps, elem_size(dtype), tune, dev, &p)) != AC_OK) return s;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     if (dtype == AC_F64)
-        return run3d<double>((double *)phi, (double *)work, nx, ny, nz, alpha, r, nsteps, tune, st);
-    return run3d<float>((float *)phi, (float *)work, nx, ny, nz, alpha, r, nsteps, tune, st);
+        return run3d<double>((double *)phi, (double *)work, nx, ny, nz, alpha, r, nsteps, p, st);
+    return run3d<float>((float *)phi, (float *)work, nx, ny, nz, alpha, r, nsteps, p, st);
 }
 
 ac_status ac_step_3d(void *phi, void *work, int32_t nx, int32_t ny, int32_t nz, double h,
                      double dt, double eps, int64_t nsteps, int32_t dtype, void *stream) {
     return ac_step_3d_tuned(phi, work, nx, ny, nz, h, dt, eps, nsteps, dtype, nullptr, stream);
+}
+
+ac_status ac_plan_2d(int32_t nx, int32_t ny, int64_t nsteps, int32_t dtype, const ac_tune *tune,
+                     ac_plan *out) {
+    g_err.clear();
+    if (!out) return fail(AC_ERR_INVALID_ARG, "out must be non-null");
+    if (nx < 1 || ny < 1 || nsteps < 0 || (dtype != AC_F32 && dtype != AC_F64))
+        return fail(AC_ERR_INVALID_ARG, "bad grid, step count or dtype");
+    ac::DevInfo dev;
+    hipError_t e = ac::device_info(&dev);
+    if (e != hipSuccess) return hip_fail(e, "device query");
+    return make_plan2d(nx, ny, nsteps, elem_size(dtype), tune, dev, out);
+}
+
+ac_status ac_plan_3d(int32_t nx, int32_t ny, int32_t nz, int64_t nsteps, int32_t dtype,
+                     const ac_tune *tune, ac_plan *out) {
+    g_err.clear();
+    if (!out) return fail(AC_ERR_INVALID_ARG, "out must be non-null");
+    if (nx < 1 || ny < 1 || nz < 1 || nsteps < 0 || (dtype != AC_F32 && dtype != AC_F64))
+        return fail(AC_ERR_INVALID_ARG, "bad grid, step count or dtype");
+    ac::DevInfo dev;
+    hipError_t e = ac::device_info(&dev);
+    if (e != hipSuccess) return hip_fail(e, "device query");
+    return make_plan3d(nx, ny, nz, nsteps, elem_size(dtype), tune, dev, out);
 }
 
 ac_status ac_check(void *stream) {

@@ -25,6 +25,8 @@
 
 namespace ac {
 
+constexpr int PD = 4;   // level-0 planes prefetched ahead of use
+
 template <typename T, int K, int CPT>
 __global__ void __launch_bounds__(512)
 stream3d_kernel(const T *__restrict__ src, T *__restrict__ dst, int nx, int ny, int nz,
@@ -66,7 +68,7 @@ stream3d_kernel(const T *__restrict__ src, T *__restrict__ dst, int nx, int ny, 
         gxy[j] = in ? (long)gy * nx + gx : 0;
     }
 
-    T cur[K][CPT], prv[K][CPT], nxt[CPT];
+    T cur[K][CPT], prv[K][CPT], pf[PD][CPT];   // pf: level-0 planes t .. t+PD-1 in flight
 #pragma unroll
     for (int s = 0; s < K; ++s)
 #pragma unroll
@@ -77,8 +79,10 @@ stream3d_kernel(const T *__restrict__ src, T *__restrict__ dst, int nx, int ny, 
     const int t1 = oz1 - 1 + K;           // last iteration: level K emits plane oz1-1
 
 #pragma unroll
-    for (int j = 0; j < CPT; ++j)
-        nxt[j] = (ld[j] && t0 < nz) ? src[(long)t0 * pstride + gxy[j]] : T(0);
+    for (int d = 0; d < PD; ++d)
+#pragma unroll
+        for (int j = 0; j < CPT; ++j)
+            pf[d][j] = (ld[j] && t0 + d < nz) ? src[(long)(t0 + d) * pstride + gxy[j]] : T(0);
 
     for (int t = t0; t <= t1; ++t) {
         T *set = slots + (size_t)(t & 1) * K * plane_l;
@@ -91,11 +95,15 @@ stream3d_kernel(const T *__restrict__ src, T *__restrict__ dst, int nx, int ny, 
 
         T nw[CPT];
 #pragma unroll
-        for (int j = 0; j < CPT; ++j) nw[j] = nxt[j];
-        // prefetch level 0 of the next iteration
+        for (int j = 0; j < CPT; ++j) nw[j] = pf[0][j];
+        // keep PD planes of level 0 in flight
+#pragma unroll
+        for (int d = 0; d + 1 < PD; ++d)
+#pragma unroll
+            for (int j = 0; j < CPT; ++j) pf[d][j] = pf[d + 1][j];
 #pragma unroll
         for (int j = 0; j < CPT; ++j)
-            nxt[j] = (ld[j] && t + 1 < nz) ? src[(long)(t + 1) * pstride + gxy[j]] : T(0);
+            pf[PD - 1][j] = (ld[j] && t + PD < nz) ? src[(long)(t + PD) * pstride + gxy[j]] : T(0);
         __syncthreads();
 
 #pragma unroll
