@@ -143,6 +143,18 @@ def extras(api, torch, workloads, params) -> dict:
     out["sphere256_fp32"] = {"R_T": round(R, 6), "R_law": round(law, 6),
                              "err_over_h": round(abs(R - law) / gs.h, 3)}
     del ps
+    # 512 uneven grids, 5000 steps, one persistent launch replayed from a hipGraph
+    insts = workloads.batch_instances(512)
+    b = api.Batch([gi.initial().astype("float32") for gi in insts],
+                  [(gi.h, gi.dt, gi.eps) for gi in insts])
+    info = b.step(5000)                       # builds and caches the plan + graph
+    torch.cuda.synchronize()
+    t = timed(lambda: b.step(5000), 1)
+    gl = b.cells * 5000 / t / 1e9
+    out["batch512_fp32"] = {"GLUPS": round(gl, 2), "f_eff": round(gl * 8 / HBM_PEAK_GBS, 3),
+                            "ms": round(t * 1e3, 2), "cells": b.cells, "launch": info}
+    log("extra batch512_fp32", out["batch512_fp32"])
+    del b
     # 64x64 FP64 phase separation, 500 steps, one LDS-resident launch
     g1 = workloads.phase64()
     p1 = torch.from_numpy(g1.initial()).cuda()

@@ -120,7 +120,76 @@ ac_status ac_plan_2d(int32_t nx, int32_t ny, int64_t nsteps, int32_t dtype,
 ac_status ac_plan_3d(int32_t nx, int32_t ny, int32_t nz, int64_t nsteps, int32_t dtype,
                      const ac_tune *tune, ac_plan *out);
 
-/* Synchronise `stream` and report any pending HIP error as AC_ERR_HIP. */
+/* ------------------------------------------------------------- batched ----
+ * Many independent 2D grids, each with its own size and (h, dt, eps), advanced
+ * by the same number of steps in ONE persistent kernel launch replayed from a
+ * hipGraph.  This batching is not in the paper; each instance computes exactly
+ * what ac_step_2d computes for it (section 2.1, Eq. pytorchACeq), bitwise. */
+typedef struct {
+    void *phi;          /* device pointer, nx*ny elements, 16-byte aligned */
+    void *work;         /* device scratch of the same size */
+    int32_t nx, ny;
+    double h, dt, eps;
+} ac_instance2d;
+
+/* What the persistent launch of a batched call looks like. */
+typedef struct {
+    int32_t grid;       /* workgroups of the persistent launch (all resident) */
+    int32_t items;      /* tiles over all instances, processed per temporal block */
+    int32_t tb_depth;   /* steps per temporal block */
+    int32_t tile_x, tile_y;
+    int32_t blocks;     /* temporal blocks = grid barriers + 1 */
+    int32_t copy_back;
+    int64_t lds_bytes;
+} ac_batch_info;
+
+/* Advance every instance by nsteps.  Every instance is validated as in
+ * ac_step_2d (argument errors name the instance index) and no two buffers of
+ * the batch may overlap.  On first use of an instance table the library
+ * uploads it, sizes the persistent grid to what the device holds at once,
+ * captures [barrier reset, persistent kernel] into a hipGraph on a private
+ * stream and caches it (the 4 most recent tables are kept); calls with the
+ * same table (same pointers, sizes and parameters) and nsteps replay the
+ * graph on `stream`.  The launch shape comes from `tune`, else from the
+ * autotuner's table (ac_autotune_batched), else the 2D defaults.  Grid
+ * barriers wait a bounded time; a timeout (e.g. if other work kept some
+ * workgroups from becoming resident) ends the kernel early and is reported by
+ * the next ac_check().  info (may be NULL) receives the launch description. */
+ac_status ac_step_batched(const ac_instance2d *inst, int32_t n_inst, int64_t nsteps,
+                          int32_t dtype, void *stream);
+ac_status ac_step_batched_tuned(const ac_instance2d *inst, int32_t n_inst, int64_t nsteps,
+                                int32_t dtype, const ac_tune *tune, ac_batch_info *info,
+                                void *stream);
+
+/* Free every cached batched plan (synchronises the device). */
+ac_status ac_batched_release(void);
+
+/* Polls a grid barrier makes before giving up (default 2e7, about 2 s;
+ * negative restores the default).  Drops cached plans.  A diagnostic control:
+ * a tiny limit forces the timeout path. */
+void ac_batched_set_spin_limit(int64_t polls);
+
+/* ----------------------------------------------------------- autotuner ----
+ * Time candidate launch shapes (tb_depth x tile) on scratch buffers of the
+ * given size, store the fastest in a process-wide table keyed by (kind,
+ * dtype, size class = floor(log2(cells))) and return it in *best.  Stepping
+ * calls made with tune == NULL use a matching table entry.  The caller's data
+ * is never touched.  Every candidate gives bitwise the same results. */
+enum { AC_TUNE_2D = 2, AC_TUNE_3D = 3, AC_TUNE_BATCHED = 4 };
+ac_status ac_autotune_2d(int32_t nx, int32_t ny, int32_t dtype, int64_t probe_steps,
+                         ac_tune *best, void *stream);
+ac_status ac_autotune_3d(int32_t nx, int32_t ny, int32_t nz, int32_t dtype,
+                         int64_t probe_steps, ac_tune *best, void *stream);
+ac_status ac_autotune_batched(const ac_instance2d *inst, int32_t n_inst, int32_t dtype,
+                              int64_t probe_steps, ac_tune *best, void *stream);
+/* Persist / restore / clear the tuning table (a small JSON file). */
+ac_status ac_tune_save(const char *path);
+ac_status ac_tune_load(const char *path);
+void ac_tune_clear(void);
+int32_t ac_tune_count(void);
+
+/* Synchronise `stream` and report any pending HIP error, or a batched grid
+ * barrier timeout, as AC_ERR_HIP. */
 ac_status ac_check(void *stream);
 
 /* Static description of a status code. */

@@ -37,6 +37,23 @@ class AcPlan(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class AcInstance2D(ctypes.Structure):
+    _fields_ = [("phi", ctypes.c_void_p), ("work", ctypes.c_void_p), ("nx", ctypes.c_int32),
+                ("ny", ctypes.c_int32), ("h", ctypes.c_double), ("dt", ctypes.c_double),
+                ("eps", ctypes.c_double)]
+
+
+class AcBatchInfo(ctypes.Structure):
+    _fields_ = [("grid", ctypes.c_int32), ("items", ctypes.c_int32), ("tb_depth", ctypes.c_int32),
+                ("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32), ("blocks", ctypes.c_int32),
+                ("copy_back", ctypes.c_int32), ("lds_bytes", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+AC_TUNE_2D, AC_TUNE_3D, AC_TUNE_BATCHED = 2, 3, 4
+
 KERNEL_NAMES = {0: "tile2d_kernel (resident)", 1: "tile2d_kernel", 2: "stream3d_kernel"}
 
 
@@ -60,6 +77,19 @@ SIGNATURES = {
     "ac_plan_2d": ([_i32, _i32, _i64, _i32, ctypes.POINTER(AcTune), ctypes.POINTER(AcPlan)], _i32),
     "ac_plan_3d": ([_i32, _i32, _i32, _i64, _i32, ctypes.POINTER(AcTune),
                     ctypes.POINTER(AcPlan)], _i32),
+    "ac_step_batched": ([ctypes.POINTER(AcInstance2D), _i32, _i64, _i32, _vp], _i32),
+    "ac_step_batched_tuned": ([ctypes.POINTER(AcInstance2D), _i32, _i64, _i32,
+                               ctypes.POINTER(AcTune), ctypes.POINTER(AcBatchInfo), _vp], _i32),
+    "ac_batched_release": ([], _i32),
+    "ac_batched_set_spin_limit": ([_i64], None),
+    "ac_autotune_2d": ([_i32, _i32, _i32, _i64, ctypes.POINTER(AcTune), _vp], _i32),
+    "ac_autotune_3d": ([_i32, _i32, _i32, _i32, _i64, ctypes.POINTER(AcTune), _vp], _i32),
+    "ac_autotune_batched": ([ctypes.POINTER(AcInstance2D), _i32, _i32, _i64,
+                             ctypes.POINTER(AcTune), _vp], _i32),
+    "ac_tune_save": ([ctypes.c_char_p], _i32),
+    "ac_tune_load": ([ctypes.c_char_p], _i32),
+    "ac_tune_clear": ([], None),
+    "ac_tune_count": ([], _i32),
     "ac_check": ([_vp], _i32),
     "ac_status_string": ([_i32], ctypes.c_char_p),
     "ac_last_error": ([], ctypes.c_char_p),

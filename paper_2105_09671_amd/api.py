@@ -101,3 +101,91 @@ def plan3d(nx: int, ny: int, nz: int, nsteps: int, dtype=torch.float32, tune=Non
     L.check(L.lib().ac_plan_3d(nx, ny, nz, int(nsteps), code, _tune(tune), ctypes.byref(p)),
             "ac_plan_3d")
     return p.as_dict()
+
+
+# ---------------------------------------------------------------- batched ----
+class Batch:
+    """Independent 2D grids packed into one phi buffer and one work buffer.
+
+    ``fields`` are (ny, nx) arrays; ``params`` are (h, dt, eps) per grid.  Each
+    grid starts on a 256-byte boundary.  ``views()`` returns the per-grid phi
+    tensors (views into the packed buffer)."""
+
+    def __init__(self, fields, params, dtype=torch.float32, device="cuda"):
+        import numpy as np
+        self.dtype = dtype
+        elem = torch.tensor([], dtype=dtype).element_size()
+        align = 256 // elem
+        self.shapes = [tuple(np.shape(f)) for f in fields]
+        self.offsets = []
+        off = 0
+        for (ny, nx) in self.shapes:
+            self.offsets.append(off)
+            off += (ny * nx + align - 1) // align * align
+        self.total = off
+        host = torch.zeros(off, dtype=dtype)
+        for f, o, (ny, nx) in zip(fields, self.offsets, self.shapes):
+            host[o:o + ny * nx] = torch.as_tensor(np.ascontiguousarray(f).ravel(), dtype=dtype)
+        self.phi = host.to(device)
+        self.work = torch.empty_like(self.phi)
+        self.params = [tuple(float(v) for v in p) for p in params]
+        self._arr = self._instances(self.phi, self.work)
+
+    def _instances(self, phi, work):
+        elem = phi.element_size()
+        arr = (L.AcInstance2D * len(self.shapes))()
+        for i, ((ny, nx), o, (h, dt, eps)) in enumerate(zip(self.shapes, self.offsets, self.params)):
+            arr[i] = L.AcInstance2D(phi.data_ptr() + o * elem, work.data_ptr() + o * elem,
+                                    nx, ny, h, dt, eps)
+        return arr
+
+    @property
+    def cells(self) -> int:
+        return sum(nx * ny for (ny, nx) in self.shapes)
+
+    def views(self):
+        return [self.phi[o:o + ny * nx].view(ny, nx) for o, (ny, nx) in zip(self.offsets, self.shapes)]
+
+    def step(self, nsteps: int, tune=None, stream=None) -> dict:
+        info = L.AcBatchInfo()
+        st = L.lib().ac_step_batched_tuned(self._arr, len(self.shapes), int(nsteps),
+                                           _dtype_code(self.phi), _tune(tune), ctypes.byref(info),
+                                           _stream(stream))
+        L.check(st, "ac_step_batched")
+        return info.as_dict()
+
+    def autotune(self, probe_steps: int = 200, stream=None) -> dict:
+        best = L.AcTune()
+        L.check(L.lib().ac_autotune_batched(self._arr, len(self.shapes), _dtype_code(self.phi),
+                                            int(probe_steps), ctypes.byref(best), _stream(stream)),
+                "ac_autotune_batched")
+        return {k: getattr(best, k) for k, _ in best._fields_}
+
+
+def autotune2d(nx: int, ny: int, dtype=torch.float32, probe_steps: int = 200, stream=None) -> dict:
+    best = L.AcTune()
+    code = L.AC_F64 if dtype == torch.float64 else L.AC_F32
+    L.check(L.lib().ac_autotune_2d(nx, ny, code, int(probe_steps), ctypes.byref(best),
+                                   _stream(stream)), "ac_autotune_2d")
+    return {k: getattr(best, k) for k, _ in best._fields_}
+
+
+def autotune3d(nx: int, ny: int, nz: int, dtype=torch.float32, probe_steps: int = 50,
+               stream=None) -> dict:
+    best = L.AcTune()
+    code = L.AC_F64 if dtype == torch.float64 else L.AC_F32
+    L.check(L.lib().ac_autotune_3d(nx, ny, nz, code, int(probe_steps), ctypes.byref(best),
+                                   _stream(stream)), "ac_autotune_3d")
+    return {k: getattr(best, k) for k, _ in best._fields_}
+
+
+def tune_save(path: str) -> None:
+    L.check(L.lib().ac_tune_save(path.encode()), "ac_tune_save")
+
+
+def tune_load(path: str) -> None:
+    L.check(L.lib().ac_tune_load(path.encode()), "ac_tune_load")
+
+
+def tune_clear() -> None:
+    L.lib().ac_tune_clear()

@@ -12,7 +12,7 @@
 
 #include "ac_internal.h"
 
-namespace {
+namespace ac {
 
 thread_local std::string g_err;
 
@@ -65,10 +65,6 @@ ac_status validate(const void *phi, const void *work, int64_t ncells, int dim, d
 // launches is even (ping-pong then ends in phi).  Returns false if that is
 // impossible (every launch is a single step and the count is odd): the caller
 // then copies work back into phi at the end.
-struct Chunks {
-    int64_t n, base, rem;  // n launches; launch i does base + (i < rem) steps
-    bool copy_back;
-};
 Chunks plan_chunks(int64_t nsteps, int64_t k) {
     Chunks c{};
     c.n = (nsteps + k - 1) / k;
@@ -221,10 +217,6 @@ ac_status run3d(T *phi, T *work, int nx, int ny, int nz, double alpha_d, double 
     return AC_OK;
 }
 
-}  // namespace
-
-namespace ac {
-
 hipError_t device_info(DevInfo *out) {
     static std::mutex mu;
     static DevInfo cache[64];
@@ -251,6 +243,8 @@ hipError_t device_info(DevInfo *out) {
 
 }  // namespace ac
 
+using namespace ac;
+
 extern "C" {
 
 ac_status ac_step_2d_tuned(void *phi, void *work, int32_t nx, int32_t ny, double h, double dt,
@@ -264,6 +258,8 @@ ac_status ac_step_2d_tuned(void *phi, void *work, int32_t nx, int32_t ny, double
     ac::DevInfo dev;
     hipError_t e = ac::device_info(&dev);
     if (e != hipSuccess) return hip_fail(e, "device query");
+    ac_tune tabled;
+    if (!tune && tuned_lookup(AC_TUNE_2D, dtype, nx, ny, 1, &tabled)) tune = &tabled;
     ac_plan p;
     if ((s = make_plan2d(nx, ny, nsteps, elem_size(dtype), tune, dev, &p)) != AC_OK) return s;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
@@ -289,6 +285,8 @@ ac_status ac_step_3d_tuned(void *phi, void *work, int32_t nx, int32_t ny, int32_
     ac::DevInfo dev;
     hipError_t e = ac::device_info(&dev);
     if (e != hipSuccess) return hip_fail(e, "device query");
+    ac_tune tabled;
+    if (!tune && tuned_lookup(AC_TUNE_3D, dtype, nx, ny, nz, &tabled)) tune = &tabled;
     ac_plan p;
     if ((s = make_plan3d(nx, ny, nz, nsteps, elem_size(dtype), tune, dev, &p)) != AC_OK) return s;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
@@ -311,6 +309,8 @@ ac_status ac_plan_2d(int32_t nx, int32_t ny, int64_t nsteps, int32_t dtype, cons
     ac::DevInfo dev;
     hipError_t e = ac::device_info(&dev);
     if (e != hipSuccess) return hip_fail(e, "device query");
+    ac_tune tabled;
+    if (!tune && tuned_lookup(AC_TUNE_2D, dtype, nx, ny, 1, &tabled)) tune = &tabled;
     return make_plan2d(nx, ny, nsteps, elem_size(dtype), tune, dev, out);
 }
 
@@ -323,6 +323,8 @@ ac_status ac_plan_3d(int32_t nx, int32_t ny, int32_t nz, int64_t nsteps, int32_t
     ac::DevInfo dev;
     hipError_t e = ac::device_info(&dev);
     if (e != hipSuccess) return hip_fail(e, "device query");
+    ac_tune tabled;
+    if (!tune && tuned_lookup(AC_TUNE_3D, dtype, nx, ny, nz, &tabled)) tune = &tabled;
     return make_plan3d(nx, ny, nz, nsteps, elem_size(dtype), tune, dev, out);
 }
 
@@ -330,7 +332,7 @@ ac_status ac_check(void *stream) {
     hipError_t e = hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream));
     if (e == hipSuccess) e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "ac_check");
-    return AC_OK;
+    return batched_check_errors();
 }
 
 const char *ac_status_string(int32_t s) {

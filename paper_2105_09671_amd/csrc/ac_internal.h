@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <string>
 
 #include "ac.h"
 
@@ -72,6 +73,32 @@ inline void set_lds_limit(const void *kernel, size_t bytes) {
         hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess)
         (void)hipGetLastError();
 }
+
+// ----------------------------------------------------- host helpers ----
+// (ac_api.hip) Status with a thread-local message; argument validation that
+// makes no HIP call; the even-launch-count step split; per-call plans.
+ac_status fail(ac_status s, const char *fmt, ...);
+ac_status hip_fail(hipError_t e, const char *what);
+extern thread_local std::string g_err;
+size_t elem_size(int32_t dtype);
+ac_status validate(const void *phi, const void *work, int64_t ncells, int dim, double h,
+                   double dt, double eps, int64_t nsteps, int32_t dtype, double *alpha,
+                   double *r);
+struct Chunks {
+    int64_t n, base, rem;  // n launches; launch i does base + (i < rem) steps
+    bool copy_back;
+};
+Chunks plan_chunks(int64_t nsteps, int64_t k);
+struct DevInfo;
+ac_status make_plan2d(int nx, int ny, int64_t nsteps, size_t elem, const ac_tune *tune,
+                      const DevInfo &dev, ac_plan *p);
+ac_status make_plan3d(int nx, int ny, int nz, int64_t nsteps, size_t elem, const ac_tune *tune,
+                      const DevInfo &dev, ac_plan *p);
+
+// Autotuner table lookup (tune.hip); kind is AC_TUNE_*.
+bool tuned_lookup(int kind, int32_t dtype, int64_t nx, int64_t ny, int64_t nz, ac_tune *out);
+// Barrier-timeout flags of cached batched plans (batched.hip).
+ac_status batched_check_errors();
 
 // Device limits, cached per device.
 struct DevInfo {

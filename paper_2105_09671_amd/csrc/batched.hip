@@ -1,0 +1,408 @@
+// Batched stepping: many independent 2D grids (own size, h, dt, eps) advanced
+// by one persistent kernel, captured once in a hipGraph and replayed.
+//
+// Work decomposition.  Every instance is cut into the same LDS tiles as the
+// single-grid tiled kernel (tile2d.h).  One "item" is one tile of one instance;
+// the item list is the same for every temporal block of tb_depth steps.  A
+// fixed grid of workgroups, sized to what the device holds at once, walks the
+// item list for block b, meets at a grid barrier, and moves on to block b+1
+// (instances ping-pong between phi and work, so the barrier is what makes the
+// halo of block b+1 see the finished block b).
+//
+// XCD-aware schedule: the dispatcher places workgroup g on XCD g mod 8, and
+// each XCD has its own L2.  The item list is split into 8 contiguous ranges
+// and XCD x's workgroups stride over range x only, so the tiles of one
+// instance -- which re-read each other's halos -- share one L2.
+//
+// The grid barrier is a monotonically increasing counter (reset by a one-thread
+// kernel captured in front of the persistent kernel).  Waits are bounded: after
+// `spin_limit` polls a workgroup raises the error flag and every workgroup
+// leaves at its next barrier, so the kernel always drains; the host reports
+// the flag through ac_check().
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cstring>
+#include <list>
+#include <mutex>
+#include <vector>
+
+#include "tile2d.h"
+
+namespace ac {
+
+struct BatchInst {
+    void *phi, *work;
+    int nx, ny;
+    double alpha, r;
+};
+
+__global__ void batch_reset_kernel(unsigned *bar) { *bar = 0u; }
+
+// Returns false once any workgroup has given up waiting.
+__device__ __forceinline__ bool grid_sync(unsigned *bar, unsigned target, int *err,
+                                          long long spin_limit) {
+    __shared__ int s_ok;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();   // publish this workgroup's stores device-wide
+        atomicAdd(bar, 1u);
+        int ok = 1;
+        long long spins = 0;
+        while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { ok = 0; break; }
+            if (++spins > spin_limit) {
+                atomicExch(err, 1);
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(4);
+        }
+        __threadfence();   // see every other workgroup's stores
+        s_ok = ok;
+    }
+    __syncthreads();
+    return s_ok != 0;
+}
+
+// Copy the output region of one tile from src to dst (final odd-count fix-up).
+template <typename T>
+__device__ void copy_tile(const T *src, T *dst, int nx, int ny, int OX, int OY, int tx, int ty) {
+    const int x0 = tx * OX, y0 = ty * OY;
+    const int x1 = min(x0 + OX, nx), y1 = min(y0 + OY, ny);
+    const int w = x1 - x0;
+    for (int i = threadIdx.x; i < w * (y1 - y0); i += blockDim.x) {
+        const int y = y0 + i / w, x = x0 + i % w;
+        dst[(size_t)y * nx + x] = src[(size_t)y * nx + x];
+    }
+}
+
+template <typename T, int LXC>
+__global__ void __launch_bounds__(256)
+batched_kernel(const BatchInst *__restrict__ inst, const int4 *__restrict__ items, int n_items,
+               int LX, int LY, int K, int nblocks, int base, int rem, int copy_back,
+               unsigned *bar, int *err, long long spin_limit)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int G = gridDim.x;                    // a multiple of 8
+    const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3, per = G >> 3;
+    const int lo = (int)((long long)n_items * xcd / 8);
+    const int hi = (int)((long long)n_items * (xcd + 1) / 8);
+    unsigned target = 0;
+    for (int b = 0; b < nblocks; ++b) {
+        const int k = base + (b < rem ? 1 : 0);
+        for (int i = lo + j; i < hi; i += per) {
+            const int4 it = items[i];
+            const BatchInst I = inst[it.x];
+            const T *src = static_cast<const T *>((b & 1) ? I.work : I.phi);
+            T *dst = static_cast<T *>((b & 1) ? I.phi : I.work);
+            tile2d_body<T, LXC>(src, dst, I.nx, I.ny, (T)I.alpha, (T)I.r, LX, LY, K, k, it.y,
+                                it.z, smem_raw);
+            __syncthreads();   // LDS is reused by the next item
+        }
+        if (b + 1 < nblocks || copy_back) {
+            target += (unsigned)G;
+            if (!grid_sync(bar, target, err, spin_limit)) return;
+        }
+    }
+    if (copy_back) {   // odd number of single-step blocks: the result sits in work
+        for (int i = lo + j; i < hi; i += per) {
+            const int4 it = items[i];
+            const BatchInst I = inst[it.x];
+            copy_tile<T>(static_cast<const T *>(I.work), static_cast<T *>(I.phi), I.nx, I.ny,
+                         LX - 2 * K, LY - 2 * K, it.y, it.z);
+        }
+    }
+}
+
+// ---------------------------------------------------------------- host ----
+
+namespace {
+
+long long g_spin_limit = 20000000;   // ~2 s of polling per barrier
+
+struct Plan {
+    // key
+    std::vector<ac_instance2d> inst;
+    int64_t nsteps;
+    int32_t dtype;
+    ac_tune tune;
+    int device;
+    // device state
+    BatchInst *d_inst = nullptr;
+    int4 *d_items = nullptr;
+    unsigned *d_bar = nullptr;
+    int *d_err = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    int grid = 0, n_items = 0;
+    ac_batch_info info{};
+};
+
+std::mutex g_mu;
+std::list<Plan> g_plans;          // most recently used first
+constexpr size_t kMaxPlans = 4;
+hipStream_t g_capture_stream[64];
+
+bool same_inst(const ac_instance2d &a, const ac_instance2d &b) {
+    return a.phi == b.phi && a.work == b.work && a.nx == b.nx && a.ny == b.ny && a.h == b.h &&
+           a.dt == b.dt && a.eps == b.eps;
+}
+
+bool key_equal(const Plan &p, const ac_instance2d *inst, int32_t n, int64_t nsteps,
+               int32_t dtype, const ac_tune &t, int dev) {
+    if (p.device != dev || p.nsteps != nsteps || p.dtype != dtype || (int32_t)p.inst.size() != n)
+        return false;
+    if (std::memcmp(&p.tune, &t, sizeof t) != 0) return false;
+    for (int32_t i = 0; i < n; ++i)
+        if (!same_inst(p.inst[i], inst[i])) return false;
+    return true;
+}
+
+void release(Plan &p) {
+    if (p.exec) (void)hipGraphExecDestroy(p.exec);
+    if (p.graph) (void)hipGraphDestroy(p.graph);
+    if (p.d_inst) (void)hipFree(p.d_inst);
+    if (p.d_items) (void)hipFree(p.d_items);
+    if (p.d_bar) (void)hipFree(p.d_bar);
+    if (p.d_err) (void)hipFree(p.d_err);
+    p.exec = nullptr; p.graph = nullptr; p.d_inst = nullptr; p.d_items = nullptr;
+    p.d_bar = nullptr; p.d_err = nullptr;
+}
+
+template <typename T, int LXC>
+const void *kernel_ptr() { return (const void *)batched_kernel<T, LXC>; }
+
+const void *select_kernel(int32_t dtype, int LX) {
+    if (dtype == AC_F64) {
+        if (LX == 64) return kernel_ptr<double, 64>();
+        if (LX == 128) return kernel_ptr<double, 128>();
+        return kernel_ptr<double, 0>();
+    }
+    if (LX == 64) return kernel_ptr<float, 64>();
+    if (LX == 128) return kernel_ptr<float, 128>();
+    return kernel_ptr<float, 0>();
+}
+
+// Validate every instance (no HIP call) and check no two buffers overlap.
+ac_status validate_batch(const ac_instance2d *inst, int32_t n, int64_t nsteps, int32_t dtype,
+                         std::vector<double> *alpha, std::vector<double> *r) {
+    if (n < 0 || (n > 0 && !inst)) return fail(AC_ERR_INVALID_ARG, "bad instance array");
+    alpha->resize(n);
+    r->resize(n);
+    std::vector<std::pair<uintptr_t, uintptr_t>> ranges;
+    ranges.reserve(2 * (size_t)n);
+    for (int32_t i = 0; i < n; ++i) {
+        const ac_instance2d &I = inst[i];
+        if (I.nx < 1 || I.ny < 1)
+            return fail(AC_ERR_INVALID_ARG, "instance %d: nx, ny must be >= 1", i);
+        ac_status s = validate(I.phi, I.work, (int64_t)I.nx * I.ny, 2, I.h, I.dt, I.eps, nsteps,
+                               dtype, &(*alpha)[i], &(*r)[i]);
+        if (s != AC_OK) {
+            std::string m = g_err;
+            return fail(s, "instance %d: %s", i, m.c_str());
+        }
+        const size_t bytes = (size_t)I.nx * I.ny * elem_size(dtype);
+        ranges.push_back({(uintptr_t)I.phi, (uintptr_t)I.phi + bytes});
+        ranges.push_back({(uintptr_t)I.work, (uintptr_t)I.work + bytes});
+    }
+    std::sort(ranges.begin(), ranges.end());
+    for (size_t i = 1; i < ranges.size(); ++i)
+        if (ranges[i].first < ranges[i - 1].second)
+            return fail(AC_ERR_INVALID_ARG, "instance buffers overlap");
+    return AC_OK;
+}
+
+ac_status build_plan(Plan &p, const ac_instance2d *inst, int32_t n, int64_t nsteps, int32_t dtype,
+                     const ac_tune &tune, const std::vector<double> &alpha,
+                     const std::vector<double> &r, const DevInfo &dev) {
+    const size_t elem = elem_size(dtype);
+    // launch shape: the single-grid tiled plan for the same tune (forced tiled)
+    ac_tune t = tune;
+    if (t.tile_x == 0) t.tile_x = 64;
+    if (t.tile_y == 0) t.tile_y = dtype == AC_F64 ? 32 : 64;
+    if (t.tb_depth == 0) t.tb_depth = dtype == AC_F64 ? 4 : 8;
+    ac_plan tp;
+    ac_status s = make_plan2d(4096, 4096, nsteps, elem, &t, dev, &tp);
+    if (s != AC_OK) return s;
+    const int LX = tp.tile_x, LY = tp.tile_y, K = tp.tb_depth;
+    const int OX = LX - 2 * K, OY = LY - 2 * K;
+    std::vector<BatchInst> hi(n);
+    std::vector<int4> items;
+    for (int32_t i = 0; i < n; ++i) {
+        hi[i] = BatchInst{inst[i].phi, inst[i].work, inst[i].nx, inst[i].ny, alpha[i], r[i]};
+        const int tx = (inst[i].nx + OX - 1) / OX, ty = (inst[i].ny + OY - 1) / OY;
+        for (int y = 0; y < ty; ++y)
+            for (int x = 0; x < tx; ++x) items.push_back(int4{i, x, y, 0});
+    }
+    const Chunks c = plan_chunks(nsteps, K);
+    const void *kern = select_kernel(dtype, LX);
+    const size_t lds = (size_t)tp.lds_bytes;
+    set_lds_limit(kern, lds);
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, lds);
+    if (e != hipSuccess) return hip_fail(e, "occupancy query");
+    if (per_cu < 1) return fail(AC_ERR_UNSUPPORTED, "batched kernel does not fit on a CU");
+    // every workgroup must be resident at once (grid barrier); 8 | grid
+    int grid = per_cu * dev.cus;
+    const int want = (int)std::min<size_t>((size_t)grid, (items.size() + 7) / 8 * 8);
+    grid = std::max(8, want / 8 * 8);
+    p.n_items = (int)items.size();
+    p.grid = grid;
+    if ((e = hipMalloc(&p.d_inst, sizeof(BatchInst) * std::max<int32_t>(n, 1))) != hipSuccess ||
+        (e = hipMalloc(&p.d_items, sizeof(int4) * std::max<size_t>(items.size(), 1))) != hipSuccess ||
+        (e = hipMalloc(&p.d_bar, sizeof(unsigned))) != hipSuccess ||
+        (e = hipMalloc(&p.d_err, sizeof(int))) != hipSuccess) {
+        release(p);
+        return fail(AC_ERR_NOMEM, "batched plan allocation: %s", hipGetErrorString(e));
+    }
+    if (n > 0) e = hipMemcpy(p.d_inst, hi.data(), sizeof(BatchInst) * n, hipMemcpyHostToDevice);
+    if (e == hipSuccess && !items.empty())
+        e = hipMemcpy(p.d_items, items.data(), sizeof(int4) * items.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(p.d_err, 0, sizeof(int));
+    if (e != hipSuccess) { release(p); return hip_fail(e, "batched plan upload"); }
+
+    // capture [reset barrier, persistent kernel] on a library-owned stream
+    hipStream_t &cs = g_capture_stream[p.device];
+    if (!cs && (e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking)) != hipSuccess) {
+        release(p);
+        return hip_fail(e, "capture stream");
+    }
+    if ((e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
+        release(p);
+        return hip_fail(e, "begin capture");
+    }
+    hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(1), 0, cs, p.d_bar);
+    const int nblocks = (int)c.n;
+    const long long spin = g_spin_limit;
+    const int cb = c.copy_back ? 1 : 0;
+    const int base = (int)c.base, rem = (int)c.rem, ni = p.n_items;
+    void *args[] = {&p.d_inst, &p.d_items, (void *)&ni, (void *)&LX, (void *)&LY, (void *)&K,
+                    (void *)&nblocks, (void *)&base, (void *)&rem, (void *)&cb, &p.d_bar,
+                    &p.d_err, (void *)&spin};
+    hipError_t le = hipLaunchKernel(kern, dim3(grid), dim3(256), args, lds, cs);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(cs, &g);
+    if (le != hipSuccess || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        release(p);
+        return hip_fail(le != hipSuccess ? le : e, "capture batched launch");
+    }
+    p.graph = g;
+    if ((e = hipGraphInstantiate(&p.exec, g, nullptr, nullptr, 0)) != hipSuccess) {
+        release(p);
+        return hip_fail(e, "instantiate batched graph");
+    }
+    p.info.grid = grid;
+    p.info.items = p.n_items;
+    p.info.tb_depth = K;
+    p.info.tile_x = LX;
+    p.info.tile_y = LY;
+    p.info.blocks = nblocks;
+    p.info.copy_back = cb;
+    p.info.lds_bytes = (int64_t)lds;
+    return AC_OK;
+}
+
+}  // namespace
+
+// Reports (and clears) a barrier timeout of any cached batched plan on this
+// device.  Called by ac_check after the stream has drained.
+ac_status batched_check_errors() {
+    std::lock_guard<std::mutex> lock(g_mu);
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return AC_OK;
+    for (Plan &p : g_plans) {
+        if (p.device != dev || !p.d_err) continue;
+        int v = 0;
+        hipError_t e = hipMemcpy(&v, p.d_err, sizeof v, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e, "read batched error flag");
+        if (v) {
+            (void)hipMemset(p.d_err, 0, sizeof(int));
+            return fail(AC_ERR_HIP, "batched grid barrier timed out; results of that call are "
+                                    "incomplete");
+        }
+    }
+    return AC_OK;
+}
+
+}  // namespace ac
+
+using namespace ac;
+
+extern "C" {
+
+ac_status ac_step_batched_tuned(const ac_instance2d *inst, int32_t n_inst, int64_t nsteps,
+                                int32_t dtype, const ac_tune *tune, ac_batch_info *info,
+                                void *stream) {
+    g_err.clear();
+    std::vector<double> alpha, r;
+    ac_status s = validate_batch(inst, n_inst, nsteps, dtype, &alpha, &r);
+    if (s != AC_OK) return s;
+    if (nsteps == 0 || n_inst == 0) {
+        if (info) std::memset(info, 0, sizeof *info);
+        return AC_OK;
+    }
+    DevInfo dev;
+    hipError_t e = device_info(&dev);
+    if (e != hipSuccess) return hip_fail(e, "device query");
+    int device = 0;
+    if ((e = hipGetDevice(&device)) != hipSuccess) return hip_fail(e, "hipGetDevice");
+    ac_tune t{};
+    if (tune) t = *tune;
+    else {
+        ac_tune tabled;
+        if (tuned_lookup(AC_TUNE_BATCHED, dtype, 0, 0, 0, &tabled)) t = tabled;
+    }
+    std::lock_guard<std::mutex> lock(g_mu);
+    auto it = g_plans.begin();
+    for (; it != g_plans.end(); ++it)
+        if (key_equal(*it, inst, n_inst, nsteps, dtype, t, device)) break;
+    if (it == g_plans.end()) {
+        Plan p;
+        p.inst.assign(inst, inst + n_inst);
+        p.nsteps = nsteps;
+        p.dtype = dtype;
+        p.tune = t;
+        p.device = device;
+        if ((s = build_plan(p, inst, n_inst, nsteps, dtype, t, alpha, r, dev)) != AC_OK) return s;
+        g_plans.push_front(std::move(p));
+        while (g_plans.size() > kMaxPlans) {
+            (void)hipDeviceSynchronize();   // the evicted graph may still be running
+            release(g_plans.back());
+            g_plans.pop_back();
+        }
+        it = g_plans.begin();
+    } else if (it != g_plans.begin()) {
+        g_plans.splice(g_plans.begin(), g_plans, it);
+        it = g_plans.begin();
+    }
+    if (info) *info = it->info;
+    if ((e = hipGraphLaunch(it->exec, reinterpret_cast<hipStream_t>(stream))) != hipSuccess)
+        return hip_fail(e, "batched graph launch");
+    return AC_OK;
+}
+
+ac_status ac_step_batched(const ac_instance2d *inst, int32_t n_inst, int64_t nsteps,
+                          int32_t dtype, void *stream) {
+    return ac_step_batched_tuned(inst, n_inst, nsteps, dtype, nullptr, nullptr, stream);
+}
+
+ac_status ac_batched_release(void) {
+    std::lock_guard<std::mutex> lock(g_mu);
+    hipError_t e = hipDeviceSynchronize();
+    for (Plan &p : g_plans) release(p);
+    g_plans.clear();
+    return e == hipSuccess ? AC_OK : hip_fail(e, "ac_batched_release");
+}
+
+void ac_batched_set_spin_limit(int64_t polls) {
+    std::lock_guard<std::mutex> lock(g_mu);
+    g_spin_limit = polls < 0 ? 20000000 : polls;
+    if (!g_plans.empty()) (void)hipDeviceSynchronize();
+    for (Plan &p : g_plans) release(p);   // the limit is baked into captured graphs
+    g_plans.clear();
+}
+
+}  // extern "C"

@@ -99,3 +99,52 @@ def test_error_message_is_thread_local_and_cleared(lib):
     assert lib.ac_last_error()
     assert s2(lib, n=0) == L.AC_OK
     assert lib.ac_last_error() == b""
+
+
+def _inst_array(lib, specs):
+    arr = (L.AcInstance2D * len(specs))()
+    for i, s in enumerate(specs):
+        arr[i] = L.AcInstance2D(*s)
+    return arr
+
+
+def test_batched_validation_before_hip(lib):
+    good = [(A, B, 64, 64, H, DT, EPS), (A + 2 ** 20, B + 2 ** 20, 32, 16, H, DT, EPS)]
+    arr = _inst_array(lib, good)
+    assert lib.ac_step_batched(arr, 2, 0, 0, None) == L.AC_OK          # nsteps = 0
+    assert lib.ac_step_batched(arr, 0, 10, 0, None) == L.AC_OK         # empty batch
+    assert lib.ac_step_batched(None, 2, 10, 0, None) == L.AC_ERR_INVALID_ARG
+    assert lib.ac_step_batched(arr, 2, -1, 0, None) == L.AC_ERR_INVALID_ARG
+    assert lib.ac_step_batched(arr, 2, 10, 5, None) == L.AC_ERR_INVALID_ARG
+    bad = _inst_array(lib, [good[0], (A + 2 ** 20, B + 2 ** 20, 0, 16, H, DT, EPS)])
+    assert lib.ac_step_batched(bad, 2, 10, 0, None) == L.AC_ERR_INVALID_ARG
+    assert b"instance 1" in lib.ac_last_error()
+    unstable = _inst_array(lib, [good[0], (A + 2 ** 20, B + 2 ** 20, 32, 16, H, 0.3 * H * H, EPS)])
+    assert lib.ac_step_batched(unstable, 2, 10, 0, None) == L.AC_ERR_UNSTABLE
+    # instance 1's phi overlaps instance 0's phi
+    overlap = _inst_array(lib, [good[0], (A + 1024, B + 2 ** 20, 32, 16, H, DT, EPS)])
+    assert lib.ac_step_batched(overlap, 2, 10, 0, None) == L.AC_ERR_INVALID_ARG
+    assert b"overlap" in lib.ac_last_error()
+
+
+def test_tune_table_json_roundtrip(lib, tmp_path):
+    lib.ac_tune_clear()
+    assert lib.ac_tune_count() == 0
+    src = tmp_path / "in.json"
+    src.write_text('{"arch": "gfx950", "entries": [\n'
+                   ' {"kind": 2, "dtype": 0, "cls": 22, "tb_depth": 8, "tile_x": 64, "tile_y": 64, "tile_z": 0},\n'
+                   ' {"kind": 3, "dtype": 1, "cls": 24, "tb_depth": 3, "tile_x": 32, "tile_y": 16, "tile_z": 32}\n'
+                   ']}\n')
+    assert lib.ac_tune_load(str(src).encode()) == L.AC_OK
+    assert lib.ac_tune_count() == 2
+    out = tmp_path / "out.json"
+    assert lib.ac_tune_save(str(out).encode()) == L.AC_OK
+    lib.ac_tune_clear()
+    assert lib.ac_tune_load(str(out).encode()) == L.AC_OK
+    assert lib.ac_tune_count() == 2
+    assert out.read_text() == src.read_text().replace("gfx950", "gfx950")
+    bad = tmp_path / "bad.json"
+    bad.write_text("{}")
+    assert lib.ac_tune_load(str(bad).encode()) == L.AC_ERR_INVALID_ARG
+    assert lib.ac_tune_load(b"/nonexistent/x.json") == L.AC_ERR_INVALID_ARG
+    lib.ac_tune_clear()

@@ -1,0 +1,177 @@
+"""Batched persistent stepping (ac_step_batched) on the GPU.
+
+Each instance of a batch must equal, bitwise, what ac_step_2d computes for it
+alone with the same launch shape, and match the FP64 oracle to the usual bars.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import diagnostics as D
+from paper_2105_09671_amd import inputs, params, workloads
+
+pytestmark = pytest.mark.gpu
+
+NP = {torch.float64: np.float64, torch.float32: np.float32}
+TOL = {torch.float64: 1e-12, torch.float32: 1e-5}
+
+
+@pytest.fixture(scope="module")
+def api():
+    assert torch.cuda.is_available()
+    from paper_2105_09671_amd import api as a
+    return a
+
+
+def _small_batch(seed=40):
+    shapes = [(64, 64), (37, 101), (1, 50), (50, 1), (130, 70), (1, 1), (96, 96), (200, 17),
+              (3, 3), (65, 129), (128, 128), (20, 300)]
+    fields, prm = [], []
+    for i, (ny, nx) in enumerate(shapes):
+        m = 3 + i % 6
+        h = 1.0 / min(nx, ny) if min(nx, ny) > 4 else 1.0 / 64
+        fields.append(inputs.random_field((ny, nx), seed, stream=i, amp=0.5))
+        prm.append((h, params.dt_of(h), params.eps_m(h, m)))
+    return fields, prm
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("nsteps,tune", [(37, None), (37, dict(tb_depth=3, tile_x=64, tile_y=32)),
+                                         (5, dict(tb_depth=1, tile_x=64, tile_y=32)),
+                                         (1, None), (8, dict(tb_depth=8, tile_x=128, tile_y=64))])
+def test_batch_matches_single_and_oracle(api, dtype, nsteps, tune):
+    fields, prm = _small_batch()
+    fields = [f.astype(NP[dtype]) for f in fields]
+    b = api.Batch(fields, prm, dtype=dtype)
+    info = b.step(nsteps, tune=tune)
+    api.check()
+    assert info["grid"] % 8 == 0 and info["items"] >= len(fields)
+    got = [v.cpu().numpy() for v in b.views()]
+    for i, (f, (h, dt, eps)) in enumerate(zip(fields, prm)):
+        ref = oracle.step2d(f.astype(np.float64), h, dt, eps, nsteps)
+        assert D.rel_linf(got[i], ref) <= TOL[dtype], "instance %d" % i
+        single = torch.from_numpy(f).cuda()
+        api.step2d(single, h, dt, eps, nsteps)
+        assert np.array_equal(single.cpu().numpy(), got[i]), "instance %d vs single grid" % i
+
+
+def test_batch_order_and_replay(api):
+    fields, prm = _small_batch(41)
+    fields = [f.astype(np.float32) for f in fields]
+    perm = np.random.RandomState(0).permutation(len(fields))
+    a = api.Batch(fields, prm)
+    bp = api.Batch([fields[i] for i in perm], [prm[i] for i in perm])
+    a.step(30)
+    bp.step(30)
+    ga = [v.cpu().numpy() for v in a.views()]
+    gb = [v.cpu().numpy() for v in bp.views()]
+    for k, i in enumerate(perm):
+        assert np.array_equal(ga[i], gb[k])
+    # graph replay: same pointers, restored data, same bits; and a second replay continues
+    a2 = api.Batch(fields, prm)
+    a2.step(30)
+    first = [v.cpu().numpy() for v in a2.views()]
+    for v, f in zip(a2.views(), fields):
+        v.copy_(torch.from_numpy(f))
+    a2.step(30)
+    assert all(np.array_equal(x, v.cpu().numpy()) for x, v in zip(first, a2.views()))
+    a2.step(30)
+    for v, f, (h, dt, eps) in zip(a2.views(), fields, prm):
+        ref = oracle.step2d(f.astype(np.float64), h, dt, eps, 60)
+        assert D.rel_linf(v.cpu().numpy(), ref) <= 1e-5
+
+
+def test_barrier_timeout_is_reported_and_recovers(api):
+    from paper_2105_09671_amd import _lib as L
+    fields, prm = _small_batch(42)
+    b = api.Batch([f.astype(np.float32) for f in fields], prm)
+    L.lib().ac_batched_set_spin_limit(0)      # host-forced: every barrier wait gives up at once
+    try:
+        b.step(40, tune=dict(tb_depth=2, tile_x=64, tile_y=32))
+        with pytest.raises(L.AcError) as ei:
+            api.check()
+        assert "timed out" in str(ei.value)
+    finally:
+        L.lib().ac_batched_set_spin_limit(-1)
+    api.check()                               # flag cleared
+    b2 = api.Batch([f.astype(np.float32) for f in fields], prm)
+    b2.step(40, tune=dict(tb_depth=2, tile_x=64, tile_y=32))
+    api.check()
+    for v, f, (h, dt, eps) in zip(b2.views(), fields, prm):
+        ref = oracle.step2d(f.astype(np.float64), h, dt, eps, 40)
+        assert D.rel_linf(v.cpu().numpy(), ref) <= 1e-5
+
+
+def test_autotune_batched_and_2d(api, tmp_path):
+    fields, prm = _small_batch(43)
+    fields = [f.astype(np.float32) for f in fields]
+    b = api.Batch(fields, prm)
+    best = b.autotune(probe_steps=40)
+    assert 1 <= best["tb_depth"] <= 8
+    ref = api.Batch(fields, prm)
+    ref.step(24, tune=dict(tb_depth=1, tile_x=64, tile_y=32))
+    b.step(24)                                 # uses the tuned table entry
+    for x, y in zip(b.views(), ref.views()):
+        assert torch.equal(x, y)
+    t2 = api.autotune2d(700, 500, probe_steps=40)
+    h, dt, eps = 1 / 700, params.dt_of(1 / 700), params.eps_m(1 / 700, 4)
+    f = inputs.random_field((500, 700), 44).astype(np.float32)
+    x = torch.from_numpy(f).cuda()
+    api.step2d(x, h, dt, eps, 21)              # tuned entry
+    y = torch.from_numpy(f).cuda()
+    api.step2d(y, h, dt, eps, 21, tune=dict(tb_depth=1, tile_x=-1))
+    assert torch.equal(x, y), t2
+    path = str(tmp_path / "tune.json")
+    api.tune_save(path)
+    api.tune_clear()
+    api.tune_load(path)
+    api.tune_clear()
+
+
+# FP32 on a random start: phase separation amplifies perturbations, so the bar
+# for such an instance is max(1e-5, SENS_FACTOR * sens), where sens is how far
+# the FP64 oracle itself moves when phi0 is moved by one FP32 ulp.  An FP32 run
+# rounds at every step, not only at t = 0, hence the factor.
+SENS_FACTOR = 10.0
+
+
+def _ulp_sensitivity(f32, prm, nsteps, ref, seed, threads):
+    up = inputs.uniform01(99, seed, f32.size).reshape(f32.shape) < 0.5
+    pert = np.nextafter(f32, np.where(up, np.float32(np.inf), np.float32(-np.inf)))
+    refp = oracle.step2d(pert.astype(np.float64), prm[0], prm[1], prm[2], nsteps, threads)
+    return D.rel_linf(refp, ref)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_batch512_sampled_against_oracle(api, dtype):
+    """The full 512-instance workload, 5000 steps in one persistent launch; every
+    8th instance (64 of them, all side lengths) is compared with the FP64 oracle:
+    FP64 to 1e-12, FP32 to 1e-5 (random starts: the conditioning bar above)."""
+    insts = workloads.batch_instances(512)
+    fields = [g.initial() for g in insts]
+    if dtype == torch.float32:
+        fields = [f.astype(np.float32) for f in fields]
+    prm = [(g.h, g.dt, g.eps) for g in insts]
+    b = api.Batch(fields, prm, dtype=dtype)
+    info = b.step(5000)
+    api.check()
+    views = b.views()
+    threads = min(32, oracle.cpus_available())
+    sample = list(range(0, 512, 8))
+    refs = oracle.step_batched2d([fields[i].astype(np.float64) for i in sample],
+                                 [prm[i][0] for i in sample], [prm[i][1] for i in sample],
+                                 [prm[i][2] for i in sample], 5000, threads)
+    worst = 0.0
+    for k, i in enumerate(sample):
+        err = D.rel_linf(views[i].cpu().numpy(), refs[k])
+        worst = max(worst, err)
+        if dtype == torch.float64:
+            assert err <= 1e-12, "instance %d rel Linf %g" % (i, err)
+        elif err > 1e-5:
+            assert insts[i].kind == "random", "instance %d (%s) rel Linf %g" % (i, insts[i].kind, err)
+            sens = _ulp_sensitivity(fields[i], prm[i], 5000, refs[k], i, threads)
+            print("instance %d: rel Linf %.3g, 1-ulp sensitivity %.3g" % (i, err, sens))
+            assert err <= SENS_FACTOR * sens, "instance %d rel Linf %g > %g x %g" % (
+                i, err, SENS_FACTOR, sens)
+    print("batch512 %s: launch %s, worst sampled rel Linf %.3g" % (dtype, info, worst))
