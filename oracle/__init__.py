@@ -24,6 +24,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "_ac_oracle.so")
 _SRC = os.path.join(_HERE, "ac_oracle.c")
+_SRCS = [_SRC, os.path.join(_HERE, "sur_oracle.c")]
 CFLAGS = ["-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
           "-std=c11", "-Wall", "-Wextra"]
 
@@ -32,9 +33,10 @@ _lib = None
 
 def build(force: bool = False) -> str:
     """Compile ac_oracle.c with gcc into oracle/_ac_oracle.so."""
-    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+    stale = not os.path.exists(_SO) or any(os.path.getmtime(_SO) < os.path.getmtime(s) for s in _SRCS)
+    if force or stale:
         tmp = _SO + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", *CFLAGS, _SRC, "-o", tmp])
+        subprocess.check_call(["gcc", *CFLAGS, *_SRCS, "-o", tmp, "-lm"])
         os.replace(tmp, _SO)
     return _SO
 
@@ -56,6 +58,18 @@ def _load():
         lib.ora_step_batched2d.restype = i32
         lib.ora_cpus_available.argtypes = []
         lib.ora_cpus_available.restype = i32
+        lib.sur_num_params.argtypes = [i32, i32, i32]
+        lib.sur_num_params.restype = i64
+        lib.sur_forward.argtypes = [pd, i32, i32, i32, pd, i32, i32, i32, pd]
+        lib.sur_forward.restype = i32
+        lib.sur_loss_grad.argtypes = [pd, i32, i32, i32, pd, pd, i32, i32, i32, pd, pd]
+        lib.sur_loss_grad.restype = i32
+        lib.sur_conv_fwd.argtypes = [pd, i32, i32, i32, i32, pd, pd, i32, i32, pd]
+        lib.sur_conv_fwd.restype = None
+        lib.sur_pool_fwd.argtypes = [pd, i32, i32, i32, i32, pd]
+        lib.sur_pool_fwd.restype = None
+        lib.sur_up_fwd.argtypes = [pd, i32, i32, i32, i32, pd]
+        lib.sur_up_fwd.restype = None
         _lib = lib
     return _lib
 
