@@ -188,6 +188,43 @@ ac_status ac_tune_load(const char *path);
 void ac_tune_clear(void);
 int32_t ac_tune_count(void);
 
+/* --------------------------------------------------- learned surrogate ----
+ * A small conv network that advances phi by K explicit steps per call
+ * (phi -> phi + U(phi)); not in the paper.  Architecture (all 3x3 convs are
+ * replicate padded, matching the zero-Neumann boundary):
+ *   e1a = relu conv3(phi; 1->32)   e1 = relu conv3(e1a; 32->32)     H x W
+ *   e2a = relu conv3(pool e1; 32->64)   e2 = relu conv3(e2a; 64->64)  H/2
+ *   bt  = relu conv3(pool e2; 64->128)                               H/4
+ *   u2  = conv1(up bt; 128->64)   d2 = relu conv3(cat(u2, e2); 128->64)
+ *   u1  = conv1(up d2; 64->32)    d1 = relu conv3(cat(u1, e1); 64->32)
+ *   out = phi + conv1(d1; 32->1)
+ * pool = 2x2 average, up = 2x nearest.  241,473 parameters, flat in that
+ * layer order: weights [Cout][ky][kx][Cin] (1x1: [Cout][Cin]), then bias.
+ * Kernels: BF16 operands on v_mfma_f32_16x16x32_bf16 with FP32 accumulation;
+ * FP32 master weights, FP32 Adam.  The handle owns all device state; inputs
+ * and outputs are device pointers to [batch][hw][hw] FP32 fields.  Calls are
+ * asynchronous on the handle's stream. */
+typedef struct ac_sur ac_sur;
+int64_t ac_sur_num_params(void);
+/* batch_max >= 1; hw >= 8 and a multiple of 4.  Weights start at zero. */
+ac_status ac_sur_create(ac_sur **out, int32_t batch_max, int32_t hw, void *stream);
+void ac_sur_destroy(ac_sur *s);
+ac_status ac_sur_set_stream(ac_sur *s, void *stream);
+/* host FP32 arrays of ac_sur_num_params() values; set also resets Adam state */
+ac_status ac_sur_set_weights(ac_sur *s, const float *host, int64_t n);
+ac_status ac_sur_get_weights(ac_sur *s, float *host, int64_t n);
+/* phi_out (may be NULL: kept internally) = phi_in + U(phi_in) */
+ac_status ac_sur_forward(ac_sur *s, const float *phi_in, float *phi_out, int32_t batch);
+/* after ac_sur_forward on the same batch: mean squared error against target;
+ * stores d loss / d out for the backward pass; loss_dev (may be NULL) receives
+ * the loss as a device float */
+ac_status ac_sur_loss(ac_sur *s, const float *target, int32_t batch, float *loss_dev);
+/* gradients of that loss with respect to every parameter */
+ac_status ac_sur_backward(ac_sur *s, int32_t batch);
+ac_status ac_sur_get_grads(ac_sur *s, float *host, int64_t n);
+/* one Adam update (bias-corrected, step t >= 1) of the FP32 master weights */
+ac_status ac_sur_adam_step(ac_sur *s, float lr, float b1, float b2, float eps_adam, int64_t t);
+
 /* Synchronise `stream` and report any pending HIP error, or a batched grid
  * barrier timeout, as AC_ERR_HIP. */
 ac_status ac_check(void *stream);

@@ -90,6 +90,18 @@ SIGNATURES = {
     "ac_tune_load": ([ctypes.c_char_p], _i32),
     "ac_tune_clear": ([], None),
     "ac_tune_count": ([], _i32),
+    "ac_sur_num_params": ([], _i64),
+    "ac_sur_create": ([ctypes.POINTER(_vp), _i32, _i32, _vp], _i32),
+    "ac_sur_destroy": ([_vp], None),
+    "ac_sur_set_stream": ([_vp, _vp], _i32),
+    "ac_sur_set_weights": ([_vp, ctypes.POINTER(ctypes.c_float), _i64], _i32),
+    "ac_sur_get_weights": ([_vp, ctypes.POINTER(ctypes.c_float), _i64], _i32),
+    "ac_sur_forward": ([_vp, _vp, _vp, _i32], _i32),
+    "ac_sur_loss": ([_vp, _vp, _i32, _vp], _i32),
+    "ac_sur_backward": ([_vp, _i32], _i32),
+    "ac_sur_get_grads": ([_vp, ctypes.POINTER(ctypes.c_float), _i64], _i32),
+    "ac_sur_adam_step": ([_vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                          _i64], _i32),
     "ac_check": ([_vp], _i32),
     "ac_status_string": ([_i32], ctypes.c_char_p),
     "ac_last_error": ([], ctypes.c_char_p),

@@ -1,0 +1,78 @@
+// BF16 MFMA building blocks of the surrogate network (gfx950).
+//
+// Activations are NHWC bf16.  A tensor view is (ptr, channel stride Cs,
+// channel offset Co): element (n, y, x, c) lives at ((n*H + y)*W + x)*Cs + Co + c,
+// so a concatenation is two views into one buffer and costs no copy.
+//
+// Every convolution is an implicit GEMM on a 64 x 64 output tile with K
+// stepped by 32.  A workgroup of 256 threads (4 waves, 2 x 2) stages one
+// 64 x 32 A tile and one 64 x 32 B tile in LDS per K step (both stored with
+// the K index contiguous), then each wave issues 2 x 2
+// v_mfma_f32_16x16x32_bf16 with FP32 accumulation.  Operand layout of that
+// instruction (wave64): lane l supplies A[l % 16][8*(l/16) .. +7] and
+// B[8*(l/16) .. +7][l % 16]; it receives D[4*(l/16) + r][l % 16], r = 0..3.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace ac {
+namespace sur {
+
+typedef unsigned short bf16_t;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int BM = 64, BN = 64, BK = 32, LP = BK + 8;   // LDS pitch (bf16 units)
+
+// float -> bf16, round to nearest even (NaN stays NaN)
+__host__ __device__ inline bf16_t f2bf(float f) {
+    unsigned u;
+    __builtin_memcpy(&u, &f, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (bf16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (bf16_t)(u >> 16);
+}
+__host__ __device__ inline float bf2f(bf16_t h) {
+    unsigned u = (unsigned)h << 16;
+    float f;
+    __builtin_memcpy(&f, &u, 4);
+    return f;
+}
+
+struct View {
+    bf16_t *p;
+    int Cs, Co;
+};
+
+__device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// One K step of the 2 x 2 MFMA tile of this wave from the staged LDS tiles.
+__device__ inline void mma_step(const bf16_t *As, const bf16_t *Bs, floatx4 acc[2][2]) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int wm = w & 1, wn = w >> 1;
+    const int r = lane & 15, kc = (lane >> 4) * 8;
+    bf16x8 a[2], b[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        a[i] = *reinterpret_cast<const bf16x8 *>(As + (wm * 32 + i * 16 + r) * LP + kc);
+        b[i] = *reinterpret_cast<const bf16x8 *>(Bs + (wn * 32 + i * 16 + r) * LP + kc);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+}
+
+// (row, col) of accumulator element r of tile (i, j) for this lane, relative
+// to the workgroup's 64 x 64 output tile.
+__device__ inline void acc_coord(int i, int j, int r, int *row, int *col) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    *row = (w & 1) * 32 + i * 16 + (lane >> 4) * 4 + r;
+    *col = (w >> 1) * 32 + j * 16 + (lane & 15);
+}
+
+}  // namespace sur
+}  // namespace ac
