@@ -148,7 +148,7 @@ typedef struct {
  * the batch may overlap.  On first use of an instance table the library
  * uploads it, sizes the persistent grid to what the device holds at once,
  * captures [barrier reset, persistent kernel] into a hipGraph on a private
- * stream and caches it (the 4 most recent tables are kept); calls with the
+ * stream and caches it (the 64 most recent tables are kept); calls with the
  * same table (same pointers, sizes and parameters) and nsteps replay the
  * graph on `stream`.  The launch shape comes from `tune`, else from the
  * autotuner's table (ac_autotune_batched), else the 2D defaults.  Grid
@@ -224,6 +224,20 @@ ac_status ac_sur_backward(ac_sur *s, int32_t batch);
 ac_status ac_sur_get_grads(ac_sur *s, float *host, int64_t n);
 /* one Adam update (bias-corrected, step t >= 1) of the FP32 master weights */
 ac_status ac_sur_adam_step(ac_sur *s, float lr, float b1, float b2, float eps_adam, int64_t t);
+
+/* ---------------------------------------------------------------- judge ----
+ * Per grid of a batch of 2D FP32 fields a (candidate) and b (reference), both
+ * [batch][ny][nx] on the device: iface_err[n] = Hausdorff distance between the
+ * zero-crossing sets of a[n] and b[n] (crossings located by linear
+ * interpolation on the edges between adjacent cell centres; physical units via
+ * h), searched within +-window cells, exact when <= (window - 1) h and +inf
+ * beyond; 0 when neither field has a crossing, +inf when only one has.
+ * l2_err[n] = root mean square of a[n] - b[n].  workspace: device scratch of
+ * ac_judge_workspace_bytes(batch) bytes owned by the caller.  1 <= window <= 16. */
+ac_status ac_judge_2d(const float *a, const float *b, int32_t batch, int32_t nx, int32_t ny,
+                      double h, int32_t window, float *iface_err, float *l2_err,
+                      void *workspace, void *stream);
+int64_t ac_judge_workspace_bytes(int32_t batch);
 
 /* Synchronise `stream` and report any pending HIP error, or a batched grid
  * barrier timeout, as AC_ERR_HIP. */

@@ -102,6 +102,8 @@ SIGNATURES = {
     "ac_sur_get_grads": ([_vp, ctypes.POINTER(ctypes.c_float), _i64], _i32),
     "ac_sur_adam_step": ([_vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                           _i64], _i32),
+    "ac_judge_2d": ([_vp, _vp, _i32, _i32, _i32, _dbl, _i32, _vp, _vp, _vp, _vp], _i32),
+    "ac_judge_workspace_bytes": ([_i32], _i64),
     "ac_check": ([_vp], _i32),
     "ac_status_string": ([_i32], ctypes.c_char_p),
     "ac_last_error": ([], ctypes.c_char_p),

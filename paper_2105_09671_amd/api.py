@@ -189,3 +189,19 @@ def tune_load(path: str) -> None:
 
 def tune_clear() -> None:
     L.lib().ac_tune_clear()
+
+
+def judge2d(a: torch.Tensor, b: torch.Tensor, h: float, window: int = 3, stream=None):
+    """(interface error, L2 error) per grid for [batch, ny, nx] FP32 device fields."""
+    if a.shape != b.shape or a.dim() != 3 or a.dtype != torch.float32 or b.dtype != torch.float32:
+        raise ValueError("two [batch, ny, nx] float32 tensors of one shape expected")
+    if not (a.is_contiguous() and b.is_contiguous()):
+        raise ValueError("contiguous tensors expected")
+    n, ny, nx = a.shape
+    iface = torch.empty(n, dtype=torch.float32, device=a.device)
+    l2 = torch.empty(n, dtype=torch.float32, device=a.device)
+    ws = torch.empty(int(L.lib().ac_judge_workspace_bytes(n)), dtype=torch.uint8, device=a.device)
+    L.check(L.lib().ac_judge_2d(a.data_ptr(), b.data_ptr(), n, nx, ny, float(h), int(window),
+                                iface.data_ptr(), l2.data_ptr(), ws.data_ptr(), _stream(stream)),
+            "ac_judge_2d")
+    return iface, l2

@@ -142,7 +142,7 @@ struct Plan {
 
 std::mutex g_mu;
 std::list<Plan> g_plans;          // most recently used first
-constexpr size_t kMaxPlans = 4;
+constexpr size_t kMaxPlans = 64;
 hipStream_t g_capture_stream[64];
 
 bool same_inst(const ac_instance2d &a, const ac_instance2d &b) {

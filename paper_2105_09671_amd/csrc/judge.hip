@@ -1,0 +1,138 @@
+// Judge of a predicted field against a reference field: interface position
+// and L2 error, per grid of a batch.
+//
+// Interface: the zero level set, sampled as the points where phi changes sign
+// along an edge between two adjacent cell centres, located by linear
+// interpolation.  The interface error is the Hausdorff distance between the
+// two point sets (physical units, cell size h).  Each crossing searches the
+// other field's crossings on the edges of the cells within `window` cells of
+// its own; with no partner there the distance is reported as +inf.  Any
+// partner outside the window is at least (window - 1) h away, so the value is
+// exact whenever it is <= (window - 1) h -- enough for a decision at h.
+// If neither field has a crossing the distance is 0; if only one has, inf.
+//
+// L2: root mean square of (a - b) over the grid.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "ac_internal.h"
+
+namespace ac {
+
+namespace {
+
+// Crossing on the edge from cell (i, j) to (i + di, j + dj); returns false if
+// the sign does not change.  Coordinates in cell units (cell (i, j) centre at
+// (i, j)).
+__device__ inline bool crossing(const float *f, int nx, int ny, int i, int j, int di, int dj,
+                                float *px, float *py) {
+    const int i2 = i + di, j2 = j + dj;
+    if (i2 >= nx || j2 >= ny) return false;
+    const float a = f[(size_t)j * nx + i], b = f[(size_t)j2 * nx + i2];
+    if ((a > 0.f) == (b > 0.f)) return false;
+    const float t = a / (a - b);
+    *px = i + di * t;
+    *py = j + dj * t;
+    return true;
+}
+
+// min distance from (px, py) to the crossings of g in the window around cell (i, j)
+__device__ inline float nearest(const float *g, int nx, int ny, int i, int j, int w, float px,
+                                float py) {
+    float best = INFINITY;
+    for (int jj = max(j - w, 0); jj <= min(j + w, ny - 1); ++jj)
+        for (int ii = max(i - w, 0); ii <= min(i + w, nx - 1); ++ii)
+            for (int e = 0; e < 2; ++e) {
+                float qx, qy;
+                if (crossing(g, nx, ny, ii, jj, e == 0, e == 1, &qx, &qy)) {
+                    const float d = sqrtf((qx - px) * (qx - px) + (qy - py) * (qy - py));
+                    best = fminf(best, d);
+                }
+            }
+    return best;
+}
+
+__global__ void judge_kernel(const float *__restrict__ a, const float *__restrict__ b, int nx,
+                             int ny, int w, unsigned *dist_bits, float *sq, int *count)
+{
+    const int n = blockIdx.y;
+    const size_t cells = (size_t)nx * ny;
+    const float *fa = a + n * cells, *fb = b + n * cells;
+    float local = 0.f, ssq = 0.f;
+    int cnt = 0;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < (int)cells; c += gridDim.x * blockDim.x) {
+        const int i = c % nx, j = c / nx;
+        const float d = fa[c] - fb[c];
+        ssq += d * d;
+        for (int e = 0; e < 2; ++e) {
+            float px, py;
+            if (crossing(fa, nx, ny, i, j, e == 0, e == 1, &px, &py)) {
+                local = fmaxf(local, nearest(fb, nx, ny, i, j, w, px, py));
+                cnt |= 1;
+            }
+            if (crossing(fb, nx, ny, i, j, e == 0, e == 1, &px, &py)) {
+                local = fmaxf(local, nearest(fa, nx, ny, i, j, w, px, py));
+                cnt |= 2;
+            }
+        }
+    }
+    // non-negative floats order like their bit patterns (+inf is the largest)
+    if (local > 0.f) atomicMax(dist_bits + n, __float_as_uint(local));
+    if (cnt) atomicOr(count + n, cnt);
+    atomicAdd(sq + n, ssq);
+}
+
+__global__ void judge_finish_kernel(const unsigned *dist_bits, const float *sq, const int *count,
+                                    int batch, size_t cells, float h, float *iface, float *l2)
+{
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= batch) return;
+    float d = __uint_as_float(dist_bits[n]);
+    if (count[n] == 0) d = 0.f;                                    // no interface in either
+    else if (count[n] != 3) d = INFINITY;                          // an interface in one only
+    iface[n] = d * h;
+    l2[n] = sqrtf(sq[n] / (float)cells);
+}
+
+__global__ void judge_zero_kernel(unsigned *dist_bits, float *sq, int *count, int batch)
+{
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n < batch) { dist_bits[n] = 0u; sq[n] = 0.f; count[n] = 0; }
+}
+
+}  // namespace
+
+}  // namespace ac
+
+using namespace ac;
+
+extern "C" {
+
+ac_status ac_judge_2d(const float *a, const float *b, int32_t batch, int32_t nx, int32_t ny,
+                      double h, int32_t window, float *iface_err, float *l2_err, void *workspace,
+                      void *stream)
+{
+    g_err.clear();
+    if (!a || !b || !iface_err || !l2_err || !workspace)
+        return fail(AC_ERR_INVALID_ARG, "null pointer argument");
+    if (batch < 1 || nx < 1 || ny < 1 || window < 1 || window > 16 || !(h > 0) || !std::isfinite(h))
+        return fail(AC_ERR_INVALID_ARG, "bad judge sizes (batch %d, %d x %d, window %d)", batch, nx, ny, window);
+    if (batch > 65535) return fail(AC_ERR_UNSUPPORTED, "batch above 65535");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    unsigned *dist = static_cast<unsigned *>(workspace);
+    float *sq = reinterpret_cast<float *>(dist + batch);
+    int *cnt = reinterpret_cast<int *>(sq + batch);
+    hipLaunchKernelGGL(judge_zero_kernel, dim3((batch + 255) / 256), dim3(256), 0, st, dist, sq, cnt, batch);
+    const long long cells = (long long)nx * ny;
+    const unsigned gx = (unsigned)std::min<long long>((cells + 255) / 256, 256);
+    hipLaunchKernelGGL(judge_kernel, dim3(gx, batch), dim3(256), 0, st, a, b, nx, ny, (int)window, dist, sq, cnt);
+    hipLaunchKernelGGL(judge_finish_kernel, dim3((batch + 255) / 256), dim3(256), 0, st, dist, sq, cnt,
+                       batch, (size_t)cells, (float)h, iface_err, l2_err);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? AC_OK : hip_fail(e, "judge launch");
+}
+
+int64_t ac_judge_workspace_bytes(int32_t batch) { return (int64_t)batch * 12; }
+
+}  // extern "C"
