@@ -7,21 +7,20 @@
 // region shrunk by s cells on every side that is not a domain edge is still
 // exact, so each sub-step computes only that region.
 //
-// Zero-Neumann boundary (section 2): the LDS tile has a one-cell frame.  Where
-// the tile touches a domain edge the frame holds the ghost layer, i.e. a copy
-// of the adjacent interior cell, exactly as in the paper's extended grid.  The
-// ghosts are written when the tile is loaded and again by every edge cell each
-// time it is updated, so the stencil reads its four neighbours from LDS with no
-// boundary test at all.  A tile whose loaded region reaches a domain edge does
-// not shrink on that side.
+// Zero-Neumann boundary (section 2): a neighbour that lies outside the domain
+// is replaced by the cell itself, at every sub-step.  The test costs nothing
+// on interior tiles: left/right edges are handled under a block-uniform
+// branch (only tiles touching the domain's x edges take it) and top/bottom
+// under a wave-uniform one (only the chunk holding row 0 or row ny-1).  A tile
+// whose loaded region reaches a domain edge does not shrink on that side.
 //
 // When the tile covers the whole grid (halo = 0) one workgroup runs every time
 // step of the call in a single launch.
 //
 // Thread layout: 64 lanes (one wave) along x, blockDim.x/64 waves along y.
-// A sub-step deals chunks of RCH rows round-robin to the waves; in a chunk each
-// lane issues all 3*RCH+2 LDS reads of its column before any arithmetic, and
-// the 64 lanes of a wave touch 64 consecutive LDS words (no bank conflicts).
+// A sub-step deals chunks of rows (16 in FP32, 8 in FP64) round-robin to the
+// waves; in a chunk each lane issues all LDS reads of its column before any
+// arithmetic, and the 64 lanes of a wave touch 64 consecutive LDS words.
 #include "tile2d.h"
 
 namespace ac {
@@ -37,7 +36,7 @@ tile2d_kernel(const T *src, T *dst, int nx, int ny, T alpha, T r,
 }
 
 size_t tile2d_lds_bytes(int LX, int LY, size_t elem) {
-    return 2 * (size_t)lds_pitch(LX) * lds_rows(LY) * elem;
+    return 2 * (size_t)lds_pitch(LX) * lds_rows(LY, elem) * elem;
 }
 
 template <typename T, int LXC>
