@@ -161,6 +161,14 @@ ac_status ac_step_batched_tuned(const ac_instance2d *inst, int32_t n_inst, int64
                                 int32_t dtype, const ac_tune *tune, ac_batch_info *info,
                                 void *stream);
 
+/* As ac_step_batched_tuned, stepping only the instances i with active[i] != 0;
+ * the others are left untouched (phi and work).  active is a device array of
+ * n_inst int32 read by the kernel at run time, so its contents may change
+ * between calls without a new plan (the plan is keyed by the pointer). */
+ac_status ac_step_batched_masked(const ac_instance2d *inst, int32_t n_inst, int64_t nsteps,
+                                 int32_t dtype, const ac_tune *tune, const int32_t *active,
+                                 ac_batch_info *info, void *stream);
+
 /* Free every cached batched plan (synchronises the device). */
 ac_status ac_batched_release(void);
 

@@ -80,6 +80,8 @@ SIGNATURES = {
     "ac_step_batched": ([ctypes.POINTER(AcInstance2D), _i32, _i64, _i32, _vp], _i32),
     "ac_step_batched_tuned": ([ctypes.POINTER(AcInstance2D), _i32, _i64, _i32,
                                ctypes.POINTER(AcTune), ctypes.POINTER(AcBatchInfo), _vp], _i32),
+    "ac_step_batched_masked": ([ctypes.POINTER(AcInstance2D), _i32, _i64, _i32,
+                                ctypes.POINTER(AcTune), _vp, ctypes.POINTER(AcBatchInfo), _vp], _i32),
     "ac_batched_release": ([], _i32),
     "ac_batched_set_spin_limit": ([_i64], None),
     "ac_autotune_2d": ([_i32, _i32, _i32, _i64, ctypes.POINTER(AcTune), _vp], _i32),

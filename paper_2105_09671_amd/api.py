@@ -154,6 +154,17 @@ class Batch:
         L.check(st, "ac_step_batched")
         return info.as_dict()
 
+    def step_masked(self, nsteps: int, active: torch.Tensor, tune=None, stream=None) -> dict:
+        """Step only the grids i with active[i] != 0 (int32 device tensor)."""
+        if active.dtype != torch.int32 or not active.is_cuda or active.numel() != len(self.shapes):
+            raise ValueError("int32 device tensor with one entry per grid expected")
+        info = L.AcBatchInfo()
+        st = L.lib().ac_step_batched_masked(self._arr, len(self.shapes), int(nsteps),
+                                            _dtype_code(self.phi), _tune(tune), active.data_ptr(),
+                                            ctypes.byref(info), _stream(stream))
+        L.check(st, "ac_step_batched_masked")
+        return info.as_dict()
+
     def autotune(self, probe_steps: int = 200, stream=None) -> dict:
         best = L.AcTune()
         L.check(L.lib().ac_autotune_batched(self._arr, len(self.shapes), _dtype_code(self.phi),

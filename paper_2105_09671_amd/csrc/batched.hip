@@ -82,7 +82,7 @@ template <typename T, int LXC>
 __global__ void __launch_bounds__(256)
 batched_kernel(const BatchInst *__restrict__ inst, const int4 *__restrict__ items, int n_items,
                int LX, int LY, int K, int nblocks, int base, int rem, int copy_back,
-               unsigned *bar, int *err, long long spin_limit)
+               const int *__restrict__ active, unsigned *bar, int *err, long long spin_limit)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int G = gridDim.x;                    // a multiple of 8
@@ -94,6 +94,7 @@ batched_kernel(const BatchInst *__restrict__ inst, const int4 *__restrict__ item
         const int k = base + (b < rem ? 1 : 0);
         for (int i = lo + j; i < hi; i += per) {
             const int4 it = items[i];
+            if (active && !active[it.x]) continue;      // same item for the whole workgroup
             const BatchInst I = inst[it.x];
             const T *src = static_cast<const T *>((b & 1) ? I.work : I.phi);
             T *dst = static_cast<T *>((b & 1) ? I.phi : I.work);
@@ -109,6 +110,7 @@ batched_kernel(const BatchInst *__restrict__ inst, const int4 *__restrict__ item
     if (copy_back) {   // odd number of single-step blocks: the result sits in work
         for (int i = lo + j; i < hi; i += per) {
             const int4 it = items[i];
+            if (active && !active[it.x]) continue;
             const BatchInst I = inst[it.x];
             copy_tile<T>(static_cast<const T *>(I.work), static_cast<T *>(I.phi), I.nx, I.ny,
                          LX - 2 * K, LY - 2 * K, it.y, it.z);
@@ -128,6 +130,7 @@ struct Plan {
     int64_t nsteps;
     int32_t dtype;
     ac_tune tune;
+    const int *active;
     int device;
     // device state
     BatchInst *d_inst = nullptr;
@@ -151,8 +154,9 @@ bool same_inst(const ac_instance2d &a, const ac_instance2d &b) {
 }
 
 bool key_equal(const Plan &p, const ac_instance2d *inst, int32_t n, int64_t nsteps,
-               int32_t dtype, const ac_tune &t, int dev) {
-    if (p.device != dev || p.nsteps != nsteps || p.dtype != dtype || (int32_t)p.inst.size() != n)
+               int32_t dtype, const ac_tune &t, const int *active, int dev) {
+    if (p.device != dev || p.nsteps != nsteps || p.dtype != dtype || (int32_t)p.inst.size() != n ||
+        p.active != active)
         return false;
     if (std::memcmp(&p.tune, &t, sizeof t) != 0) return false;
     for (int32_t i = 0; i < n; ++i)
@@ -278,9 +282,10 @@ ac_status build_plan(Plan &p, const ac_instance2d *inst, int32_t n, int64_t nste
     const long long spin = g_spin_limit;
     const int cb = c.copy_back ? 1 : 0;
     const int base = (int)c.base, rem = (int)c.rem, ni = p.n_items;
+    const int *act = p.active;
     void *args[] = {&p.d_inst, &p.d_items, (void *)&ni, (void *)&LX, (void *)&LY, (void *)&K,
-                    (void *)&nblocks, (void *)&base, (void *)&rem, (void *)&cb, &p.d_bar,
-                    &p.d_err, (void *)&spin};
+                    (void *)&nblocks, (void *)&base, (void *)&rem, (void *)&cb, (void *)&act,
+                    &p.d_bar, &p.d_err, (void *)&spin};
     hipError_t le = hipLaunchKernel(kern, dim3(grid), dim3(256), args, lds, cs);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(cs, &g);
@@ -333,9 +338,9 @@ using namespace ac;
 
 extern "C" {
 
-ac_status ac_step_batched_tuned(const ac_instance2d *inst, int32_t n_inst, int64_t nsteps,
-                                int32_t dtype, const ac_tune *tune, ac_batch_info *info,
-                                void *stream) {
+ac_status ac_step_batched_masked(const ac_instance2d *inst, int32_t n_inst, int64_t nsteps,
+                                 int32_t dtype, const ac_tune *tune, const int32_t *active,
+                                 ac_batch_info *info, void *stream) {
     g_err.clear();
     std::vector<double> alpha, r;
     ac_status s = validate_batch(inst, n_inst, nsteps, dtype, &alpha, &r);
@@ -358,13 +363,14 @@ ac_status ac_step_batched_tuned(const ac_instance2d *inst, int32_t n_inst, int64
     std::lock_guard<std::mutex> lock(g_mu);
     auto it = g_plans.begin();
     for (; it != g_plans.end(); ++it)
-        if (key_equal(*it, inst, n_inst, nsteps, dtype, t, device)) break;
+        if (key_equal(*it, inst, n_inst, nsteps, dtype, t, active, device)) break;
     if (it == g_plans.end()) {
         Plan p;
         p.inst.assign(inst, inst + n_inst);
         p.nsteps = nsteps;
         p.dtype = dtype;
         p.tune = t;
+        p.active = active;
         p.device = device;
         if ((s = build_plan(p, inst, n_inst, nsteps, dtype, t, alpha, r, dev)) != AC_OK) return s;
         g_plans.push_front(std::move(p));
@@ -382,6 +388,12 @@ ac_status ac_step_batched_tuned(const ac_instance2d *inst, int32_t n_inst, int64
     if ((e = hipGraphLaunch(it->exec, reinterpret_cast<hipStream_t>(stream))) != hipSuccess)
         return hip_fail(e, "batched graph launch");
     return AC_OK;
+}
+
+ac_status ac_step_batched_tuned(const ac_instance2d *inst, int32_t n_inst, int64_t nsteps,
+                                int32_t dtype, const ac_tune *tune, ac_batch_info *info,
+                                void *stream) {
+    return ac_step_batched_masked(inst, n_inst, nsteps, dtype, tune, nullptr, info, stream);
 }
 
 ac_status ac_step_batched(const ac_instance2d *inst, int32_t n_inst, int64_t nsteps,

@@ -4,11 +4,11 @@
 // channel offset Co): element (n, y, x, c) lives at ((n*H + y)*W + x)*Cs + Co + c,
 // so a concatenation is two views into one buffer and costs no copy.
 //
-// Every convolution is an implicit GEMM on a 64 x 64 output tile with K
-// stepped by 32.  A workgroup of 256 threads (4 waves, 2 x 2) stages one
-// 64 x 32 A tile and one 64 x 32 B tile in LDS per K step (both stored with
-// the K index contiguous), then each wave issues 2 x 2
-// v_mfma_f32_16x16x32_bf16 with FP32 accumulation.  Operand layout of that
+// Every convolution is an implicit GEMM on a (32 WM) x (32 WN) output tile
+// with K stepped by 32.  A workgroup of 256 threads (WM x WN = 4 waves) stages
+// one A tile and one B tile in LDS per K step (both stored with the K index
+// contiguous), then each wave issues 2 x 2 v_mfma_f32_16x16x32_bf16 with FP32
+// accumulation on its 32 x 32 block.  Operand layout of that
 // instruction (wave64): lane l supplies A[l % 16][8*(l/16) .. +7] and
 // B[8*(l/16) .. +7][l % 16]; it receives D[4*(l/16) + r][l % 16], r = 0..3.
 #pragma once
@@ -48,10 +48,12 @@ struct View {
 
 __device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
-// One K step of the 2 x 2 MFMA tile of this wave from the staged LDS tiles.
-__device__ inline void mma_step(const bf16_t *As, const bf16_t *Bs, floatx4 acc[2][2]) {
+// Generalised tile: WM x WN waves (WM * WN = 4), each owning a 32 x 32 block
+// (2 x 2 MFMA tiles); the workgroup tile is (32 WM) x (32 WN).
+template <int WM, int WN>
+__device__ inline void mma_step_t(const bf16_t *As, const bf16_t *Bs, floatx4 acc[2][2]) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int wm = w & 1, wn = w >> 1;
+    const int wm = w % WM, wn = w / WM;
     const int r = lane & 15, kc = (lane >> 4) * 8;
     bf16x8 a[2], b[2];
 #pragma unroll
@@ -66,12 +68,11 @@ __device__ inline void mma_step(const bf16_t *As, const bf16_t *Bs, floatx4 acc[
             acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
 }
 
-// (row, col) of accumulator element r of tile (i, j) for this lane, relative
-// to the workgroup's 64 x 64 output tile.
-__device__ inline void acc_coord(int i, int j, int r, int *row, int *col) {
+template <int WM, int WN>
+__device__ inline void acc_coord_t(int i, int j, int r, int *row, int *col) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    *row = (w & 1) * 32 + i * 16 + (lane >> 4) * 4 + r;
-    *col = (w >> 1) * 32 + j * 16 + (lane & 15);
+    *row = (w % WM) * 32 + i * 16 + (lane >> 4) * 4 + r;
+    *col = (w / WM) * 32 + j * 16 + (lane & 15);
 }
 
 }  // namespace sur

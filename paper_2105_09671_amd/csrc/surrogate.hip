@@ -36,53 +36,75 @@ namespace sur {
 // Y = act(conv(X) + bias).  GEMM rows = output pixels, cols = output
 // channels, K = KS*KS*Cin ordered (tap, ci) like the weights [Cout][tap][Cin].
 // UP: X is at low resolution and each result goes to a 2x2 block of Y.
-template <int KS, bool UP>
+// Tile (32 WM) x (32 WN); 32-channel layers use WN = 1 so no MFMA lane idles.
+template <int KS, bool UP, int WM, int WN>
 __global__ void __launch_bounds__(256)
 conv_fwd_kernel(View X, int lgCin, int B, int H, int W, const bf16_t *__restrict__ Wk,
                 const float *__restrict__ bias, int Cout, View Y, int relu)
 {
-    __shared__ __align__(16) bf16_t As[BM * LP];
-    __shared__ __align__(16) bf16_t Bs[BN * LP];
+    constexpr int TBM = 32 * WM, TBN = 32 * WN;
+    constexpr int NA = (TBM * 4 + 255) / 256, NB = (TBN * 4 + 255) / 256;
+    __shared__ __align__(16) bf16_t As[TBM * LP];
+    __shared__ __align__(16) bf16_t Bs[TBN * LP];
     const int Cin = 1 << lgCin, K = KS * KS * Cin, M = B * H * W;
-    const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
-    const int t = threadIdx.x, r = t >> 2, kc = (t & 3) * 8;
-    const int m = m0 + r;
-    const bool mok = m < M;
-    int pn = 0, py = 0, px = 0;
-    if (mok) {
-        pn = m / (H * W);
-        const int rem = m - pn * H * W;
-        py = rem / W;
-        px = rem - py * W;
-    }
-    const int cob = n0 + r;
-    auto loadA = [&](int k0) -> uint4 {
-        const int k = k0 + kc;
-        if (!mok || k >= K) return uint4{0, 0, 0, 0};
-        const int tap = k >> lgCin, ci = k & (Cin - 1);
-        int yy = py, xx = px;
-        if (KS == 3) {
-            yy = clampi(py + tap / 3 - 1, 0, H - 1);
-            xx = clampi(px + tap % 3 - 1, 0, W - 1);
+    const int m0 = blockIdx.x * TBM, n0 = blockIdx.y * TBN;
+    const int t = threadIdx.x;
+    int arow[NA], akc[NA], pn[NA], py[NA], px[NA];
+    bool aok[NA];
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+        const int c = t + 256 * u;
+        arow[u] = c >> 2;
+        akc[u] = (c & 3) * 8;
+        const int m = m0 + arow[u];
+        aok[u] = c < TBM * 4 && m < M;
+        pn[u] = py[u] = px[u] = 0;
+        if (aok[u]) {
+            pn[u] = m / (H * W);
+            const int rem = m - pn[u] * H * W;
+            py[u] = rem / W;
+            px[u] = rem - py[u] * W;
         }
-        return *reinterpret_cast<const uint4 *>(X.p + ((size_t)(pn * H + yy) * W + xx) * X.Cs + X.Co + ci);
+    }
+    auto loadA = [&](int u, int k0) -> uint4 {
+        const int k = k0 + akc[u];
+        if (!aok[u] || k >= K) return uint4{0, 0, 0, 0};
+        const int tap = k >> lgCin, ci = k & (Cin - 1);
+        int yy = py[u], xx = px[u];
+        if (KS == 3) {
+            yy = clampi(py[u] + tap / 3 - 1, 0, H - 1);
+            xx = clampi(px[u] + tap % 3 - 1, 0, W - 1);
+        }
+        return *reinterpret_cast<const uint4 *>(X.p + ((size_t)(pn[u] * H + yy) * W + xx) * X.Cs + X.Co + ci);
     };
-    auto loadB = [&](int k0) -> uint4 {
-        const int k = k0 + kc;
-        if (cob >= Cout || k >= K) return uint4{0, 0, 0, 0};
-        return *reinterpret_cast<const uint4 *>(Wk + (size_t)cob * K + k);
+    auto loadB = [&](int u, int k0) -> uint4 {
+        const int c = t + 256 * u, co = n0 + (c >> 2), k = k0 + (c & 3) * 8;
+        if (c >= TBN * 4 || co >= Cout || k >= K) return uint4{0, 0, 0, 0};
+        return *reinterpret_cast<const uint4 *>(Wk + (size_t)co * K + k);
     };
     floatx4 acc[2][2] = {};
-    uint4 ra = loadA(0), rb = loadB(0);
+    uint4 ra[NA], rb[NB];
+#pragma unroll
+    for (int u = 0; u < NA; ++u) ra[u] = loadA(u, 0);
+#pragma unroll
+    for (int u = 0; u < NB; ++u) rb[u] = loadB(u, 0);
     for (int k0 = 0; k0 < K; k0 += BK) {
-        *reinterpret_cast<uint4 *>(As + r * LP + kc) = ra;
-        *reinterpret_cast<uint4 *>(Bs + r * LP + kc) = rb;
+#pragma unroll
+        for (int u = 0; u < NA; ++u)
+            if (t + 256 * u < TBM * 4) *reinterpret_cast<uint4 *>(As + arow[u] * LP + akc[u]) = ra[u];
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const int c = t + 256 * u;
+            if (c < TBN * 4) *reinterpret_cast<uint4 *>(Bs + (c >> 2) * LP + (c & 3) * 8) = rb[u];
+        }
         __syncthreads();
         if (k0 + BK < K) {
-            ra = loadA(k0 + BK);
-            rb = loadB(k0 + BK);
+#pragma unroll
+            for (int u = 0; u < NA; ++u) ra[u] = loadA(u, k0 + BK);
+#pragma unroll
+            for (int u = 0; u < NB; ++u) rb[u] = loadB(u, k0 + BK);
         }
-        mma_step(As, Bs, acc);
+        mma_step_t<WM, WN>(As, Bs, acc);
         __syncthreads();
     }
 #pragma unroll
@@ -92,7 +114,7 @@ conv_fwd_kernel(View X, int lgCin, int B, int H, int W, const bf16_t *__restrict
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 int row, col;
-                acc_coord(i, j, q, &row, &col);
+                acc_coord_t<WM, WN>(i, j, q, &row, &col);
                 const int mg = m0 + row, cg = n0 + col;
                 if (mg >= M || cg >= Cout) continue;
                 float v = acc[i][j][q] + bias[cg];
@@ -117,55 +139,76 @@ conv_fwd_kernel(View X, int lgCin, int B, int H, int W, const bf16_t *__restrict
 // channels, K = (tap, co) with the weights pre-transposed to [tap][Cin][Cout].
 // Epilogue: channels >= mask_c0 are multiplied by [mask > 0] (the relu of the
 // layer that produced X); accumulate adds to what dX holds.
-template <int KS>
+template <int KS, int WM, int WN>
 __global__ void __launch_bounds__(256)
 conv_dgrad_kernel(View dZ, int lgCout, int B, int H, int W, const bf16_t *__restrict__ Wt,
                   int Cin, View dX, View mask, int mask_c0, int accumulate)
 {
-    __shared__ __align__(16) bf16_t As[BM * LP];
-    __shared__ __align__(16) bf16_t Bs[BN * LP];
+    constexpr int TBM = 32 * WM, TBN = 32 * WN;
+    constexpr int NA = (TBM * 4 + 255) / 256, NB = (TBN * 4 + 255) / 256;
+    __shared__ __align__(16) bf16_t As[TBM * LP];
+    __shared__ __align__(16) bf16_t Bs[TBN * LP];
     const int Cout = 1 << lgCout, K = KS * KS * Cout, M = B * H * W;
-    const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
-    const int t = threadIdx.x, r = t >> 2, kc = (t & 3) * 8;
-    const int m = m0 + r;
-    const bool mok = m < M;
-    int pn = 0, py = 0, px = 0;
-    if (mok) {
-        pn = m / (H * W);
-        const int rem = m - pn * H * W;
-        py = rem / W;
-        px = rem - py * W;
+    const int m0 = blockIdx.x * TBM, n0 = blockIdx.y * TBN;
+    const int t = threadIdx.x;
+    int arow[NA], akc[NA], pn[NA], py[NA], px[NA];
+    bool aok[NA];
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+        const int c = t + 256 * u;
+        arow[u] = c >> 2;
+        akc[u] = (c & 3) * 8;
+        const int m = m0 + arow[u];
+        aok[u] = c < TBM * 4 && m < M;
+        pn[u] = py[u] = px[u] = 0;
+        if (aok[u]) {
+            pn[u] = m / (H * W);
+            const int rem = m - pn[u] * H * W;
+            py[u] = rem / W;
+            px[u] = rem - py[u] * W;
+        }
     }
-    const int cib = n0 + r;
-    auto loadA = [&](int k0) -> uint4 {
-        const int k = k0 + kc;
-        if (!mok || k >= K) return uint4{0, 0, 0, 0};
+    auto loadA = [&](int u, int k0) -> uint4 {
+        const int k = k0 + akc[u];
+        if (!aok[u] || k >= K) return uint4{0, 0, 0, 0};
         const int tap = k >> lgCout, co = k & (Cout - 1);
-        int yy = py, xx = px;
+        int yy = py[u], xx = px[u];
         if (KS == 3) {
-            yy = py + 1 - tap / 3;
-            xx = px + 1 - tap % 3;
+            yy = py[u] + 1 - tap / 3;
+            xx = px[u] + 1 - tap % 3;
             if (yy < 0 || yy >= H || xx < 0 || xx >= W) return uint4{0, 0, 0, 0};
         }
-        return *reinterpret_cast<const uint4 *>(dZ.p + ((size_t)(pn * H + yy) * W + xx) * dZ.Cs + dZ.Co + co);
+        return *reinterpret_cast<const uint4 *>(dZ.p + ((size_t)(pn[u] * H + yy) * W + xx) * dZ.Cs + dZ.Co + co);
     };
-    auto loadB = [&](int k0) -> uint4 {
-        const int k = k0 + kc;
-        if (cib >= Cin || k >= K) return uint4{0, 0, 0, 0};
+    auto loadB = [&](int u, int k0) -> uint4 {
+        const int c = t + 256 * u, ci = n0 + (c >> 2), k = k0 + (c & 3) * 8;
+        if (c >= TBN * 4 || ci >= Cin || k >= K) return uint4{0, 0, 0, 0};
         const int tap = k >> lgCout, co = k & (Cout - 1);
-        return *reinterpret_cast<const uint4 *>(Wt + ((size_t)tap * Cin + cib) * Cout + co);
+        return *reinterpret_cast<const uint4 *>(Wt + ((size_t)tap * Cin + ci) * Cout + co);
     };
     floatx4 acc[2][2] = {};
-    uint4 ra = loadA(0), rb = loadB(0);
+    uint4 ra[NA], rb[NB];
+#pragma unroll
+    for (int u = 0; u < NA; ++u) ra[u] = loadA(u, 0);
+#pragma unroll
+    for (int u = 0; u < NB; ++u) rb[u] = loadB(u, 0);
     for (int k0 = 0; k0 < K; k0 += BK) {
-        *reinterpret_cast<uint4 *>(As + r * LP + kc) = ra;
-        *reinterpret_cast<uint4 *>(Bs + r * LP + kc) = rb;
+#pragma unroll
+        for (int u = 0; u < NA; ++u)
+            if (t + 256 * u < TBM * 4) *reinterpret_cast<uint4 *>(As + arow[u] * LP + akc[u]) = ra[u];
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const int c = t + 256 * u;
+            if (c < TBN * 4) *reinterpret_cast<uint4 *>(Bs + (c >> 2) * LP + (c & 3) * 8) = rb[u];
+        }
         __syncthreads();
         if (k0 + BK < K) {
-            ra = loadA(k0 + BK);
-            rb = loadB(k0 + BK);
+#pragma unroll
+            for (int u = 0; u < NA; ++u) ra[u] = loadA(u, k0 + BK);
+#pragma unroll
+            for (int u = 0; u < NB; ++u) rb[u] = loadB(u, k0 + BK);
         }
-        mma_step(As, Bs, acc);
+        mma_step_t<WM, WN>(As, Bs, acc);
         __syncthreads();
     }
 #pragma unroll
@@ -175,7 +218,7 @@ conv_dgrad_kernel(View dZ, int lgCout, int B, int H, int W, const bf16_t *__rest
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 int row, col;
-                acc_coord(i, j, q, &row, &col);
+                acc_coord_t<WM, WN>(i, j, q, &row, &col);
                 const int mg = m0 + row, cg = n0 + col;
                 if (mg >= M || cg >= Cin) continue;
                 float v = acc[i][j][q];
@@ -242,29 +285,31 @@ __global__ void dgrad_fold_kernel(View dZ, int Cout, int B, int H, int W,
 // output channels, cols = (tap, ci), K = pixels.  Both operands are read 8
 // channels at a time and transposed into LDS (K contiguous).  Each workgroup
 // owns one pixel range (split K) and adds its tile into dW with FP32 atomics.
-template <int KS>
+template <int KS, int WM, int WN>
 __global__ void __launch_bounds__(256)
 conv_wgrad_kernel(View dZ, int Cout, View X, int lgCin, int B, int H, int W,
                   float *__restrict__ dW, int pix_per_split)
 {
-    __shared__ __align__(16) bf16_t As[BM * LP];
-    __shared__ __align__(16) bf16_t Bs[BN * LP];
+    constexpr int TBM = 32 * WM, TBN = 32 * WN;
+    constexpr int CA = TBM / 8, CB = TBN / 8;                  // 8-channel chunks per pixel
+    constexpr int NA = (32 * CA + 255) / 256, NB = (32 * CB + 255) / 256;
+    __shared__ __align__(16) bf16_t As[TBM * LP];
+    __shared__ __align__(16) bf16_t Bs[TBN * LP];
     const int Cin = 1 << lgCin, Kw = KS * KS * Cin, M = B * H * W;
-    const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+    const int m0 = blockIdx.x * TBM, n0 = blockIdx.y * TBN;
     const int p_begin = blockIdx.z * pix_per_split;
     const int p_end = min(M, p_begin + pix_per_split);
     if (p_begin >= p_end) return;
-    const int t = threadIdx.x, pl = t >> 3, cc = (t & 7) * 8;
-    const int co = m0 + cc, kk = n0 + cc;
-    const int tap = kk >> lgCin, ci = kk & (Cin - 1);
-    auto loadA = [&](int p0) -> uint4 {
-        const int p = p0 + pl;
-        if (p >= p_end || co >= Cout) return uint4{0, 0, 0, 0};
+    const int t = threadIdx.x;
+    auto loadA = [&](int u, int p0) -> uint4 {
+        const int c = t + 256 * u, pl = c / CA, co = m0 + (c % CA) * 8, p = p0 + pl;
+        if (c >= 32 * CA || p >= p_end || co >= Cout) return uint4{0, 0, 0, 0};
         return *reinterpret_cast<const uint4 *>(dZ.p + (size_t)p * dZ.Cs + dZ.Co + co);
     };
-    auto loadB = [&](int p0) -> uint4 {
-        const int p = p0 + pl;
-        if (p >= p_end || kk >= Kw) return uint4{0, 0, 0, 0};
+    auto loadB = [&](int u, int p0) -> uint4 {
+        const int c = t + 256 * u, pl = c / CB, kk = n0 + (c % CB) * 8, p = p0 + pl;
+        if (c >= 32 * CB || p >= p_end || kk >= Kw) return uint4{0, 0, 0, 0};
+        const int tap = kk >> lgCin, ci = kk & (Cin - 1);
         const int n = p / (H * W), rem = p - n * H * W;
         int y = rem / W, x = rem - y * W;
         if (KS == 3) {
@@ -274,21 +319,40 @@ conv_wgrad_kernel(View dZ, int Cout, View X, int lgCin, int B, int H, int W,
         return *reinterpret_cast<const uint4 *>(X.p + ((size_t)(n * H + y) * W + x) * X.Cs + X.Co + ci);
     };
     floatx4 acc[2][2] = {};
-    uint4 ra = loadA(p_begin), rb = loadB(p_begin);
-    for (int p0 = p_begin; p0 < p_end; p0 += BK) {
-        const bf16_t *va = reinterpret_cast<const bf16_t *>(&ra);
-        const bf16_t *vb = reinterpret_cast<const bf16_t *>(&rb);
+    uint4 ra[NA], rb[NB];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            As[(cc + e) * LP + pl] = va[e];
-            Bs[(cc + e) * LP + pl] = vb[e];
+    for (int u = 0; u < NA; ++u) ra[u] = loadA(u, p_begin);
+#pragma unroll
+    for (int u = 0; u < NB; ++u) rb[u] = loadB(u, p_begin);
+    for (int p0 = p_begin; p0 < p_end; p0 += BK) {
+#pragma unroll
+        for (int u = 0; u < NA; ++u) {
+            const int c = t + 256 * u;
+            if (c < 32 * CA) {
+                const bf16_t *v = reinterpret_cast<const bf16_t *>(&ra[u]);
+                const int pl = c / CA, cc = (c % CA) * 8;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) As[(cc + e) * LP + pl] = v[e];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const int c = t + 256 * u;
+            if (c < 32 * CB) {
+                const bf16_t *v = reinterpret_cast<const bf16_t *>(&rb[u]);
+                const int pl = c / CB, cc = (c % CB) * 8;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) Bs[(cc + e) * LP + pl] = v[e];
+            }
         }
         __syncthreads();
         if (p0 + BK < p_end) {
-            ra = loadA(p0 + BK);
-            rb = loadB(p0 + BK);
+#pragma unroll
+            for (int u = 0; u < NA; ++u) ra[u] = loadA(u, p0 + BK);
+#pragma unroll
+            for (int u = 0; u < NB; ++u) rb[u] = loadB(u, p0 + BK);
         }
-        mma_step(As, Bs, acc);
+        mma_step_t<WM, WN>(As, Bs, acc);
         __syncthreads();
     }
 #pragma unroll
@@ -298,7 +362,7 @@ conv_wgrad_kernel(View dZ, int Cout, View X, int lgCin, int B, int H, int W,
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 int row, col;
-                acc_coord(i, j, q, &row, &col);
+                acc_coord_t<WM, WN>(i, j, q, &row, &col);
                 const int rg = m0 + row, cg = n0 + col;
                 if (rg < Cout && cg < Kw) atomicAdd(dW + (size_t)rg * Kw + cg, acc[i][j][q]);
             }
@@ -554,20 +618,51 @@ const bf16_t *wk_of(const ac_sur *s, int l) { return s->wb + s->kwoff[l]; }
 const bf16_t *wt_of(const ac_sur *s, int l) { return s->wt + s->kwoff[l]; }
 
 // Y = act(conv(X)); H, W: the resolution of X (and Y unless up)
+template <int KS, bool UP, int WM, int WN>
+void launch_fwd(ac_sur *s, int l, View X, int lgcin, int B, int H, int W, View Y, bool relu) {
+    const LayerDef &L = kLayers[l];
+    const int M = B * H * W;
+    dim3 grid((M + 32 * WM - 1) / (32 * WM), (L.cout + 32 * WN - 1) / (32 * WN));
+    hipLaunchKernelGGL((conv_fwd_kernel<KS, UP, WM, WN>), grid, dim3(256), 0, s->st, X, lgcin, B,
+                       H, W, wk_of(s, l), bias_of(s, l), L.cout, Y, (int)relu);
+}
+
 void conv_fwd(ac_sur *s, int l, View X, int B, int H, int W, View Y, bool relu, bool up) {
     const LayerDef &L = kLayers[l];
-    const int cin = l == L_E1A ? 8 : L.cin;
+    const int lg = lg2(l == L_E1A ? 8 : L.cin);
+    const bool narrow = L.cout <= 32;          // 128 x 32 tiles
+    if (L.k == 3) {
+        if (narrow) launch_fwd<3, false, 4, 1>(s, l, X, lg, B, H, W, Y, relu);
+        else launch_fwd<3, false, 2, 2>(s, l, X, lg, B, H, W, Y, relu);
+    } else if (up) {
+        if (narrow) launch_fwd<1, true, 4, 1>(s, l, X, lg, B, H, W, Y, relu);
+        else launch_fwd<1, true, 2, 2>(s, l, X, lg, B, H, W, Y, relu);
+    } else {
+        if (narrow) launch_fwd<1, false, 4, 1>(s, l, X, lg, B, H, W, Y, relu);
+        else launch_fwd<1, false, 2, 2>(s, l, X, lg, B, H, W, Y, relu);
+    }
+}
+
+template <int KS, int WM, int WN>
+void launch_wgrad(ac_sur *s, View dZ, int cout, View X, int lgcin, int B, int H, int W, float *dW) {
+    const int M = B * H * W, Kw = KS * KS * (1 << lgcin);
+    const int tiles = ((cout + 32 * WM - 1) / (32 * WM)) * ((Kw + 32 * WN - 1) / (32 * WN));
+    int splits = std::max(1, std::min(2048 / tiles, (M + 255) / 256));
+    int per = (M + splits - 1) / splits;
+    per = (per + BK - 1) / BK * BK;
+    splits = (M + per - 1) / per;
+    dim3 gw((cout + 32 * WM - 1) / (32 * WM), (Kw + 32 * WN - 1) / (32 * WN), splits);
+    hipLaunchKernelGGL((conv_wgrad_kernel<KS, WM, WN>), gw, dim3(256), 0, s->st, dZ, cout, X, lgcin,
+                       B, H, W, dW, per);
+}
+
+template <int KS, int WM, int WN>
+void launch_dgrad(ac_sur *s, int l, View dZ, int lgcout, int B, int H, int W, int cin, View dX,
+                  View mask, int mask_c0) {
     const int M = B * H * W;
-    dim3 grid((M + BM - 1) / BM, (L.cout + BN - 1) / BN);
-    if (L.k == 3)
-        hipLaunchKernelGGL((conv_fwd_kernel<3, false>), grid, dim3(256), 0, s->st, X, lg2(cin), B,
-                           H, W, wk_of(s, l), bias_of(s, l), L.cout, Y, (int)relu);
-    else if (up)
-        hipLaunchKernelGGL((conv_fwd_kernel<1, true>), grid, dim3(256), 0, s->st, X, lg2(cin), B,
-                           H, W, wk_of(s, l), bias_of(s, l), L.cout, Y, (int)relu);
-    else
-        hipLaunchKernelGGL((conv_fwd_kernel<1, false>), grid, dim3(256), 0, s->st, X, lg2(cin), B,
-                           H, W, wk_of(s, l), bias_of(s, l), L.cout, Y, (int)relu);
+    dim3 gd((M + 32 * WM - 1) / (32 * WM), (cin + 32 * WN - 1) / (32 * WN));
+    hipLaunchKernelGGL((conv_dgrad_kernel<KS, WM, WN>), gd, dim3(256), 0, s->st, dZ, lgcout, B, H, W,
+                       wt_of(s, l), cin, dX, mask, mask_c0, 0);
 }
 
 // gradients of layer l from dZ (grad at its pre-activation output) and its
@@ -578,33 +673,30 @@ void conv_bwd(ac_sur *s, int l, View X, View dZ, int B, int H, int W, float *dWd
     const LayerDef &L = kLayers[l];
     const int cin = l == L_E1A ? 8 : L.cin;
     const int M = B * H * W;
-    const int Kw = L.k * L.k * cin;
-    // weight gradient, split over pixels
-    const int tiles = ((L.cout + BM - 1) / BM) * ((Kw + BN - 1) / BN);
-    int splits = std::max(1, std::min(2048 / tiles, (M + 255) / 256));
-    int per = (M + splits - 1) / splits;
-    per = (per + BK - 1) / BK * BK;
-    splits = (M + per - 1) / per;
-    dim3 gw((L.cout + BM - 1) / BM, (Kw + BN - 1) / BN, splits);
-    if (L.k == 3)
-        hipLaunchKernelGGL((conv_wgrad_kernel<3>), gw, dim3(256), 0, s->st, dZ, L.cout, X, lg2(cin),
-                           B, H, W, dWdst, per);
-    else
-        hipLaunchKernelGGL((conv_wgrad_kernel<1>), gw, dim3(256), 0, s->st, dZ, L.cout, X, lg2(cin),
-                           B, H, W, dWdst, per);
+    const int lgcin = lg2(cin), lgcout = lg2(L.cout);
+    // weight gradient: rows = output channels
+    if (L.k == 3) {
+        if (L.cout <= 32) launch_wgrad<3, 1, 4>(s, dZ, L.cout, X, lgcin, B, H, W, dWdst);
+        else if (L.cout <= 64) launch_wgrad<3, 2, 2>(s, dZ, L.cout, X, lgcin, B, H, W, dWdst);
+        else launch_wgrad<3, 4, 1>(s, dZ, L.cout, X, lgcin, B, H, W, dWdst);
+    } else {
+        if (L.cout <= 32) launch_wgrad<1, 1, 4>(s, dZ, L.cout, X, lgcin, B, H, W, dWdst);
+        else if (L.cout <= 64) launch_wgrad<1, 2, 2>(s, dZ, L.cout, X, lgcin, B, H, W, dWdst);
+        else launch_wgrad<1, 4, 1>(s, dZ, L.cout, X, lgcin, B, H, W, dWdst);
+    }
     hipLaunchKernelGGL(bias_grad_kernel, dim3(std::min(1024, (M + 7) / 8)), dim3(256 / L.cout * L.cout),
                        0, s->st, dZ, L.cout, M, s->g + s->boff[l]);
     if (!dX.p) return;
-    dim3 gd((M + BM - 1) / BM, (cin + BN - 1) / BN);
+    const bool narrow = cin <= 32;
     if (L.k == 3) {
-        hipLaunchKernelGGL((conv_dgrad_kernel<3>), gd, dim3(256), 0, s->st, dZ, lg2(L.cout), B, H, W,
-                           wt_of(s, l), cin, dX, mask, mask_c0, 0);
+        if (narrow) launch_dgrad<3, 4, 1>(s, l, dZ, lgcout, B, H, W, cin, dX, mask, mask_c0);
+        else launch_dgrad<3, 2, 2>(s, l, dZ, lgcout, B, H, W, cin, dX, mask, mask_c0);
         const int nb = (H == 1 || W == 1) ? H * W : 2 * W + 2 * (H - 2);
         hipLaunchKernelGGL(dgrad_fold_kernel, grid1((long long)B * nb * cin), dim3(256), 0, s->st,
                            dZ, L.cout, B, H, W, wk_of(s, l), cin, dX, mask, mask_c0);
     } else {
-        hipLaunchKernelGGL((conv_dgrad_kernel<1>), gd, dim3(256), 0, s->st, dZ, lg2(L.cout), B, H, W,
-                           wt_of(s, l), cin, dX, mask, mask_c0, 0);
+        if (narrow) launch_dgrad<1, 4, 1>(s, l, dZ, lgcout, B, H, W, cin, dX, mask, mask_c0);
+        else launch_dgrad<1, 2, 2>(s, l, dZ, lgcout, B, H, W, cin, dX, mask, mask_c0);
     }
 }
 

@@ -9,10 +9,10 @@ Training: mini-batches of pairs, MSE of phi + U(phi) against phi_{k+1}, Adam;
 forward, backward and update all run in libac's BF16-MFMA kernels.
 
 Inference to T with judge and fallback: each K-block the surrogate advances
-every grid; the judge runs the plain stepper on a rotating sample of the grids
-and compares (interface error <= h and RMS <= l2_bar); if any sampled grid
-fails, the whole block is recomputed by the plain stepper from the last
-accepted state.  Time-to-T includes the judge and every fallback.
+every trusted grid; the plain stepper advances a rotating sample of them (the
+judge compares the two: interface error <= h and RMS <= l2_bar) and every grid
+that has failed once (the fallback), all in one masked batched launch.
+Time-to-T includes the judge and the fallback.
 
   python -m paper_2105_09671_amd.sur_train --out weights.npz [--trajectories 4096] [--steps 3000]
 """
@@ -73,10 +73,20 @@ def init_weights(seed: int, n: int) -> np.ndarray:
     return w
 
 
-def train(data: torch.Tensor, steps: int, batch: int = 32, lr: float = 2e-3, seed: int = 0,
-          net: Surrogate | None = None, log_every: int = 200):
+def training_pairs(kinds, blocks: int):
+    """(trajectory, block) pairs used for training: every block of every
+    trajectory except the first block of a random start -- from raw noise the
+    outcome after K steps is set by the exact noise amplified (spinodal
+    growth), which no local map can predict; the judge falls back there."""
+    return np.array([(t, k) for t, kd in enumerate(kinds) for k in range(blocks)
+                     if not (kd == "random" and k == 0)], dtype=np.int64)
+
+
+def train(data: torch.Tensor, steps: int, batch: int = 32, lr: float = 1e-3, seed: int = 0,
+          net: Surrogate | None = None, log_every: int = 500, kinds=None):
     """Adam on MSE of random (trajectory, block) pairs; cosine-decayed lr."""
     ntraj, nb = data.shape[0], data.shape[1] - 1
+    pairs = training_pairs(kinds or ["circle"] * ntraj, nb)
     if net is None:
         net = Surrogate(batch, HW)
         net.set_weights(init_weights(seed, net.n))
@@ -86,8 +96,9 @@ def train(data: torch.Tensor, steps: int, batch: int = 32, lr: float = 2e-3, see
     hist = []
     t0 = time.perf_counter()
     for it in range(steps):
-        ti = torch.from_numpy(rng.randint(0, ntraj, batch)).cuda()
-        ki = torch.from_numpy(rng.randint(0, nb, batch)).cuda()
+        sel = pairs[rng.randint(0, len(pairs), batch)]
+        ti = torch.from_numpy(sel[:, 0]).cuda()
+        ki = torch.from_numpy(sel[:, 1]).cuda()
         x.copy_(data[ti, ki])
         y.copy_(data[ti, ki + 1])
         a = lr * (0.05 + 0.95 * 0.5 * (1 + math.cos(math.pi * it / max(steps, 1))))
@@ -100,9 +111,65 @@ def train(data: torch.Tensor, steps: int, batch: int = 32, lr: float = 2e-3, see
     return net, hist, time.perf_counter() - t0
 
 
+def validate(net: Surrogate, data: torch.Tensor, kinds) -> dict:
+    """Mean squared error of phi + U(phi) against the stepper, per kind and block."""
+    out = {}
+    nb = data.shape[1] - 1
+    B = net.batch_max
+    pred = torch.empty(B, HW, HW, device="cuda")
+    for kd in sorted(set(kinds)):
+        idx = [i for i, x in enumerate(kinds) if x == kd]
+        row = []
+        for k in range(nb):
+            se, n = 0.0, 0
+            for s in range(0, len(idx), B):
+                sub = torch.tensor(idx[s:s + B], device="cuda")
+                x = data[sub, k].contiguous()
+                net.forward(x, pred[:len(sub)])
+                se += float(((pred[:len(sub)] - data[sub, k + 1]) ** 2).sum().item())
+                n += len(sub) * HW * HW
+            row.append(se / n)
+        out[kd] = row
+    return out
+
+
+# FLOPs of one forward pass on a 256 x 256 grid (2 per multiply-add), the two
+# 1x1 layers counted at the low resolution where they are evaluated
+FORWARD_FLOP = 2 * sum(ci * co * k * k * (HW // f) ** 2 for ci, co, k, f in [
+    (1, 32, 3, 1), (32, 32, 3, 1), (32, 64, 3, 2), (64, 64, 3, 2), (64, 128, 3, 4),
+    (128, 64, 1, 4), (128, 64, 3, 2), (64, 32, 1, 2), (64, 32, 3, 1), (32, 1, 1, 1)])
+
+
+def forward_rate(net: Surrogate, n: int, reps: int = 3) -> dict:
+    """Time the forward pass alone on n grids: ms per call and TFLOP/s."""
+    x = torch.zeros(n, HW, HW, device="cuda")
+    y = torch.empty_like(x)
+    B = net.batch_max
+    for s in range(0, n, B):
+        net.forward(x[s:s + B], y[s:s + B])
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        for s in range(0, n, B):
+            net.forward(x[s:s + B], y[s:s + B])
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return {"grids": n, "ms": round(ms, 3), "TFLOPs": round(n * FORWARD_FLOP / ms / 1e9, 1),
+            "flop_per_grid": FORWARD_FLOP}
+
+
 def evaluate(net: Surrogate, seeds, T_blocks: int = 20, sample_every: int = 16,
              l2_bar: float = L2_BAR) -> dict:
-    """Surrogate + judge + fallback to T versus the plain stepper, on held-out seeds."""
+    """Surrogate + judge + fallback to T versus the plain stepper, on held-out seeds.
+
+    Per K-block: the surrogate advances every trusted grid; the plain stepper
+    advances a rotating 1/sample_every of the trusted grids (the judge sample)
+    and every untrusted grid, in one masked batched launch.  A sampled grid
+    keeps the plain result; if the surrogate's prediction for it fails the
+    judge (interface error > h or RMS > l2_bar) the grid is untrusted from then
+    on.  Unsampled trusted grids take the surrogate's prediction."""
     gs, fields = grids_for(seeds)
     params = [(g.h, g.dt, g.eps) for g in gs]
     N = len(seeds)
@@ -120,46 +187,47 @@ def evaluate(net: Surrogate, seeds, T_blocks: int = 20, sample_every: int = 16,
     torch.cuda.synchronize()
     plain_ms = s0.elapsed_time(s1)
     ref_T = plain.phi.view(N, HW, HW).clone()
+    del plain
 
-    # surrogate path: state in a batch (its plain stepper is the fallback)
     fb = api.Batch(fields, params)
     state = fb.phi.view(N, HW, HW)
-    fb.step(K_STEPS)                                    # warm the fallback plan
-    for v, f in zip(fb.views(), fields):
-        v.copy_(torch.from_numpy(f).float())
-    # judge batches: the rotating samples, built (and their graphs captured) up front
-    nsamp = max(1, (N + sample_every - 1) // sample_every)
-    rounds = min(sample_every, T_blocks)
-    samples, judges = [], []
-    for k in range(rounds):
-        idx = [(k + j * sample_every) % N for j in range(nsamp)]
-        jb = api.Batch([fields[i] for i in idx], [params[i] for i in idx])
-        jb.step(K_STEPS)
-        samples.append(torch.tensor(idx, device="cuda"))
-        judges.append(jb)
+    active = torch.zeros(N, dtype=torch.int32, device="cuda")
+    fb.step_masked(K_STEPS, active)                     # builds the plan; steps nothing
+    trusted = torch.ones(N, dtype=torch.bool, device="cuda")
     pred = torch.empty_like(state)
-    for s in range(0, N, net.batch_max):                # warm-up
-        net.forward(state[s:s + net.batch_max], pred[s:s + net.batch_max])
+    B = net.batch_max
+    net.forward(state[:min(N, B)].contiguous(), pred[:min(N, B)])   # warm-up
     torch.cuda.synchronize()
-    fallbacks, judged_fail = 0, 0
+    sur_grid_blocks, judged, judged_fail = 0, 0, 0
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for k in range(T_blocks):
-        for s in range(0, N, net.batch_max):
-            net.forward(state[s:s + net.batch_max], pred[s:s + net.batch_max])
-        idx, jb = samples[k % rounds], judges[k % rounds]
-        jstate = jb.phi.view(len(idx), HW, HW)
-        jstate.copy_(state[idx])                        # plain steps from the same start
-        jb.step(K_STEPS)
-        iface, l2 = api.judge2d(pred[idx].contiguous(), jstate, h)
-        ok = (iface <= h) & (l2 <= l2_bar)
-        nfail = int((~ok).sum().item())
-        judged_fail += nfail
-        if nfail == 0:
-            state.copy_(pred)
-        else:
-            fallbacks += 1
-            fb.step(K_STEPS)                            # every grid by the plain stepper
+        tidx = trusted.nonzero().flatten()
+        nt = int(tidx.numel())
+        if nt:
+            x = state[tidx]
+            out = torch.empty_like(x)
+            for s in range(0, nt, B):
+                net.forward(x[s:s + B], out[s:s + B])
+        samp = tidx[(k % sample_every)::sample_every]
+        active.zero_()
+        active[samp] = 1
+        active[~trusted] = 1
+        fb.step_masked(K_STEPS, active)                 # plain: sample + untrusted, in place
+        if samp.numel():
+            pos = torch.arange(k % sample_every, nt, sample_every, device="cuda")
+            iface, l2 = api.judge2d(out[pos].contiguous(), state[samp].contiguous(), h)
+            ok = (iface <= h) & (l2 <= l2_bar)
+            judged += int(samp.numel())
+            nfail = int((~ok).sum().item())
+            judged_fail += nfail
+            if nfail:
+                trusted[samp[~ok]] = False
+        if nt:
+            keep = torch.ones(nt, dtype=torch.bool, device="cuda")
+            keep[k % sample_every::sample_every] = False
+            state[tidx[keep]] = out[keep]
+            sur_grid_blocks += int(keep.sum().item())
     e1.record()
     torch.cuda.synchronize()
     sur_ms = e0.elapsed_time(e1)
@@ -167,32 +235,56 @@ def evaluate(net: Surrogate, seeds, T_blocks: int = 20, sample_every: int = 16,
     iface_T, l2_T = iface_T.cpu().numpy(), l2_T.cpu().numpy()
     kinds = [g.kind for g in gs]
     ok_T = (iface_T <= h) & (l2_T <= l2_bar)
-    by_kind = {kd: float(np.mean(ok_T[[i for i, x in enumerate(kinds) if x == kd]]))
+    trusted_np = trusted.cpu().numpy()
+    by_kind = {kd: {"final_ok": float(np.mean(ok_T[[i for i, x in enumerate(kinds) if x == kd]])),
+                    "trusted_at_T": float(np.mean(trusted_np[[i for i, x in enumerate(kinds) if x == kd]]))}
                for kd in sorted(set(kinds))}
     return {"grids": N, "T_steps": K_STEPS * T_blocks, "plain_ms": round(plain_ms, 3),
             "surrogate_ms": round(sur_ms, 3), "speedup": round(plain_ms / sur_ms, 4),
-            "fallback_blocks": fallbacks, "blocks": T_blocks, "judged_failures": judged_fail,
-            "sample_every": sample_every, "final_ok_fraction": float(np.mean(ok_T)),
-            "final_ok_by_kind": by_kind,
+            "forward": forward_rate(net, N),
+            "surrogate_grid_blocks": sur_grid_blocks, "grid_blocks": N * T_blocks,
+            "judged": judged, "judged_failures": judged_fail, "sample_every": sample_every,
+            "final_ok_fraction": float(np.mean(ok_T)), "by_kind": by_kind,
             "final_iface_median_over_h": float(np.median(np.minimum(iface_T / h, 1e9))),
             "final_l2_median": float(np.median(l2_T))}
 
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--out", required=True, help="weights file (.npz) to write")
+    ap.add_argument("--out", default="", help="weights file (.npz) to write")
     ap.add_argument("--trajectories", type=int, default=4096)
-    ap.add_argument("--steps", type=int, default=3000)
+    ap.add_argument("--steps", type=int, default=30000)
     ap.add_argument("--batch", type=int, default=32)
-    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--eval", type=int, default=256, help="held-out grids (seeds 100000..)")
+    ap.add_argument("--init", default="", help="start from these weights (.npz)")
+    ap.add_argument("--evaluate-only", action="store_true",
+                    help="skip training: evaluate the weights given by --init")
     args = ap.parse_args()
+    if args.evaluate_only:
+        ev = Surrogate(min(256, args.eval), HW)
+        ev.set_weights(np.load(args.init)["weights"])
+        print(json.dumps(evaluate(ev, list(range(100000, 100000 + args.eval)))), flush=True)
+        return
     t0 = time.perf_counter()
-    data = make_trajectories(list(range(args.trajectories)))
+    seeds = list(range(args.trajectories))
+    kinds = [workloads.surrogate_grid(s, HW).kind for s in seeds]
+    data = make_trajectories(seeds)
     log("trajectories %s in %.1f s" % (tuple(data.shape), time.perf_counter() - t0))
-    net, hist, tsec = train(data, args.steps, args.batch, args.lr)
+    net = None
+    if args.init:
+        net = Surrogate(args.batch, HW)
+        net.set_weights(np.load(args.init)["weights"])
+    net, hist, tsec = train(data, args.steps, args.batch, args.lr, net=net, kinds=kinds)
     del data
     w = net.get_weights()
+    vseeds = list(range(200000, 200064))
+    vkinds = [workloads.surrogate_grid(s, HW).kind for s in vseeds]
+    vdata = make_trajectories(vseeds)
+    val = validate(net, vdata, vkinds)
+    del vdata
+    log("validation MSE per kind and block: %s" % json.dumps(
+        {k: ["%.2e" % v for v in row] for k, row in val.items()}))
     np.savez(args.out, weights=w, history=np.array(hist), steps=args.steps,
              trajectories=args.trajectories, batch=args.batch, lr=args.lr, train_seconds=tsec)
     log("saved %s (%d params, %.1f s of training)" % (args.out, w.size, tsec))
@@ -201,6 +293,7 @@ def main():
     res = evaluate(ev, list(range(100000, 100000 + args.eval)))
     res["train_seconds"] = round(tsec, 2)
     res["final_loss"] = hist[-1][1]
+    res["validation_mse"] = val
     print(json.dumps(res), flush=True)
 
 

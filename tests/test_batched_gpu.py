@@ -175,3 +175,28 @@ def test_batch512_sampled_against_oracle(api, dtype):
             assert err <= SENS_FACTOR * sens, "instance %d rel Linf %g > %g x %g" % (
                 i, err, SENS_FACTOR, sens)
     print("batch512 %s: launch %s, worst sampled rel Linf %.3g" % (dtype, info, worst))
+
+
+def test_masked_batch_steps_only_active_grids(api):
+    fields, prm = _small_batch(45)
+    fields = [f.astype(np.float32) for f in fields]
+    b = api.Batch(fields, prm)
+    full = api.Batch(fields, prm)
+    full.step(23)
+    active = torch.zeros(len(fields), dtype=torch.int32, device="cuda")
+    on = [1, 4, 6, 11]
+    active[on] = 1
+    b.step_masked(23, active)
+    for i, (v, w) in enumerate(zip(b.views(), full.views())):
+        if i in on:
+            assert torch.equal(v, w), i
+        else:
+            assert np.array_equal(v.cpu().numpy(), fields[i]), i
+    # the mask is read at run time: a new mask reuses the plan
+    active.zero_()
+    active[[0, 1]] = 1
+    info1 = b.step_masked(23, active)
+    ref = api.Batch(fields, prm)
+    ref.step(46)
+    assert torch.equal(b.views()[1], ref.views()[1])
+    assert info1["items"] > 0
