@@ -17,8 +17,9 @@ Printed as one JSON line on stdout:
   cpu_baseline  the FP64 CPU oracle timed on this host's cores on a bounded
             sample of the same workload.
   extra     the other workloads: the FP64 circle, the 3D 256^3 FP32 grid at
-            every temporal-blocking depth, the 3D sphere radius check and the
-            64x64 FP64 phase-separation grid.
+            every temporal-blocking depth, the 3D sphere radius check, the
+            512-grid batch, the learned surrogate's time-to-T against the
+            plain stepper, and the 64x64 FP64 phase-separation grid.
 """
 from __future__ import annotations
 
@@ -155,6 +156,19 @@ def extras(api, torch, workloads, params) -> dict:
                             "ms": round(t * 1e3, 2), "cells": b.cells, "launch": info}
     log("extra batch512_fp32", out["batch512_fp32"])
     del b
+    # learned K=100-step surrogate vs the plain stepper: 256 held-out 256^2
+    # grids to T = 2000 steps, judge + fallback included (stored weights)
+    import numpy as np
+    from paper_2105_09671_amd import sur_train, surrogate
+    wpath = os.path.join(ROOT, "paper_2105_09671_amd", "weights", "sur256.npz")
+    net = surrogate.Surrogate(256, 256)
+    net.set_weights(np.load(wpath)["weights"])
+    out["sur256"] = sur_train.evaluate(net, list(range(100000, 100256)))
+    out["sur256"]["roofline"] = {"bound": "mfma", "peak": 2500.0, "unit": "TFLOP/s",
+                                 "achieved": out["sur256"]["forward"]["TFLOPs"],
+                                 "frac": round(out["sur256"]["forward"]["TFLOPs"] / 2500.0, 4)}
+    net.close()
+    log("extra sur256", {k: v for k, v in out["sur256"].items() if k != "by_kind"})
     # 64x64 FP64 phase separation, 500 steps, one LDS-resident launch
     g1 = workloads.phase64()
     p1 = torch.from_numpy(g1.initial()).cuda()

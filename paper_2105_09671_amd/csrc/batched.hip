@@ -40,6 +40,40 @@ struct BatchInst {
 
 __global__ void batch_reset_kernel(unsigned *bar) { *bar = 0u; }
 
+// Masked batches: copy the items of active instances, in order, to `out` and
+// their number to *count.  One workgroup of 1024 threads scans the list in
+// chunks with an LDS prefix sum, so the order (and hence the XCD grouping of
+// neighbouring tiles) is kept.
+__global__ void __launch_bounds__(1024)
+batch_compact_kernel(const int4 *__restrict__ items, int n_items, const int *__restrict__ active,
+                     int4 *__restrict__ out, int *count)
+{
+    __shared__ int scan[1024];
+    int base = 0;
+    for (int c0 = 0; c0 < n_items; c0 += 1024) {
+        const int i = c0 + threadIdx.x;
+        int4 it{0, 0, 0, 0};
+        int f = 0;
+        if (i < n_items) {
+            it = items[i];
+            f = active[it.x] != 0;
+        }
+        scan[threadIdx.x] = f;
+        __syncthreads();
+        for (int d = 1; d < 1024; d <<= 1) {       // inclusive Hillis-Steele scan
+            const int v = threadIdx.x >= (unsigned)d ? scan[threadIdx.x - d] : 0;
+            __syncthreads();
+            scan[threadIdx.x] += v;
+            __syncthreads();
+        }
+        if (f) out[base + scan[threadIdx.x] - 1] = it;
+        const int total = scan[1023];
+        __syncthreads();
+        base += total;
+    }
+    if (threadIdx.x == 0) *count = base;
+}
+
 // Returns false once any workgroup has given up waiting.
 __device__ __forceinline__ bool grid_sync(unsigned *bar, unsigned target, int *err,
                                           long long spin_limit) {
@@ -82,9 +116,10 @@ template <typename T, int LXC>
 __global__ void __launch_bounds__(256)
 batched_kernel(const BatchInst *__restrict__ inst, const int4 *__restrict__ items, int n_items,
                int LX, int LY, int K, int nblocks, int base, int rem, int copy_back,
-               const int *__restrict__ active, unsigned *bar, int *err, long long spin_limit)
+               const int *__restrict__ n_active, unsigned *bar, int *err, long long spin_limit)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
+    if (n_active) n_items = *n_active;            // masked: `items` is the compacted list
     const int G = gridDim.x;                    // a multiple of 8
     const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3, per = G >> 3;
     const int lo = (int)((long long)n_items * xcd / 8);
@@ -94,7 +129,6 @@ batched_kernel(const BatchInst *__restrict__ inst, const int4 *__restrict__ item
         const int k = base + (b < rem ? 1 : 0);
         for (int i = lo + j; i < hi; i += per) {
             const int4 it = items[i];
-            if (active && !active[it.x]) continue;      // same item for the whole workgroup
             const BatchInst I = inst[it.x];
             const T *src = static_cast<const T *>((b & 1) ? I.work : I.phi);
             T *dst = static_cast<T *>((b & 1) ? I.phi : I.work);
@@ -110,7 +144,6 @@ batched_kernel(const BatchInst *__restrict__ inst, const int4 *__restrict__ item
     if (copy_back) {   // odd number of single-step blocks: the result sits in work
         for (int i = lo + j; i < hi; i += per) {
             const int4 it = items[i];
-            if (active && !active[it.x]) continue;
             const BatchInst I = inst[it.x];
             copy_tile<T>(static_cast<const T *>(I.work), static_cast<T *>(I.phi), I.nx, I.ny,
                          LX - 2 * K, LY - 2 * K, it.y, it.z);
@@ -135,6 +168,8 @@ struct Plan {
     // device state
     BatchInst *d_inst = nullptr;
     int4 *d_items = nullptr;
+    int4 *d_compact = nullptr;      // masked plans: active items of the current call
+    int *d_count = nullptr;
     unsigned *d_bar = nullptr;
     int *d_err = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -169,9 +204,12 @@ void release(Plan &p) {
     if (p.graph) (void)hipGraphDestroy(p.graph);
     if (p.d_inst) (void)hipFree(p.d_inst);
     if (p.d_items) (void)hipFree(p.d_items);
+    if (p.d_compact) (void)hipFree(p.d_compact);
+    if (p.d_count) (void)hipFree(p.d_count);
     if (p.d_bar) (void)hipFree(p.d_bar);
     if (p.d_err) (void)hipFree(p.d_err);
     p.exec = nullptr; p.graph = nullptr; p.d_inst = nullptr; p.d_items = nullptr;
+    p.d_compact = nullptr; p.d_count = nullptr;
     p.d_bar = nullptr; p.d_err = nullptr;
 }
 
@@ -256,6 +294,8 @@ ac_status build_plan(Plan &p, const ac_instance2d *inst, int32_t n, int64_t nste
     p.grid = grid;
     if ((e = hipMalloc(&p.d_inst, sizeof(BatchInst) * std::max<int32_t>(n, 1))) != hipSuccess ||
         (e = hipMalloc(&p.d_items, sizeof(int4) * std::max<size_t>(items.size(), 1))) != hipSuccess ||
+        (p.active && (e = hipMalloc(&p.d_compact, sizeof(int4) * std::max<size_t>(items.size(), 1))) != hipSuccess) ||
+        (p.active && (e = hipMalloc(&p.d_count, sizeof(int))) != hipSuccess) ||
         (e = hipMalloc(&p.d_bar, sizeof(unsigned))) != hipSuccess ||
         (e = hipMalloc(&p.d_err, sizeof(int))) != hipSuccess) {
         release(p);
@@ -278,13 +318,17 @@ ac_status build_plan(Plan &p, const ac_instance2d *inst, int32_t n, int64_t nste
         return hip_fail(e, "begin capture");
     }
     hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(1), 0, cs, p.d_bar);
+    if (p.active)
+        hipLaunchKernelGGL(batch_compact_kernel, dim3(1), dim3(1024), 0, cs, p.d_items, p.n_items,
+                           p.active, p.d_compact, p.d_count);
     const int nblocks = (int)c.n;
     const long long spin = g_spin_limit;
     const int cb = c.copy_back ? 1 : 0;
     const int base = (int)c.base, rem = (int)c.rem, ni = p.n_items;
-    const int *act = p.active;
-    void *args[] = {&p.d_inst, &p.d_items, (void *)&ni, (void *)&LX, (void *)&LY, (void *)&K,
-                    (void *)&nblocks, (void *)&base, (void *)&rem, (void *)&cb, (void *)&act,
+    int4 *list = p.active ? p.d_compact : p.d_items;
+    const int *cnt = p.d_count;
+    void *args[] = {&p.d_inst, &list, (void *)&ni, (void *)&LX, (void *)&LY, (void *)&K,
+                    (void *)&nblocks, (void *)&base, (void *)&rem, (void *)&cb, (void *)&cnt,
                     &p.d_bar, &p.d_err, (void *)&spin};
     hipError_t le = hipLaunchKernel(kern, dim3(grid), dim3(256), args, lds, cs);
     hipGraph_t g = nullptr;

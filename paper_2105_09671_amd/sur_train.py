@@ -165,11 +165,12 @@ def evaluate(net: Surrogate, seeds, T_blocks: int = 20, sample_every: int = 16,
     """Surrogate + judge + fallback to T versus the plain stepper, on held-out seeds.
 
     Per K-block: the surrogate advances every trusted grid; the plain stepper
-    advances a rotating 1/sample_every of the trusted grids (the judge sample)
-    and every untrusted grid, in one masked batched launch.  A sampled grid
-    keeps the plain result; if the surrogate's prediction for it fails the
-    judge (interface error > h or RMS > l2_bar) the grid is untrusted from then
-    on.  Unsampled trusted grids take the surrogate's prediction."""
+    advances the judge sample -- every grid in the first block, then a rotating
+    1/sample_every of the trusted grids -- and every untrusted grid, in one
+    masked batched launch.  A sampled grid keeps the plain result; if the
+    surrogate's prediction for it fails the judge (interface error > h or
+    RMS > l2_bar) the grid is untrusted from then on.  Unsampled trusted grids
+    take the surrogate's prediction."""
     gs, fields = grids_for(seeds)
     params = [(g.h, g.dt, g.eps) for g in gs]
     N = len(seeds)
@@ -193,41 +194,44 @@ def evaluate(net: Surrogate, seeds, T_blocks: int = 20, sample_every: int = 16,
     state = fb.phi.view(N, HW, HW)
     active = torch.zeros(N, dtype=torch.int32, device="cuda")
     fb.step_masked(K_STEPS, active)                     # builds the plan; steps nothing
-    trusted = torch.ones(N, dtype=torch.bool, device="cuda")
     pred = torch.empty_like(state)
     B = net.batch_max
     net.forward(state[:min(N, B)].contiguous(), pred[:min(N, B)])   # warm-up
     torch.cuda.synchronize()
+    # book-keeping on the host: which grids are trusted, sampled, stepped
+    trusted = np.ones(N, dtype=bool)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.int64)).cuda()
     sur_grid_blocks, judged, judged_fail = 0, 0, 0
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for k in range(T_blocks):
-        tidx = trusted.nonzero().flatten()
-        nt = int(tidx.numel())
-        if nt:
-            x = state[tidx]
+        tidx = np.nonzero(trusted)[0]
+        nt = len(tidx)
+        # the first block of every trajectory is judged for every grid; then a
+        # rotating 1/sample_every of the trusted grids
+        spos = np.arange(nt) if k == 0 else np.arange(k % sample_every, nt, sample_every)
+        kpos = np.setdiff1d(np.arange(nt), spos)
+        samp = tidx[spos]
+        if nt == N:
+            x, out = state, pred                        # every grid trusted: no gather
+        elif nt:
+            x = state.index_select(0, dev(tidx))
             out = torch.empty_like(x)
-            for s in range(0, nt, B):
-                net.forward(x[s:s + B], out[s:s + B])
-        samp = tidx[(k % sample_every)::sample_every]
-        active.zero_()
-        active[samp] = 1
-        active[~trusted] = 1
+        for s in range(0, nt, B):
+            net.forward(x[s:s + B], out[s:s + B])
+        act = ~trusted
+        act[samp] = True
+        active.copy_(torch.from_numpy(act.astype(np.int32)))
         fb.step_masked(K_STEPS, active)                 # plain: sample + untrusted, in place
-        if samp.numel():
-            pos = torch.arange(k % sample_every, nt, sample_every, device="cuda")
-            iface, l2 = api.judge2d(out[pos].contiguous(), state[samp].contiguous(), h)
-            ok = (iface <= h) & (l2 <= l2_bar)
-            judged += int(samp.numel())
-            nfail = int((~ok).sum().item())
-            judged_fail += nfail
-            if nfail:
-                trusted[samp[~ok]] = False
-        if nt:
-            keep = torch.ones(nt, dtype=torch.bool, device="cuda")
-            keep[k % sample_every::sample_every] = False
-            state[tidx[keep]] = out[keep]
-            sur_grid_blocks += int(keep.sum().item())
+        if len(samp):
+            iface, l2 = api.judge2d(out.index_select(0, dev(spos)), state.index_select(0, dev(samp)), h)
+            ok = ((iface <= h) & (l2 <= l2_bar)).cpu().numpy()
+            judged += len(samp)
+            judged_fail += int((~ok).sum())
+            trusted[samp[~ok]] = False
+        if len(kpos):
+            state.index_copy_(0, dev(tidx[kpos]), out.index_select(0, dev(kpos)))
+            sur_grid_blocks += len(kpos)
     e1.record()
     torch.cuda.synchronize()
     sur_ms = e0.elapsed_time(e1)
@@ -235,7 +239,7 @@ def evaluate(net: Surrogate, seeds, T_blocks: int = 20, sample_every: int = 16,
     iface_T, l2_T = iface_T.cpu().numpy(), l2_T.cpu().numpy()
     kinds = [g.kind for g in gs]
     ok_T = (iface_T <= h) & (l2_T <= l2_bar)
-    trusted_np = trusted.cpu().numpy()
+    trusted_np = trusted
     by_kind = {kd: {"final_ok": float(np.mean(ok_T[[i for i, x in enumerate(kinds) if x == kd]])),
                     "trusted_at_T": float(np.mean(trusted_np[[i for i, x in enumerate(kinds) if x == kd]]))}
                for kd in sorted(set(kinds))}
