@@ -37,16 +37,20 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 NSTEPS = 20000
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_tile2d_circle2048_fp32.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_2105_09671_amd", "csrc", "stencil2d.hip")
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2105_09671_amd", "csrc", f)
+               for f in ("stencil2d.hip", "tile2d.h", "ac_internal.h")]
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def src_hash(path: str) -> str:
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+def src_hash(paths) -> str:
+    h = hashlib.sha256()
+    for p in paths:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def timed(fn, reps: int):
@@ -72,7 +76,7 @@ def measured_traffic():
         return None
     with open(TRAFFIC_FILE) as f:
         t = json.load(f)
-    if t.get("src_sha256") != src_hash(KERNEL_SRC):
+    if t.get("src_sha256") != src_hash(KERNEL_SRCS):
         return None
     return t.get("hbm_bytes_per_launch")
 
@@ -82,9 +86,16 @@ def cpu_baseline(phi0, g, budget_s: float) -> dict:
     import oracle
     threads = oracle.cpus_available()
     cells = g.nx * g.ny
-    t0 = time.perf_counter()
-    oracle.step2d(phi0, g.h, g.dt, g.eps, 2, threads)
-    per = (time.perf_counter() - t0) / 2
+    # per-step cost from a probe long enough to hide thread start-up
+    probe, el = 2, 0.0
+    while True:
+        t0 = time.perf_counter()
+        oracle.step2d(phi0, g.h, g.dt, g.eps, probe, threads)
+        el = time.perf_counter() - t0
+        if el > 0.05 * budget_s or probe >= NSTEPS // 4:
+            break
+        probe *= 4
+    per = el / probe
     steps = int(max(2, min(NSTEPS, budget_s / max(per, 1e-9))))
     t0 = time.perf_counter()
     oracle.step2d(phi0, g.h, g.dt, g.eps, steps, threads)
@@ -175,6 +186,46 @@ def extras(api, torch, workloads, params) -> dict:
     t = timed(lambda: api.step2d(p1, g1.h, g1.dt, g1.eps, 500), 5)
     out["phase64_fp64"] = {"GLUPS": round(64 * 64 * 500 / t / 1e9, 3), "ms": round(t * 1e3, 3),
                            "plan": api.plan2d(64, 64, 500, torch.float64)}
+    del p1
+    out.update(hbm_resident(api, torch, workloads))
+    return out
+
+
+def hbm_resident(api, torch, workloads) -> dict:
+    """Grids far larger than the last-level cache: every launch streams its
+    tile rows from HBM.  Also the device's achievable copy bandwidth."""
+    from paper_2105_09671_amd import inputs
+    out = {}
+    n = workloads.HBM_STEPS
+    g = workloads.hbm16k()
+    t = inputs.random_field_torch((g.ny, g.nx), g.seed, g.stream, dtype=torch.float32, device="cuda")
+    api.step2d(t, g.h, g.dt, g.eps, n)
+    sec = timed(lambda: api.step2d(t, g.h, g.dt, g.eps, n), 3)
+    glups = g.nx * g.ny * n / sec / 1e9
+    out["hbm16k_fp32"] = {"GLUPS": round(glups, 2), "f_eff": round(glups * 8 / HBM_PEAK_GBS, 3),
+                          "ms": round(sec * 1e3, 2), "steps": n,
+                          "plan": api.plan2d(g.nx, g.ny, n, torch.float32)}
+    log("extra hbm16k_fp32", out["hbm16k_fp32"])
+    # achievable HBM bandwidth: a 1 GiB device-to-device copy (read + write)
+    dst = torch.empty_like(t)
+    dst.copy_(t)
+    sec = timed(lambda: dst.copy_(t), 5)
+    out["copy_1GiB"] = {"GBps": round(2 * t.numel() * 4 / sec / 1e9, 1), "ms": round(sec * 1e3, 3)}
+    log("extra copy_1GiB", out["copy_1GiB"])
+    del t, dst
+    api.release_work()
+    g3 = workloads.hbm1024c()
+    t = inputs.random_field_torch((g3.nz, g3.ny, g3.nx), g3.seed, 0, dtype=torch.float32, device="cuda")
+    api.step3d(t, g3.h, g3.dt, g3.eps, n)
+    sec = timed(lambda: api.step3d(t, g3.h, g3.dt, g3.eps, n), 3)
+    glups = g3.nx * g3.ny * g3.nz * n / sec / 1e9
+    out["hbm1024c_fp32"] = {"GLUPS": round(glups, 2), "f_eff": round(glups * 8 / HBM_PEAK_GBS, 3),
+                            "ms": round(sec * 1e3, 2), "steps": n,
+                            "plan": api.plan3d(g3.nx, g3.ny, g3.nz, n, torch.float32)}
+    log("extra hbm1024c_fp32", out["hbm1024c_fp32"])
+    del t
+    api.release_work()
+    torch.cuda.empty_cache()
     return out
 
 
@@ -243,7 +294,8 @@ def main():
     achieved = alg_bytes / avg_launch / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
-            "kernel": "tile2d_kernel<float,%d>" % plan["tile_x"],
+            "kernel": ("tile2d_inplace_kernel<float>" if plan["kernel"] == 3
+                       else "tile2d_kernel<float,%d>" % plan["tile_x"]),
             "algorithmic_bytes_per_launch": int(alg_bytes),
             "avg_launch_us": round(avg_launch * 1e6, 3), "launches_timed": launches}
 

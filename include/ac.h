@@ -97,7 +97,8 @@ ac_status ac_step_3d_tuned(void *phi, void *work, int32_t nx, int32_t ny, int32_
 enum {
     AC_KERNEL_2D_RESIDENT = 0, /* whole grid in one workgroup's LDS, all steps in one launch */
     AC_KERNEL_2D_TILED = 1,    /* LDS tiles, tb_depth steps per launch */
-    AC_KERNEL_3D_STREAM = 2    /* z-streamed tiles, tb_depth levels per launch */
+    AC_KERNEL_3D_STREAM = 2,   /* z-streamed tiles, tb_depth levels per launch */
+    AC_KERNEL_2D_INPLACE = 3   /* 64-wide LDS tiles updated in place, tb_depth steps per launch */
 };
 
 /* What a stepping call with the same arguments launches (filled by ac_plan_*). */

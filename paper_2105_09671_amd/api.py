@@ -41,6 +41,11 @@ def work_like(phi: torch.Tensor) -> torch.Tensor:
     return w
 
 
+def release_work() -> None:
+    """Drop the cached scratch buffers (they are re-created on demand)."""
+    _work_cache.clear()
+
+
 def _stream(stream) -> int:
     s = stream if stream is not None else torch.cuda.current_stream()
     return s.cuda_stream

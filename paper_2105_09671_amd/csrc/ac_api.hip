@@ -82,6 +82,45 @@ Chunks plan_chunks(int64_t nsteps, int64_t k) {
 // A plan fixes the kernel, its launch shape and the launch sequence of one
 // call.  Built on the host from the device limits; executing it makes no other
 // decision, so ac_plan_* reports exactly what ac_step_* will launch.
+// Steady-state throughput of the in-place 2D kernel on MI355X (GLUPS on a
+// 16384^2 grid, where every CU runs many tiles back to back), by depth and
+// tile height.
+struct TileRate { int K, LY; double glups; };
+static const TileRate kRateF32[] = {{6, 64, 1603}, {7, 64, 1617}, {8, 64, 1645},
+                                    {6, 128, 1682}, {7, 128, 1707}, {8, 128, 1732}};
+static const TileRate kRateF64[] = {{3, 32, 666}, {4, 32, 749}, {5, 32, 758}, {6, 32, 730},
+                                    {3, 64, 661}, {4, 64, 719}, {5, 64, 731}, {6, 64, 725}};
+
+// Predicted time of a launch ~ (rounds of resident tiles) x (time of one full
+// round), a full round taking S tiles of OX*OY*K updates at the steady rate
+// (S = resident tiles on the device).  A grid whose tile count just exceeds a
+// multiple of S pays a whole extra round, so the depth and tile height are
+// chosen per grid.
+void choose_tile2d(int nx, int ny, size_t elem, const ac::DevInfo &dev, int *K, int *LY) {
+    const TileRate *tab = elem == 8 ? kRateF64 : kRateF32;
+    const int n = elem == 8 ? (int)(sizeof kRateF64 / sizeof *kRateF64)
+                            : (int)(sizeof kRateF32 / sizeof *kRateF32);
+    double best = -1.0;
+    *K = tab[0].K;
+    *LY = tab[0].LY;
+    for (int i = 0; i < n; ++i) {
+        const int k = tab[i].K, ly = tab[i].LY;
+        const int OX = 64 - 2 * k, OY = ly - 2 * k;
+        const int64_t tiles = (int64_t)((nx + OX - 1) / OX) * ((ny + OY - 1) / OY);
+        if ((ny + OY - 1) / OY > 65535) continue;
+        const int per_cu = ac::tile2d_inplace_blocks_per_cu(ly, elem);
+        const int64_t slots = (int64_t)std::max(per_cu, 1) * std::max(dev.cus, 1);
+        const int64_t rounds = (tiles + slots - 1) / slots;
+        const double round_time = (double)slots * OX * OY * k / tab[i].glups;
+        const double rate = (double)nx * ny * k / (rounds * round_time);
+        if (rate > best) {
+            best = rate;
+            *K = k;
+            *LY = ly;
+        }
+    }
+}
+
 ac_status make_plan2d(int nx, int ny, int64_t nsteps, size_t elem, const ac_tune *tune,
                       const ac::DevInfo &dev, ac_plan *p) {
     std::memset(p, 0, sizeof *p);
@@ -97,29 +136,40 @@ ac_status make_plan2d(int nx, int ny, int64_t nsteps, size_t elem, const ac_tune
         return AC_OK;
     }
     const bool f64 = elem == 8;
-    // defaults measured on MI355X for large grids (2048^2): depth 8 / 64x64
-    // tiles in FP32, depth 4 / 64x32 in FP64
-    int K = f64 ? 4 : 8, LX = 64, LY = f64 ? 32 : 64;
+    int K = 0, LX = 64, LY = 0;
     if (tune) {
-        if (tune->tb_depth) K = tune->tb_depth;
+        K = tune->tb_depth;
         if (tune->tile_x > 0) LX = tune->tile_x;
         if (tune->tile_y > 0) LY = tune->tile_y;
+    }
+    if (!K || !LY) {
+        // default: the (depth, tile height) of the in-place kernel with the best
+        // predicted time on this grid
+        int dK = 0, dLY = 0;
+        choose_tile2d(nx, ny, elem, dev, &dK, &dLY);
+        if (!K) K = dK;
+        if (!LY) LY = dLY;
     }
     if (K < 1 || K > 8) return fail(AC_ERR_UNSUPPORTED, "tb_depth must be 1..8, got %d", K);
     if (LX < 2 * K + 1 || LY < 2 * K + 1 || LX > 4096 || LY > 4096)
         return fail(AC_ERR_UNSUPPORTED, "tile %dx%d too small/large for depth %d", LX, LY, K);
-    const size_t lds = ac::tile2d_lds_bytes(LX, LY, elem);
+    const int rch = ac::rows_per_chunk(elem);
+    // 64-wide tiles of at most 16 row chunks run in place (one LDS buffer)
+    const bool inplace = LX == 64 && (LY + rch - 1) / rch <= 16;
+    const size_t lds = inplace ? ac::tile2d_inplace_lds_bytes(LY, elem) : ac::tile2d_lds_bytes(LX, LY, elem);
     if (lds > dev.lds_per_block)
         return fail(AC_ERR_UNSUPPORTED, "tile %dx%d needs %zu B LDS > %zu", LX, LY, lds,
                     dev.lds_per_block);
     const int64_t gy = (ny + (LY - 2 * K) - 1) / (LY - 2 * K);
     if (gy > 65535) return fail(AC_ERR_UNSUPPORTED, "grid of %lld tile rows exceeds 65535", (long long)gy);
     const Chunks c = plan_chunks(nsteps, K);
-    p->kernel = AC_KERNEL_2D_TILED;
+    p->kernel = inplace ? AC_KERNEL_2D_INPLACE : AC_KERNEL_2D_TILED;
     p->tb_depth = K;
     p->tile_x = LX;
     p->tile_y = LY;
-    p->threads = 256;
+    // one wave per row chunk of the widest sub-step (in place: of the tile), at most 16
+    p->threads = inplace ? ac::tile2d_inplace_threads(LY, elem)
+                         : 64 * std::max(1, std::min(16, (LY - 2 + rch - 1) / rch));
     p->launches = nsteps > 0 ? c.n : 0;
     p->copy_back = nsteps > 0 && c.copy_back;
     p->lds_bytes = (int64_t)lds;
@@ -184,7 +234,9 @@ ac_status run2d(T *phi, T *work, int nx, int ny, double alpha_d, double r_d, int
     T *src = phi, *dst = work;
     for (int64_t i = 0; i < c.n; ++i) {
         const int k = (int)(c.base + (i < c.rem ? 1 : 0));
-        e = ac::launch_tile2d<T>(src, dst, nx, ny, alpha, r, t, k, stream);
+        e = p.kernel == AC_KERNEL_2D_INPLACE
+                ? ac::launch_tile2d_inplace<T>(src, dst, nx, ny, alpha, r, t, k, stream)
+                : ac::launch_tile2d<T>(src, dst, nx, ny, alpha, r, t, k, stream);
         if (e != hipSuccess) return hip_fail(e, "tiled 2D launch");
         T *tmp = src; src = dst; dst = tmp;
     }

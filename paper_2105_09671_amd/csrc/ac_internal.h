@@ -48,6 +48,10 @@ __device__ __forceinline__ T update3d(T c, T xm, T xp, T ym, T yp, T zm, T zp, T
 // 2D tiled kernel: each workgroup loads a (LX x LY) tile including a `halo`
 // ring, advances it `ksteps` <= halo steps in LDS (or all steps if the tile is
 // the whole grid), and stores the interior.
+// rows a lane updates per chunk of a 2D tile sub-step (registers: about 4.5
+// values per row per lane)
+__host__ __device__ inline int rows_per_chunk(size_t elem) { return elem == 8 ? 8 : 16; }
+
 struct Tile2D {
     int LX, LY, halo, threads;
 };
@@ -55,6 +59,13 @@ template <typename T>
 hipError_t launch_tile2d(const T *src, T *dst, int nx, int ny, T alpha, T r,
                          const Tile2D &t, int ksteps, hipStream_t stream);
 size_t tile2d_lds_bytes(int LX, int LY, size_t elem);
+// in-place variant (LX = 64, one LDS buffer, one row chunk per wave)
+template <typename T>
+hipError_t launch_tile2d_inplace(const T *src, T *dst, int nx, int ny, T alpha, T r,
+                                 const Tile2D &t, int ksteps, hipStream_t stream);
+size_t tile2d_inplace_lds_bytes(int LY, size_t elem);
+int tile2d_inplace_threads(int LY, size_t elem);
+int tile2d_inplace_blocks_per_cu(int LY, size_t elem);   // 0 if the query fails
 
 // 3D z-streaming kernel with K time levels pipelined along z.
 struct Tile3D {

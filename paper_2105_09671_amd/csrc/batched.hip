@@ -3,22 +3,28 @@
 //
 // Work decomposition.  Every instance is cut into the same LDS tiles as the
 // single-grid tiled kernel (tile2d.h).  One "item" is one tile of one instance;
-// the item list is the same for every temporal block of tb_depth steps.  A
-// fixed grid of workgroups, sized to what the device holds at once, walks the
-// item list for block b, meets at a grid barrier, and moves on to block b+1
-// (instances ping-pong between phi and work, so the barrier is what makes the
-// halo of block b+1 see the finished block b).
+// the item list is the same for every temporal block ("phase") of tb_depth
+// steps.  A grid of workgroups, sized to what the device holds at once, takes
+// the items of phase b from ticket counters, meets at a phase barrier, and
+// moves on to phase b+1 (instances ping-pong between phi and work, so the
+// barrier is what makes the halo of phase b+1 see the finished phase b).
 //
 // XCD-aware schedule: the dispatcher places workgroup g on XCD g mod 8, and
-// each XCD has its own L2.  The item list is split into 8 contiguous ranges
-// and XCD x's workgroups stride over range x only, so the tiles of one
-// instance -- which re-read each other's halos -- share one L2.
+// each XCD has its own L2.  The item list is split into 8 contiguous ranges,
+// each with its own ticket counter, and XCD x's workgroups take tickets of
+// range x only, so the tiles of one instance -- which re-read each other's
+// halos -- share one L2.
 //
-// The grid barrier is a monotonically increasing counter (reset by a one-thread
-// kernel captured in front of the persistent kernel).  Waits are bounded: after
-// `spin_limit` polls a workgroup raises the error flag and every workgroup
-// leaves at its next barrier, so the kernel always drains; the host reports
-// the flag through ac_check().
+// No workgroup waits for another one to start: tickets are monotonic across
+// phases (ticket t of range x is item t mod n_x of phase t / n_x), a
+// workgroup holding a ticket of a later phase keeps it until it gets there,
+// and the barrier counts finished items, not arrived workgroups.  So the
+// kernel completes whether or not every workgroup of the grid is resident at
+// once.  Waits are bounded (poll count and wall clock): a workgroup that
+// gives up raises the error flag and every workgroup leaves at its next
+// barrier, so the kernel always drains; the host reports the flag through
+// ac_check().  The counters are zeroed by a small kernel captured in front of
+// the persistent kernel.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -38,7 +44,13 @@ struct BatchInst {
     double alpha, r;
 };
 
-__global__ void batch_reset_kernel(unsigned *bar) { *bar = 0u; }
+// sync[0]: items finished (over all phases); sync[1 + x]: tickets taken from
+// XCD x's item range.
+constexpr int SYNC_WORDS = 9;
+
+__global__ void batch_reset_kernel(unsigned *sync) {
+    if (threadIdx.x < SYNC_WORDS) sync[threadIdx.x] = 0u;
+}
 
 // Masked batches: copy the items of active instances, in order, to `out` and
 // their number to *count.  One workgroup of 1024 threads scans the list in
@@ -74,19 +86,23 @@ batch_compact_kernel(const int4 *__restrict__ items, int n_items, const int *__r
     if (threadIdx.x == 0) *count = base;
 }
 
-// Returns false once any workgroup has given up waiting.
-__device__ __forceinline__ bool grid_sync(unsigned *bar, unsigned target, int *err,
-                                          long long spin_limit) {
+// End of a phase for this workgroup: publish its `mine` finished items and wait
+// until `target` items are finished in total.  Returns false once any
+// workgroup has given up waiting (after spin_limit polls or wall_limit ticks
+// of the constant-rate clock).
+__device__ __forceinline__ bool phase_sync(unsigned *done, unsigned mine, unsigned target, int *err,
+                                           long long spin_limit, long long wall_limit) {
     __shared__ int s_ok;
     __syncthreads();
     if (threadIdx.x == 0) {
         __threadfence();   // publish this workgroup's stores device-wide
-        atomicAdd(bar, 1u);
+        if (mine) atomicAdd(done, mine);
         int ok = 1;
         long long spins = 0;
-        while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        const long long t0 = wall_clock64();
+        while (__hip_atomic_load(done, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
             if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { ok = 0; break; }
-            if (++spins > spin_limit) {
+            if (++spins > spin_limit || wall_clock64() - t0 > wall_limit) {
                 atomicExch(err, 1);
                 ok = 0;
                 break;
@@ -112,42 +128,56 @@ __device__ void copy_tile(const T *src, T *dst, int nx, int ny, int OX, int OY, 
     }
 }
 
-template <typename T, int LXC>
-__global__ void __launch_bounds__(256)
+template <typename T, int LXC, bool INPLACE>
+__global__ void __launch_bounds__(1024)
 batched_kernel(const BatchInst *__restrict__ inst, const int4 *__restrict__ items, int n_items,
                int LX, int LY, int K, int nblocks, int base, int rem, int copy_back,
-               const int *__restrict__ n_active, unsigned *bar, int *err, long long spin_limit)
+               const int *__restrict__ n_active, unsigned *sync, int *err, long long spin_limit,
+               long long wall_limit)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ unsigned s_ticket;
     if (n_active) n_items = *n_active;            // masked: `items` is the compacted list
-    const int G = gridDim.x;                    // a multiple of 8
-    const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3, per = G >> 3;
+    const int xcd = blockIdx.x & 7;
     const int lo = (int)((long long)n_items * xcd / 8);
-    const int hi = (int)((long long)n_items * (xcd + 1) / 8);
-    unsigned target = 0;
-    for (int b = 0; b < nblocks; ++b) {
+    const unsigned cnt = (unsigned)((long long)n_items * (xcd + 1) / 8 - lo);
+    unsigned *tickets = sync + 1 + xcd;
+    const int phases = nblocks + (copy_back ? 1 : 0);   // copy_back: a last copy phase
+    if (threadIdx.x == 0) s_ticket = atomicAdd(tickets, 1u);
+    __syncthreads();
+    unsigned t = s_ticket;
+    for (int b = 0; b < phases; ++b) {
+        const unsigned end = (unsigned)(b + 1) * cnt;
         const int k = base + (b < rem ? 1 : 0);
-        for (int i = lo + j; i < hi; i += per) {
-            const int4 it = items[i];
+        unsigned mine = 0;
+        while (t < end) {
+            const int4 it = items[lo + (int)(t - (unsigned)b * cnt)];
+            __syncthreads();                      // every lane has read s_ticket
+            unsigned next = 0;
+            if (threadIdx.x == 0) next = atomicAdd(tickets, 1u);   // in flight during the item
             const BatchInst I = inst[it.x];
-            const T *src = static_cast<const T *>((b & 1) ? I.work : I.phi);
-            T *dst = static_cast<T *>((b & 1) ? I.phi : I.work);
-            tile2d_body<T, LXC>(src, dst, I.nx, I.ny, (T)I.alpha, (T)I.r, LX, LY, K, k, it.y,
-                                it.z, smem_raw);
-            __syncthreads();   // LDS is reused by the next item
+            if (b < nblocks) {
+                const T *src = static_cast<const T *>((b & 1) ? I.work : I.phi);
+                T *dst = static_cast<T *>((b & 1) ? I.phi : I.work);
+                if constexpr (INPLACE)
+                    tile2d_body<T, 64, Rows<T>::value, true, INPLACE_LB, INPLACE_D>(
+                        src, dst, I.nx, I.ny, (T)I.alpha, (T)I.r, 64, LY, K, k, it.y, it.z,
+                        smem_raw);
+                else
+                    tile2d_body<T, LXC>(src, dst, I.nx, I.ny, (T)I.alpha, (T)I.r, LX, LY, K, k,
+                                        it.y, it.z, smem_raw);
+            } else {   // odd number of single-step phases: the result sits in work
+                copy_tile<T>(static_cast<const T *>(I.work), static_cast<T *>(I.phi), I.nx, I.ny,
+                             LX - 2 * K, LY - 2 * K, it.y, it.z);
+            }
+            if (threadIdx.x == 0) s_ticket = next;
+            __syncthreads();                      // LDS is reused by the next item
+            t = s_ticket;
+            ++mine;
         }
-        if (b + 1 < nblocks || copy_back) {
-            target += (unsigned)G;
-            if (!grid_sync(bar, target, err, spin_limit)) return;
-        }
-    }
-    if (copy_back) {   // odd number of single-step blocks: the result sits in work
-        for (int i = lo + j; i < hi; i += per) {
-            const int4 it = items[i];
-            const BatchInst I = inst[it.x];
-            copy_tile<T>(static_cast<const T *>(I.work), static_cast<T *>(I.phi), I.nx, I.ny,
-                         LX - 2 * K, LY - 2 * K, it.y, it.z);
-        }
+        if (b + 1 < phases &&
+            !phase_sync(sync, mine, (unsigned)(b + 1) * (unsigned)n_items, err, spin_limit, wall_limit))
+            return;
     }
 }
 
@@ -213,15 +243,18 @@ void release(Plan &p) {
     p.d_bar = nullptr; p.d_err = nullptr;
 }
 
-template <typename T, int LXC>
-const void *kernel_ptr() { return (const void *)batched_kernel<T, LXC>; }
+template <typename T, int LXC, bool INPLACE = false>
+const void *kernel_ptr() { return (const void *)batched_kernel<T, LXC, INPLACE>; }
 
-const void *select_kernel(int32_t dtype, int LX) {
+// the tile body the single-grid plan chose: in place (64-wide tiles) or two buffers
+const void *select_kernel(int32_t dtype, int LX, bool inplace) {
     if (dtype == AC_F64) {
+        if (inplace) return kernel_ptr<double, 64, true>();
         if (LX == 64) return kernel_ptr<double, 64>();
         if (LX == 128) return kernel_ptr<double, 128>();
         return kernel_ptr<double, 0>();
     }
+    if (inplace) return kernel_ptr<float, 64, true>();
     if (LX == 64) return kernel_ptr<float, 64>();
     if (LX == 128) return kernel_ptr<float, 128>();
     return kernel_ptr<float, 0>();
@@ -279,11 +312,17 @@ ac_status build_plan(Plan &p, const ac_instance2d *inst, int32_t n, int64_t nste
             for (int x = 0; x < tx; ++x) items.push_back(int4{i, x, y, 0});
     }
     const Chunks c = plan_chunks(nsteps, K);
-    const void *kern = select_kernel(dtype, LX);
+    // tickets and finished-item counts are 32-bit and monotonic over the call
+    if (((double)c.n + 2.0) * (double)items.size() + 1e6 > (double)INT_MAX)
+        return fail(AC_ERR_UNSUPPORTED, "%zu tiles x %lld phases exceed the 32-bit work counters",
+                    items.size(), (long long)c.n);
+    // workgroup size and LDS follow the tile body the plan chose
+    const void *kern = select_kernel(dtype, LX, tp.kernel == AC_KERNEL_2D_INPLACE);
     const size_t lds = (size_t)tp.lds_bytes;
+    const int threads = tp.threads;
     set_lds_limit(kern, lds);
     int per_cu = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, lds);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, lds);
     if (e != hipSuccess) return hip_fail(e, "occupancy query");
     if (per_cu < 1) return fail(AC_ERR_UNSUPPORTED, "batched kernel does not fit on a CU");
     // every workgroup must be resident at once (grid barrier); 8 | grid
@@ -296,7 +335,7 @@ ac_status build_plan(Plan &p, const ac_instance2d *inst, int32_t n, int64_t nste
         (e = hipMalloc(&p.d_items, sizeof(int4) * std::max<size_t>(items.size(), 1))) != hipSuccess ||
         (p.active && (e = hipMalloc(&p.d_compact, sizeof(int4) * std::max<size_t>(items.size(), 1))) != hipSuccess) ||
         (p.active && (e = hipMalloc(&p.d_count, sizeof(int))) != hipSuccess) ||
-        (e = hipMalloc(&p.d_bar, sizeof(unsigned))) != hipSuccess ||
+        (e = hipMalloc(&p.d_bar, sizeof(unsigned) * SYNC_WORDS)) != hipSuccess ||
         (e = hipMalloc(&p.d_err, sizeof(int))) != hipSuccess) {
         release(p);
         return fail(AC_ERR_NOMEM, "batched plan allocation: %s", hipGetErrorString(e));
@@ -317,20 +356,26 @@ ac_status build_plan(Plan &p, const ac_instance2d *inst, int32_t n, int64_t nste
         release(p);
         return hip_fail(e, "begin capture");
     }
-    hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(1), 0, cs, p.d_bar);
+    hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, cs, p.d_bar);
     if (p.active)
         hipLaunchKernelGGL(batch_compact_kernel, dim3(1), dim3(1024), 0, cs, p.d_items, p.n_items,
                            p.active, p.d_compact, p.d_count);
     const int nblocks = (int)c.n;
     const long long spin = g_spin_limit;
+    // wall-clock bound of one wait: about 2 s of the constant-rate clock
+    int clock_khz = 0;
+    if (hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, p.device) != hipSuccess ||
+        clock_khz <= 0)
+        clock_khz = 100000;
+    const long long wall = g_spin_limit == 0 ? 0 : 2000LL * clock_khz;
     const int cb = c.copy_back ? 1 : 0;
     const int base = (int)c.base, rem = (int)c.rem, ni = p.n_items;
     int4 *list = p.active ? p.d_compact : p.d_items;
     const int *cnt = p.d_count;
     void *args[] = {&p.d_inst, &list, (void *)&ni, (void *)&LX, (void *)&LY, (void *)&K,
                     (void *)&nblocks, (void *)&base, (void *)&rem, (void *)&cb, (void *)&cnt,
-                    &p.d_bar, &p.d_err, (void *)&spin};
-    hipError_t le = hipLaunchKernel(kern, dim3(grid), dim3(256), args, lds, cs);
+                    &p.d_bar, &p.d_err, (void *)&spin, (void *)&wall};
+    hipError_t le = hipLaunchKernel(kern, dim3(grid), dim3(threads), args, lds, cs);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(cs, &g);
     if (le != hipSuccess || e != hipSuccess) {

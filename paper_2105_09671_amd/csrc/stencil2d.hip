@@ -35,6 +35,59 @@ tile2d_kernel(const T *src, T *dst, int nx, int ny, T alpha, T r,
                         blockIdx.y, smem_raw);
 }
 
+// In-place variant for 64-wide tiles (parameters in tile2d.h).
+
+template <typename T>
+__global__ void __launch_bounds__(1024)
+tile2d_inplace_kernel(const T *src, T *dst, int nx, int ny, T alpha, T r, int LY, int halo,
+                      int ksteps)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    tile2d_body<T, 64, Rows<T>::value, true, INPLACE_LB, INPLACE_D>(
+        src, dst, nx, ny, alpha, r, 64, LY, halo, ksteps, blockIdx.x, blockIdx.y, smem_raw);
+}
+
+size_t tile2d_inplace_lds_bytes(int LY, size_t elem) {
+    return (size_t)lds_pitch(64) * lds_rows(LY, elem) * elem;
+}
+
+int tile2d_inplace_threads(int LY, size_t elem) {
+    const int rch = rows_per_chunk(elem);
+    return 64 * ((LY + rch - 1) / rch);
+}
+
+int tile2d_inplace_blocks_per_cu(int LY, size_t elem) {
+    const void *k = elem == 8 ? (const void *)tile2d_inplace_kernel<double>
+                              : (const void *)tile2d_inplace_kernel<float>;
+    const size_t lds = tile2d_inplace_lds_bytes(LY, elem);
+    set_lds_limit(k, lds);
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, tile2d_inplace_threads(LY, elem), lds) !=
+        hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return n;
+}
+
+template <typename T>
+hipError_t launch_tile2d_inplace(const T *src, T *dst, int nx, int ny, T alpha, T r,
+                                 const Tile2D &t, int ksteps, hipStream_t stream)
+{
+    const int OX = 64 - 2 * t.halo, OY = t.LY - 2 * t.halo;
+    dim3 grid((nx + OX - 1) / OX, (ny + OY - 1) / OY);
+    const size_t lds = tile2d_inplace_lds_bytes(t.LY, sizeof(T));
+    set_lds_limit((const void *)tile2d_inplace_kernel<T>, lds);
+    hipLaunchKernelGGL(tile2d_inplace_kernel<T>, grid, dim3(t.threads), lds, stream, src, dst, nx,
+                       ny, alpha, r, t.LY, t.halo, ksteps);
+    return hipGetLastError();
+}
+
+template hipError_t launch_tile2d_inplace<float>(const float *, float *, int, int, float, float,
+                                                 const Tile2D &, int, hipStream_t);
+template hipError_t launch_tile2d_inplace<double>(const double *, double *, int, int, double,
+                                                  double, const Tile2D &, int, hipStream_t);
+
 size_t tile2d_lds_bytes(int LX, int LY, size_t elem) {
     return 2 * (size_t)lds_pitch(LX) * lds_rows(LY, elem) * elem;
 }

@@ -85,11 +85,61 @@ def _mesh3d(nx, ny, nz, h, origin=(0.0, 0.0, 0.0)):
 
 # ------------------------------------------------------- initial states ----
 
-def random_field(shape, seed: int, stream: int = 0, amp: float = 0.1) -> np.ndarray:
-    """amp * rand with rand uniform on [-1, 1), i.i.d. per cell, row-major order."""
+def random_field(shape, seed: int, stream: int = 0, amp: float = 0.1,
+                 dtype=np.float64, chunk: int = 1 << 24) -> np.ndarray:
+    """amp * rand with rand uniform on [-1, 1), i.i.d. per cell, row-major order.
+
+    The value of cell ``i`` is counter ``i`` of the stream, computed in double
+    precision; ``dtype=np.float32`` rounds each value once.  Large fields are
+    drawn ``chunk`` cells at a time, with the same result.
+    """
     n = int(np.prod(shape))
-    u = uniform01(seed, stream, n)
-    return (amp * (2.0 * u - 1.0)).reshape(shape)
+    out = np.empty(n, dtype=dtype)
+    for s in range(0, n, chunk):
+        m = min(chunk, n - s)
+        u = uniform01(seed, stream, m, start=s)
+        out[s:s + m] = amp * (2.0 * u - 1.0)
+    return out.reshape(shape)
+
+
+def _signed(c: int) -> int:
+    """A 64-bit constant as the signed integer with the same bits."""
+    return c - (1 << 64) if c >= (1 << 63) else c
+
+
+def random_field_torch(shape, seed: int, stream: int = 0, amp: float = 0.1, dtype=None,
+                       device="cpu", chunk: int = 1 << 26):
+    """``random_field`` drawn with torch on ``device`` (bit-identical values).
+
+    SplitMix64 runs on int64 tensors: products wrap modulo 2**64 as for
+    uint64, and a logical right shift is an arithmetic shift with the copied
+    sign bits masked off.  Meant for fields too large to draw quickly on the
+    host (a 1024^3 grid).
+    """
+    import torch
+    dtype = dtype or torch.float64
+    G, M1, M2 = _signed(int(GOLDEN)), _signed(int(_M1)), _signed(int(_M2))
+
+    def shr(z, k):
+        return (z >> k) & ((1 << (64 - k)) - 1)
+
+    def mix(z):
+        z = (z ^ shr(z, 30)) * M1
+        z = (z ^ shr(z, 27)) * M2
+        return z ^ shr(z, 31)
+
+    with np.errstate(over="ignore"):
+        key = _signed(int(_mix64(np.array([np.uint64(seed) * GOLDEN + np.uint64(stream)],
+                                          dtype=np.uint64))[0]))
+    n = int(np.prod(shape))
+    out = torch.empty(n, dtype=dtype, device=device)
+    for s in range(0, n, chunk):
+        m = min(chunk, n - s)
+        idx = torch.arange(s + 1, s + m + 1, dtype=torch.int64, device=device)
+        x = mix(key + idx * G)
+        u = shr(x, 11).to(torch.float64) * (2.0 ** -53)
+        out[s:s + m] = (amp * (2.0 * u - 1.0)).to(dtype)
+    return out.reshape(shape)
 
 
 def circle2d(nx, ny, h, eps, R0, centre=None) -> np.ndarray:

@@ -61,6 +61,15 @@ def _counter(d: str, kernel: str):
     return name, ker, copies
 
 
+def sources_sha256(paths) -> str:
+    """sha256 over the concatenated bytes of the given source files, in order."""
+    h = hashlib.sha256()
+    for p in paths:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
 def traffic(fetch_dir, write_dir, out, kernel, copy_bytes, alg_bytes, src, out_json, command):
     res = {}
     lines = ["# HBM traffic per dispatch of %s from rocprofv3 --pmc" % kernel,
@@ -85,9 +94,9 @@ def traffic(fetch_dir, write_dir, out, kernel, copy_bytes, alg_bytes, src, out_j
     open(out, "w").write("\n".join(lines) + "\n")
     print("\n".join(lines))
     if out_json:
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest() if src else None
+        sha = sources_sha256(src.split(",")) if src else None
         json.dump({"kernel": kernel, "counters": res, "hbm_bytes_per_launch": int(total),
-                   "algorithmic_bytes_per_launch": alg_bytes, "src": os.path.basename(src or ""),
+                   "algorithmic_bytes_per_launch": alg_bytes, "src": ",".join(os.path.basename(x) for x in src.split(",")) if src else "",
                    "src_sha256": sha, "command": command}, open(out_json, "w"), indent=1)
 
 
@@ -105,7 +114,7 @@ def main():
     f.add_argument("--kernel", required=True)
     f.add_argument("--copy-bytes", type=int, default=256 * 2 ** 20)
     f.add_argument("--alg-bytes", type=int, default=0)
-    f.add_argument("--src", default="")
+    f.add_argument("--src", default="", help="comma-separated kernel source files")
     f.add_argument("--json", default="")
     f.add_argument("--command", default="")
     a = ap.parse_args()

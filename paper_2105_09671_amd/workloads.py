@@ -11,6 +11,9 @@ involved.  Sizes follow the configurations this implementation is measured on:
                 {96,128,192,256,384,512,768,1024}, m in {3..8}, mixed
                 random / circle (R0=0.25) / star (0.3 + 0.08 cos 6θ), 5000 steps
 * ``sur256``    2D 256x256 grids for the learned K=100-step surrogate
+* ``hbm16k`` / ``hbm1024c``  HBM-resident sizes well past the last-level
+                cache: 2D 16384^2 (1 GiB per FP32 buffer, seed 5) and 3D 1024^3
+                (4 GiB per FP32 buffer, seed 6), m=4, random phi0, 200 steps
 """
 from __future__ import annotations
 
@@ -37,9 +40,9 @@ class Grid2D:
     seed: int
     stream: int = 0
 
-    def initial(self) -> np.ndarray:
+    def initial(self, dtype=np.float64) -> np.ndarray:
         if self.kind == "random":
-            return inputs.random_field((self.ny, self.nx), self.seed, self.stream)
+            return inputs.random_field((self.ny, self.nx), self.seed, self.stream, dtype=dtype)
         if self.kind == "circle":
             return inputs.circle2d(self.nx, self.ny, self.h, self.eps, 0.25)
         if self.kind == "star":
@@ -72,9 +75,9 @@ class Grid3D:
     seed: int
     R0: float = 0.3
 
-    def initial(self) -> np.ndarray:
+    def initial(self, dtype=np.float64) -> np.ndarray:
         if self.kind == "random":
-            return inputs.random_field((self.nz, self.ny, self.nx), self.seed, 0)
+            return inputs.random_field((self.nz, self.ny, self.nx), self.seed, 0, dtype=dtype)
         if self.kind == "sphere":
             return inputs.sphere3d(self.nx, self.ny, self.nz, self.h, self.eps, self.R0)
         raise ValueError(self.kind)
@@ -91,6 +94,17 @@ def sep256c(n: int = 256) -> Grid3D:
 
 def sphere256(n: int = 256) -> Grid3D:
     return unit_grid3d(n, 4, "sphere")
+
+
+HBM_STEPS = 200
+
+
+def hbm16k(n: int = 16384) -> Grid2D:
+    return unit_grid2d(n, 4, "random", seed=5)
+
+
+def hbm1024c(n: int = 1024) -> Grid3D:
+    return unit_grid3d(n, 4, "random", seed=6)
 
 
 def batch_instances(n_inst: int = 512, seed: int = 4, sides=SIDES,

@@ -99,3 +99,68 @@ def test_sphere256_radius_law(api):
     api.step3d(t, g.h, g.dt, g.eps, 2000)
     R = D.volume_radius(t.cpu().numpy(), g.h)
     assert abs(R - D.radius_law(0.3, 2000 * g.dt, 3)) <= g.h
+
+
+def _windowed_parity(t, wins, nsteps, run, step, f32):
+    """Parity of an in-place GPU run on sampled windows.
+
+    Each window is checked against the oracle run on a crop of phi0 that
+    extends it by nsteps cells on every side (clipped at the domain).  A 5/7-
+    point step moves information one cell per step, so the crop's artificial
+    Neumann faces cannot reach the window: the cropped oracle is exact there.
+    Returns (rel. L-inf error, the oracle's one-FP32-ulp sensitivity or 0)."""
+    shape = t.shape
+    crops = [tuple(slice(max(a - nsteps, 0), min(b + nsteps, n)) for (a, b), n in zip(w, shape))
+             for w in wins]
+    phi0 = [t[c].cpu().numpy().copy() for c in crops]
+    run()
+    err = sens = 0.0
+    for w, c, p in zip(wins, crops, phi0):
+        inner = tuple(slice(a - s.start, b - s.start) for (a, b), s in zip(w, c))
+        got = t[tuple(slice(a, b) for a, b in w)].cpu().numpy().astype(np.float64)
+        ref = step(p.astype(np.float64), nsteps)[inner]
+        err = max(err, D.rel_linf(got, ref))
+        if f32:
+            refp = step(_ulp_perturbed(p).astype(np.float64), nsteps)[inner]
+            sens = max(sens, D.rel_linf(refp, ref))
+    return err, sens
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_hbm16k_windows(api, dtype):
+    """2D 16384^2 random start (1 GiB per FP32 buffer), 200 steps, default
+    plan: three 160x160 windows (corner, interior across tile seams, far
+    corner).  At 200 steps the random start is in the middle of phase
+    separation, which amplifies perturbations: the FP32 bar is
+    max(1e-5, sens) as for the other random starts."""
+    from paper_2105_09671_amd import inputs
+    g, n = workloads.hbm16k(), workloads.HBM_STEPS
+    t = inputs.random_field_torch((g.ny, g.nx), g.seed, g.stream, dtype=dtype, device="cuda")
+    N = g.nx
+    wins = [((0, 160), (0, 160)), ((8150, 8310), (7000, 7160)), ((N - 160, N), (N - 160, N))]
+    err, sens = _windowed_parity(t, wins, n, lambda: api.step2d(t, g.h, g.dt, g.eps, n),
+                                 lambda p, k: oracle.step2d(p, g.h, g.dt, g.eps, k, THREADS),
+                                 dtype == torch.float32)
+    del t
+    api.release_work()
+    print("hbm16k %s windows rel Linf %.3g (1-ulp sensitivity %.3g)" % (dtype, err, sens))
+    assert err <= (1e-12 if dtype == torch.float64 else max(1e-5, sens))
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_hbm1024c_windows(api, dtype):
+    """3D 1024^3 random start (4 GiB per FP32 buffer), 200 steps, default
+    plan: three 12^3 windows, bars as for the 2D HBM-resident grid."""
+    from paper_2105_09671_amd import inputs
+    g, n = workloads.hbm1024c(), workloads.HBM_STEPS
+    t = inputs.random_field_torch((g.nz, g.ny, g.nx), g.seed, 0, dtype=dtype, device="cuda")
+    N = g.nx
+    wins = [((0, 12), (0, 12), (0, 12)), ((500, 512), (530, 542), (28, 40)),
+            ((N - 12, N), (N - 12, N), (N - 12, N))]
+    err, sens = _windowed_parity(t, wins, n, lambda: api.step3d(t, g.h, g.dt, g.eps, n),
+                                 lambda p, k: oracle.step3d(p, g.h, g.dt, g.eps, k, THREADS),
+                                 dtype == torch.float32)
+    del t
+    api.release_work()
+    print("hbm1024c %s windows rel Linf %.3g (1-ulp sensitivity %.3g)" % (dtype, err, sens))
+    assert err <= (1e-12 if dtype == torch.float64 else max(1e-5, sens))

@@ -262,3 +262,25 @@ def test_thread_count_does_not_change_result(oracle_mod):
     phi3 = inputs.random_field((10, 12, 14), seed=8)
     assert np.array_equal(oracle_mod.step3d(phi3, h, dt, eps, 10, 1),
                           oracle_mod.step3d(phi3, h, dt, eps, 10, 4))
+
+
+def test_crop_locality(oracle_mod):
+    """After n steps a cell depends only on cells within n of it (one cell per
+    step along each axis): running on a crop that extends a window by n cells
+    gives the window exactly.  The full-size GPU checks rely on this."""
+    n = 7
+    p2 = inputs.random_field((40, 44), seed=21, amp=0.6)
+    full = oracle_mod.step2d(p2, 1 / 44, 0.1 / 44 ** 2, params.eps_m(1 / 44, 3), n)
+    crop = oracle_mod.step2d(np.ascontiguousarray(p2[3:32, 10:30]), 1 / 44, 0.1 / 44 ** 2,
+                             params.eps_m(1 / 44, 3), n)
+    assert np.array_equal(full[10:25, 17:23], crop[7:22, 7:13])
+    # one cell fewer of margin is not enough
+    crop1 = oracle_mod.step2d(np.ascontiguousarray(p2[4:31, 11:29]), 1 / 44, 0.1 / 44 ** 2,
+                              params.eps_m(1 / 44, 3), n)
+    assert not np.array_equal(full[10:25, 17:23], crop1[6:21, 6:12])
+    p3 = inputs.random_field((20, 21, 22), seed=22, amp=0.6)
+    h = 1 / 22
+    full3 = oracle_mod.step3d(p3, h, 0.1 * h * h, params.eps_m(h, 3), n)
+    crop3 = oracle_mod.step3d(np.ascontiguousarray(p3[0:15, 5:20, 8:22]), h, 0.1 * h * h,
+                              params.eps_m(h, 3), n)
+    assert np.array_equal(full3[0:8, 12:13, 15:22], crop3[0:8, 7:8, 7:14])
