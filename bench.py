@@ -36,7 +36,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 NSTEPS = 20000
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_tile2d_circle2048_fp32.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_tile2d_inplace_circle2048_fp32.json")
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2105_09671_amd", "csrc", f)
                for f in ("stencil2d.hip", "tile2d.h", "ac_internal.h")]
 

@@ -82,8 +82,10 @@ static ac_status sweep(const std::vector<ac_tune> &cands, hipStream_t st, F fn, 
 
 static std::vector<ac_tune> cands2d() {
     std::vector<ac_tune> v;
-    const int tiles[][2] = {{64, 32}, {64, 64}, {128, 32}, {128, 64}, {64, 128}};
-    for (int k : {2, 4, 6, 8})
+    // 64-wide tiles run in place with one wave per 16 (FP32) or 8 (FP64) rows;
+    // heights that are multiples of 4 waves keep the SIMDs of a CU balanced
+    const int tiles[][2] = {{64, 32}, {64, 64}, {64, 128}, {128, 64}};
+    for (int k : {3, 4, 5, 6, 7, 8})
         for (auto &t : tiles) v.push_back(ac_tune{k, t[0], t[1], 0});
     return v;
 }
