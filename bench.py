@@ -188,6 +188,11 @@ def extras(api, torch, workloads, params) -> dict:
                            "plan": api.plan2d(64, 64, 500, torch.float64)}
     del p1
     out.update(hbm_resident(api, torch, workloads))
+    # the paper's own workloads at its tables' step counts (its times: other
+    # hardware, context only)
+    from paper_2105_09671_amd import paper_suite
+    out["paper_suite_fp32"] = paper_suite.timings(torch.float32)
+    log("extra paper_suite_fp32", out["paper_suite_fp32"])
     return out
 
 
