@@ -234,6 +234,25 @@ ac_status ac_sur_get_grads(ac_sur *s, float *host, int64_t n);
 /* one Adam update (bias-corrected, step t >= 1) of the FP32 master weights */
 ac_status ac_sur_adam_step(ac_sur *s, float lr, float b1, float b2, float eps_adam, int64_t t);
 
+/* ------------------------------------------------------- precision trace ----
+ * The paper's Err (section 2, Eq. ERReq) between FP32 and FP64 runs of the
+ * explicit step: both fields advance nsteps steps together (one launch per
+ * step, no temporal blocking), and after step t (t = 1..nsteps)
+ *   rms[t-1] = sqrt(mean over cells of (phi32 - phi64)^2)   (FP64)
+ * and *err = the mean of rms over the nsteps steps.  phi32/work32 (float) and
+ * phi64/work64 (double) are caller-owned device buffers of nx*ny(*nz) cells,
+ * pairwise disjoint and 16-byte aligned; the final states end in phi32 and
+ * phi64.  rms (nsteps doubles) and err (one double) are device memory.  The
+ * FP32 path computes exactly what ac_step_2d / ac_step_3d compute in FP32 (the
+ * same update, bit for bit); the FP64 path that of the FP64 call.  h, dt, eps
+ * are validated as for the stepping calls; nsteps = 0 sets *err = 0. */
+ac_status ac_err_2d(float *phi32, float *work32, double *phi64, double *work64, int32_t nx,
+                    int32_t ny, double h, double dt, double eps, int64_t nsteps, double *rms,
+                    double *err, void *stream);
+ac_status ac_err_3d(float *phi32, float *work32, double *phi64, double *work64, int32_t nx,
+                    int32_t ny, int32_t nz, double h, double dt, double eps, int64_t nsteps,
+                    double *rms, double *err, void *stream);
+
 /* ---------------------------------------------------------------- judge ----
  * Per grid of a batch of 2D FP32 fields a (candidate) and b (reference), both
  * [batch][ny][nx] on the device: iface_err[n] = Hausdorff distance between the

@@ -106,6 +106,9 @@ SIGNATURES = {
     "ac_sur_adam_step": ([_vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                           _i64], _i32),
     "ac_judge_2d": ([_vp, _vp, _i32, _i32, _i32, _dbl, _i32, _vp, _vp, _vp, _vp], _i32),
+    "ac_err_2d": ([_vp, _vp, _vp, _vp, _i32, _i32, _dbl, _dbl, _dbl, _i64, _vp, _vp, _vp], _i32),
+    "ac_err_3d": ([_vp, _vp, _vp, _vp, _i32, _i32, _i32, _dbl, _dbl, _dbl, _i64, _vp, _vp, _vp],
+                  _i32),
     "ac_judge_workspace_bytes": ([_i32], _i64),
     "ac_check": ([_vp], _i32),
     "ac_status_string": ([_i32], ctypes.c_char_p),

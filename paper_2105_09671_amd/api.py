@@ -221,3 +221,32 @@ def judge2d(a: torch.Tensor, b: torch.Tensor, h: float, window: int = 3, stream=
                                 iface.data_ptr(), l2.data_ptr(), ws.data_ptr(), _stream(stream)),
             "ac_judge_2d")
     return iface, l2
+
+
+def err_trace(phi32: torch.Tensor, phi64: torch.Tensor, h: float, dt: float, eps: float,
+              nsteps: int, stream=None):
+    """Advance an FP32 and an FP64 copy of one grid together by nsteps steps,
+    in place, and return (rms, err): rms[t] is the RMS difference of the two
+    states after step t + 1 (a device FP64 tensor), err its mean -- the
+    paper's Err (Eq. ERReq) between the two precisions."""
+    if phi32.dtype != torch.float32 or phi64.dtype != torch.float64:
+        raise TypeError("phi32 must be float32 and phi64 float64")
+    if phi32.shape != phi64.shape or phi32.dim() not in (2, 3):
+        raise ValueError("phi32 and phi64 must be 2D or 3D grids of one shape")
+    _check_tensor(phi32, phi32.dim())
+    _check_tensor(phi64, phi64.dim())
+    w32, w64 = torch.empty_like(phi32), torch.empty_like(phi64)
+    rms = torch.empty(max(int(nsteps), 1), dtype=torch.float64, device=phi32.device)
+    err = torch.empty(1, dtype=torch.float64, device=phi32.device)
+    if phi32.dim() == 2:
+        ny, nx = phi32.shape
+        st = L.lib().ac_err_2d(phi32.data_ptr(), w32.data_ptr(), phi64.data_ptr(), w64.data_ptr(),
+                               nx, ny, float(h), float(dt), float(eps), int(nsteps),
+                               rms.data_ptr(), err.data_ptr(), _stream(stream))
+    else:
+        nz, ny, nx = phi32.shape
+        st = L.lib().ac_err_3d(phi32.data_ptr(), w32.data_ptr(), phi64.data_ptr(), w64.data_ptr(),
+                               nx, ny, nz, float(h), float(dt), float(eps), int(nsteps),
+                               rms.data_ptr(), err.data_ptr(), _stream(stream))
+    L.check(st, "ac_err")
+    return rms[:int(nsteps)], float(err.item())

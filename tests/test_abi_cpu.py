@@ -148,3 +148,25 @@ def test_tune_table_json_roundtrip(lib, tmp_path):
     assert lib.ac_tune_load(str(bad).encode()) == L.AC_ERR_INVALID_ARG
     assert lib.ac_tune_load(b"/nonexistent/x.json") == L.AC_ERR_INVALID_ARG
     lib.ac_tune_clear()
+
+
+# precision trace: FP32 pair A, B; FP64 pair C, D; rms and err slots R, E
+C, D, R, E = 0x30000000, 0x40000000, 0x50000000, 0x60000000
+
+
+def e2(lib, p32=A, w32=B, p64=C, w64=D, nx=64, ny=64, h=H, dt=DT, eps=EPS, n=10, rms=R, err=E):
+    return lib.ac_err_2d(p32, w32, p64, w64, nx, ny, h, dt, eps, n, rms, err, None)
+
+
+@pytest.mark.parametrize("kw", [dict(p64=A), dict(w64=B + 64), dict(p64=0), dict(w32=A),
+                                dict(nx=0), dict(rms=0), dict(err=0), dict(eps=float("nan")),
+                                dict(n=-1), dict(p32=A + 4)])
+def test_precision_trace_rejects_bad_arguments(lib, kw):
+    assert e2(lib, **kw) == L.AC_ERR_INVALID_ARG
+    assert lib.ac_last_error()
+
+
+def test_precision_trace_stability_gate(lib):
+    assert e2(lib, dt=0.3 * H * H) == L.AC_ERR_UNSTABLE
+    assert lib.ac_err_3d(A, B, C, D, 8, 8, 8, H, 0.2 * H * H, EPS, 10, R, E, None) == L.AC_ERR_UNSTABLE
+    assert lib.ac_err_3d(A, B, C, D, 8, 0, 8, H, DT, EPS, 10, R, E, None) == L.AC_ERR_INVALID_ARG
