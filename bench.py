@@ -180,6 +180,17 @@ def extras(api, torch, workloads, params) -> dict:
                                  "frac": round(out["sur256"]["forward"]["TFLOPs"] / 2500.0, 4)}
     net.close()
     log("extra sur256", {k: v for k, v in out["sur256"].items() if k != "by_kind"})
+    # 64 independent 3D grids (sides 24..128), 1000 steps, one persistent launch
+    insts3 = workloads.batch3d_instances(64)
+    b3 = api.Batch3D([g3.initial().astype("float32") for g3 in insts3],
+                     [(g3.h, g3.dt, g3.eps) for g3 in insts3])
+    info3 = b3.step(1000)
+    t = timed(lambda: b3.step(1000), 3)
+    glups = b3.cells * 1000 / t / 1e9
+    out["batch3d64_fp32"] = {"GLUPS": round(glups, 2), "f_eff": round(glups * 8 / HBM_PEAK_GBS, 3),
+                             "ms": round(t * 1e3, 2), "cells": b3.cells, "launch": info3}
+    log("extra batch3d64_fp32", out["batch3d64_fp32"])
+    del b3
     # 64x64 FP64 phase separation, 500 steps, one LDS-resident launch
     g1 = workloads.phase64()
     p1 = torch.from_numpy(g1.initial()).cuda()

@@ -170,6 +170,25 @@ ac_status ac_step_batched_masked(const ac_instance2d *inst, int32_t n_inst, int6
                                  int32_t dtype, const ac_tune *tune, const int32_t *active,
                                  ac_batch_info *info, void *stream);
 
+/* A 3D instance: its own grid nx x ny x nz (x fastest), h, dt and eps. */
+typedef struct {
+    void *phi, *work;
+    int32_t nx, ny, nz;
+    double h, dt, eps;
+} ac_instance3d;
+
+/* Advance every 3D instance by nsteps in one persistent launch (the
+ * z-streamed 7-point tile of ac_step_3d, one item per (instance, xy tile, z
+ * segment)), captured in a hipGraph and cached like the 2D batch.  Validation
+ * as in ac_step_3d per instance, no two buffers may overlap.  The launch shape
+ * comes from `tune` (tb_depth 1..4, tile_x, tile_y, tile_z), else the 3D
+ * defaults; nsteps not divisible by tb_depth adds one shorter phase.  Result
+ * in each phi.  Each instance is stepped exactly as ac_step_3d steps it, bit
+ * for bit (the update of a cell does not depend on tile shape or depth). */
+ac_status ac_step_batched_3d(const ac_instance3d *inst, int32_t n_inst, int64_t nsteps,
+                             int32_t dtype, const ac_tune *tune, ac_batch_info *info,
+                             void *stream);
+
 /* Free every cached batched plan (synchronises the device). */
 ac_status ac_batched_release(void);
 

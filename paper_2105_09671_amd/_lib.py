@@ -43,6 +43,12 @@ class AcInstance2D(ctypes.Structure):
                 ("eps", ctypes.c_double)]
 
 
+class AcInstance3D(ctypes.Structure):
+    _fields_ = [("phi", ctypes.c_void_p), ("work", ctypes.c_void_p), ("nx", ctypes.c_int32),
+                ("ny", ctypes.c_int32), ("nz", ctypes.c_int32), ("h", ctypes.c_double),
+                ("dt", ctypes.c_double), ("eps", ctypes.c_double)]
+
+
 class AcBatchInfo(ctypes.Structure):
     _fields_ = [("grid", ctypes.c_int32), ("items", ctypes.c_int32), ("tb_depth", ctypes.c_int32),
                 ("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32), ("blocks", ctypes.c_int32),
@@ -81,6 +87,8 @@ SIGNATURES = {
     "ac_step_batched": ([ctypes.POINTER(AcInstance2D), _i32, _i64, _i32, _vp], _i32),
     "ac_step_batched_tuned": ([ctypes.POINTER(AcInstance2D), _i32, _i64, _i32,
                                ctypes.POINTER(AcTune), ctypes.POINTER(AcBatchInfo), _vp], _i32),
+    "ac_step_batched_3d": ([ctypes.POINTER(AcInstance3D), _i32, _i64, _i32,
+                            ctypes.POINTER(AcTune), ctypes.POINTER(AcBatchInfo), _vp], _i32),
     "ac_step_batched_masked": ([ctypes.POINTER(AcInstance2D), _i32, _i64, _i32,
                                 ctypes.POINTER(AcTune), _vp, ctypes.POINTER(AcBatchInfo), _vp], _i32),
     "ac_batched_release": ([], _i32),

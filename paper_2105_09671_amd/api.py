@@ -178,6 +178,49 @@ class Batch:
         return {k: getattr(best, k) for k, _ in best._fields_}
 
 
+class Batch3D:
+    """Independent 3D grids packed into one phi and one work buffer; ``fields``
+    are (nz, ny, nx) arrays, ``params`` (h, dt, eps) per grid."""
+
+    def __init__(self, fields, params, dtype=torch.float32, device="cuda"):
+        import numpy as np
+        self.dtype = dtype
+        align = 256 // torch.tensor([], dtype=dtype).element_size()
+        self.shapes = [tuple(np.shape(f)) for f in fields]
+        self.offsets, off = [], 0
+        for sh in self.shapes:
+            self.offsets.append(off)
+            off += (int(np.prod(sh)) + align - 1) // align * align
+        host = torch.zeros(off, dtype=dtype)
+        for f, o, sh in zip(fields, self.offsets, self.shapes):
+            n = int(np.prod(sh))
+            host[o:o + n] = torch.as_tensor(np.ascontiguousarray(f).ravel(), dtype=dtype)
+        self.phi = host.to(device)
+        self.work = torch.empty_like(self.phi)
+        self.params = [tuple(float(v) for v in p) for p in params]
+        elem = self.phi.element_size()
+        self._arr = (L.AcInstance3D * len(self.shapes))()
+        for i, ((nz, ny, nx), o, (h, dt, eps)) in enumerate(zip(self.shapes, self.offsets, self.params)):
+            self._arr[i] = L.AcInstance3D(self.phi.data_ptr() + o * elem,
+                                          self.work.data_ptr() + o * elem, nx, ny, nz, h, dt, eps)
+
+    @property
+    def cells(self) -> int:
+        return sum(nx * ny * nz for (nz, ny, nx) in self.shapes)
+
+    def views(self):
+        return [self.phi[o:o + nz * ny * nx].view(nz, ny, nx)
+                for o, (nz, ny, nx) in zip(self.offsets, self.shapes)]
+
+    def step(self, nsteps: int, tune=None, stream=None) -> dict:
+        info = L.AcBatchInfo()
+        st = L.lib().ac_step_batched_3d(self._arr, len(self.shapes), int(nsteps),
+                                        _dtype_code(self.phi), _tune(tune), ctypes.byref(info),
+                                        _stream(stream))
+        L.check(st, "ac_step_batched_3d")
+        return info.as_dict()
+
+
 def autotune2d(nx: int, ny: int, dtype=torch.float32, probe_steps: int = 200, stream=None) -> dict:
     best = L.AcTune()
     code = L.AC_F64 if dtype == torch.float64 else L.AC_F32

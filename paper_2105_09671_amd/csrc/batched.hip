@@ -34,6 +34,7 @@
 #include <mutex>
 #include <vector>
 
+#include "stream3d.h"
 #include "tile2d.h"
 
 namespace ac {
@@ -42,6 +43,7 @@ struct BatchInst {
     void *phi, *work;
     int nx, ny;
     double alpha, r;
+    int nz, tiles_x;   // 3D batches: depth and xy tiles along x
 };
 
 // sync[0]: items finished (over all phases); sync[1 + x]: tickets taken from
@@ -181,6 +183,70 @@ batched_kernel(const BatchInst *__restrict__ inst, const int4 *__restrict__ item
     }
 }
 
+// Copy the output region of one 3D item (xy tile, z segment) from src to dst.
+template <typename T>
+__device__ void copy_tile3d(const T *src, T *dst, int nx, int ny, int nz, int OX, int OY, int LZ,
+                            int tiles_x, int tile, int zseg) {
+    const int x0 = (tile % tiles_x) * OX, y0 = (tile / tiles_x) * OY, z0 = zseg * LZ;
+    const int w = min(x0 + OX, nx) - x0, hh = min(y0 + OY, ny) - y0, d = min(z0 + LZ, nz) - z0;
+    const long long n = (long long)w * hh * d;
+    for (long long i = threadIdx.x; i < n; i += blockDim.x) {
+        const int x = x0 + (int)(i % w), y = y0 + (int)((i / w) % hh), z = z0 + (int)(i / ((long long)w * hh));
+        const size_t c = ((size_t)z * ny + y) * nx + x;
+        dst[c] = src[c];
+    }
+}
+
+// 3D batch: items (instance, xy tile, z segment, -); every phase advances each
+// item by K steps with the z-streaming body of ac_step_3d.  Phases are
+// numbered from phase0 for the phi/work ping-pong, so a second launch can run
+// a shorter remainder phase.  Scheduling as in batched_kernel.
+template <typename T, int K, int CPT>
+__global__ void __launch_bounds__(512)
+batched3d_kernel(const BatchInst *__restrict__ inst, const int4 *__restrict__ items, int n_items,
+                 int LX, int LY, int LZ, int nphase, int phase0, int copy_back, unsigned *sync,
+                 int *err, long long spin_limit, long long wall_limit)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ unsigned s_ticket;
+    const int xcd = blockIdx.x & 7;
+    const int lo = (int)((long long)n_items * xcd / 8);
+    const unsigned cnt = (unsigned)((long long)n_items * (xcd + 1) / 8 - lo);
+    unsigned *tickets = sync + 1 + xcd;
+    const int phases = nphase + (copy_back ? 1 : 0);
+    if (threadIdx.x == 0) s_ticket = atomicAdd(tickets, 1u);
+    __syncthreads();
+    unsigned t = s_ticket;
+    for (int b = 0; b < phases; ++b) {
+        const unsigned end = (unsigned)(b + 1) * cnt;
+        unsigned mine = 0;
+        while (t < end) {
+            const int4 it = items[lo + (int)(t - (unsigned)b * cnt)];
+            __syncthreads();                      // every lane has read s_ticket
+            unsigned next = 0;
+            if (threadIdx.x == 0) next = atomicAdd(tickets, 1u);
+            const BatchInst I = inst[it.x];
+            if (b < nphase) {
+                const int g = phase0 + b;
+                const T *src = static_cast<const T *>((g & 1) ? I.work : I.phi);
+                T *dst = static_cast<T *>((g & 1) ? I.phi : I.work);
+                stream3d_body<T, K, CPT>(src, dst, I.nx, I.ny, I.nz, (T)I.alpha, (T)I.r, LX, LY,
+                                         LZ, I.tiles_x, it.y, it.z, smem_raw);
+            } else {
+                copy_tile3d<T>(static_cast<const T *>(I.work), static_cast<T *>(I.phi), I.nx, I.ny,
+                               I.nz, LX - 2 * K, LY - 2 * K, LZ, I.tiles_x, it.y, it.z);
+            }
+            if (threadIdx.x == 0) s_ticket = next;
+            __syncthreads();
+            t = s_ticket;
+            ++mine;
+        }
+        if (b + 1 < phases &&
+            !phase_sync(sync, mine, (unsigned)(b + 1) * (unsigned)n_items, err, spin_limit, wall_limit))
+            return;
+    }
+}
+
 // ---------------------------------------------------------------- host ----
 
 namespace {
@@ -189,7 +255,9 @@ long long g_spin_limit = 20000000;   // ~2 s of polling per barrier
 
 struct Plan {
     // key
+    int dim = 2;
     std::vector<ac_instance2d> inst;
+    std::vector<ac_instance3d> inst3;
     int64_t nsteps;
     int32_t dtype;
     ac_tune tune;
@@ -220,7 +288,7 @@ bool same_inst(const ac_instance2d &a, const ac_instance2d &b) {
 
 bool key_equal(const Plan &p, const ac_instance2d *inst, int32_t n, int64_t nsteps,
                int32_t dtype, const ac_tune &t, const int *active, int dev) {
-    if (p.device != dev || p.nsteps != nsteps || p.dtype != dtype || (int32_t)p.inst.size() != n ||
+    if (p.dim != 2 || p.device != dev || p.nsteps != nsteps || p.dtype != dtype || (int32_t)p.inst.size() != n ||
         p.active != active)
         return false;
     if (std::memcmp(&p.tune, &t, sizeof t) != 0) return false;
@@ -401,6 +469,190 @@ ac_status build_plan(Plan &p, const ac_instance2d *inst, int32_t n, int64_t nste
     return AC_OK;
 }
 
+bool same_inst3(const ac_instance3d &a, const ac_instance3d &b) {
+    return a.phi == b.phi && a.work == b.work && a.nx == b.nx && a.ny == b.ny && a.nz == b.nz &&
+           a.h == b.h && a.dt == b.dt && a.eps == b.eps;
+}
+
+bool key_equal3(const Plan &p, const ac_instance3d *inst, int32_t n, int64_t nsteps, int32_t dtype,
+                const ac_tune &t, int dev) {
+    if (p.dim != 3 || p.device != dev || p.nsteps != nsteps || p.dtype != dtype ||
+        (int32_t)p.inst3.size() != n)
+        return false;
+    if (std::memcmp(&p.tune, &t, sizeof t) != 0) return false;
+    for (int32_t i = 0; i < n; ++i)
+        if (!same_inst3(p.inst3[i], inst[i])) return false;
+    return true;
+}
+
+ac_status validate_batch3(const ac_instance3d *inst, int32_t n, int64_t nsteps, int32_t dtype,
+                          std::vector<double> *alpha, std::vector<double> *r) {
+    if (n < 0 || (n > 0 && !inst)) return fail(AC_ERR_INVALID_ARG, "bad instance array");
+    alpha->resize(n);
+    r->resize(n);
+    std::vector<std::pair<uintptr_t, uintptr_t>> ranges;
+    ranges.reserve(2 * (size_t)n);
+    for (int32_t i = 0; i < n; ++i) {
+        const ac_instance3d &I = inst[i];
+        if (I.nx < 1 || I.ny < 1 || I.nz < 1)
+            return fail(AC_ERR_INVALID_ARG, "instance %d: nx, ny, nz must be >= 1", i);
+        const int64_t cells = (int64_t)I.nx * I.ny * I.nz;
+        ac_status s = validate(I.phi, I.work, cells, 3, I.h, I.dt, I.eps, nsteps, dtype,
+                               &(*alpha)[i], &(*r)[i]);
+        if (s != AC_OK) {
+            std::string m = g_err;
+            return fail(s, "instance %d: %s", i, m.c_str());
+        }
+        const size_t bytes = (size_t)cells * elem_size(dtype);
+        ranges.push_back({(uintptr_t)I.phi, (uintptr_t)I.phi + bytes});
+        ranges.push_back({(uintptr_t)I.work, (uintptr_t)I.work + bytes});
+    }
+    std::sort(ranges.begin(), ranges.end());
+    for (size_t i = 1; i < ranges.size(); ++i)
+        if (ranges[i].first < ranges[i - 1].second)
+            return fail(AC_ERR_INVALID_ARG, "instance buffers overlap");
+    return AC_OK;
+}
+
+template <typename T, int K>
+const void *kernel3_cpt(int cpt) {
+    if (cpt <= 1) return (const void *)batched3d_kernel<T, K, 1>;
+    if (cpt <= 2) return (const void *)batched3d_kernel<T, K, 2>;
+    if (cpt <= 4) return (const void *)batched3d_kernel<T, K, 4>;
+    return nullptr;
+}
+
+template <typename T>
+const void *kernel3_of(int K, int cpt) {
+    switch (K) {
+    case 1: return kernel3_cpt<T, 1>(cpt);
+    case 2: return kernel3_cpt<T, 2>(cpt);
+    case 3: return kernel3_cpt<T, 3>(cpt);
+    case 4: return kernel3_cpt<T, 4>(cpt);
+    default: return nullptr;
+    }
+}
+
+ac_status build_plan3d(Plan &p, const ac_instance3d *inst, int32_t n, int64_t nsteps,
+                       int32_t dtype, const ac_tune &tune, const std::vector<double> &alpha,
+                       const std::vector<double> &r, const DevInfo &dev) {
+    const size_t elem = elem_size(dtype);
+    ac_plan tp;
+    ac_status s = make_plan3d(256, 256, 256, nsteps, elem, &tune, dev, &tp);
+    if (s != AC_OK) return s;
+    const int LX = tp.tile_x, LY = tp.tile_y, LZ = tp.tile_z, K = tp.tb_depth, threads = tp.threads;
+    if (K > 4) return fail(AC_ERR_UNSUPPORTED, "batched 3D supports tb_depth 1..4, got %d", K);
+    const int OX = LX - 2 * K, OY = LY - 2 * K;
+    Tile3D t3{LX, LY, LZ, K, threads};
+    const int cpt = stream3d_cells_per_thread(t3);
+    std::vector<BatchInst> hi(n);
+    std::vector<int4> items;
+    for (int32_t i = 0; i < n; ++i) {
+        const int tx = (inst[i].nx + OX - 1) / OX, ty = (inst[i].ny + OY - 1) / OY;
+        const int tz = (inst[i].nz + LZ - 1) / LZ;
+        hi[i] = BatchInst{inst[i].phi, inst[i].work, inst[i].nx, inst[i].ny, alpha[i], r[i],
+                          inst[i].nz, tx};
+        for (int z = 0; z < tz; ++z)
+            for (int y = 0; y < ty; ++y)
+                for (int x = 0; x < tx; ++x) items.push_back(int4{i, y * tx + x, z, 0});
+    }
+    // whole phases of K steps, then one phase of the remaining steps
+    const int64_t q = nsteps / K, rem = nsteps % K;
+    const int64_t phases = q + (rem ? 1 : 0);
+    const int cb = (int)(phases & 1);                 // result in work: a final copy phase
+    if (((double)phases + 2.0) * (double)items.size() + 1e6 > (double)INT_MAX)
+        return fail(AC_ERR_UNSUPPORTED, "%zu tiles x %lld phases exceed the 32-bit work counters",
+                    items.size(), (long long)phases);
+    const bool f64 = dtype == AC_F64;
+    const void *kA = f64 ? kernel3_of<double>(K, cpt) : kernel3_of<float>(K, cpt);
+    const void *kB = rem ? (f64 ? kernel3_of<double>((int)rem, cpt) : kernel3_of<float>((int)rem, cpt))
+                         : nullptr;
+    if (!kA || (rem && !kB)) return fail(AC_ERR_UNSUPPORTED, "no batched 3D kernel for this shape");
+    const size_t ldsA = stream3d_lds_bytes(t3, elem);
+    Tile3D tB{LX, LY, LZ, (int)(rem ? rem : K), threads};
+    const size_t ldsB = stream3d_lds_bytes(tB, elem);
+    set_lds_limit(kA, ldsA);
+    if (kB) set_lds_limit(kB, ldsB);
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kA, threads, ldsA);
+    if (e != hipSuccess) return hip_fail(e, "occupancy query");
+    if (per_cu < 1) return fail(AC_ERR_UNSUPPORTED, "batched 3D kernel does not fit on a CU");
+    int grid = per_cu * dev.cus;
+    const int want = (int)std::min<size_t>((size_t)grid, (items.size() + 7) / 8 * 8);
+    grid = std::max(8, want / 8 * 8);
+    p.n_items = (int)items.size();
+    p.grid = grid;
+    if ((e = hipMalloc(&p.d_inst, sizeof(BatchInst) * std::max<int32_t>(n, 1))) != hipSuccess ||
+        (e = hipMalloc(&p.d_items, sizeof(int4) * std::max<size_t>(items.size(), 1))) != hipSuccess ||
+        (e = hipMalloc(&p.d_bar, sizeof(unsigned) * SYNC_WORDS)) != hipSuccess ||
+        (e = hipMalloc(&p.d_err, sizeof(int))) != hipSuccess) {
+        release(p);
+        return fail(AC_ERR_NOMEM, "batched 3D plan allocation: %s", hipGetErrorString(e));
+    }
+    if (n > 0) e = hipMemcpy(p.d_inst, hi.data(), sizeof(BatchInst) * n, hipMemcpyHostToDevice);
+    if (e == hipSuccess && !items.empty())
+        e = hipMemcpy(p.d_items, items.data(), sizeof(int4) * items.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(p.d_err, 0, sizeof(int));
+    if (e != hipSuccess) { release(p); return hip_fail(e, "batched 3D plan upload"); }
+
+    hipStream_t &cs = g_capture_stream[p.device];
+    if (!cs && (e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking)) != hipSuccess) {
+        release(p);
+        return hip_fail(e, "capture stream");
+    }
+    if ((e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
+        release(p);
+        return hip_fail(e, "begin capture");
+    }
+    const long long spin = g_spin_limit;
+    int clock_khz = 0;
+    if (hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, p.device) != hipSuccess ||
+        clock_khz <= 0)
+        clock_khz = 100000;
+    const long long wall = g_spin_limit == 0 ? 0 : 2000LL * clock_khz;
+    const int ni = p.n_items;
+    hipError_t le = hipSuccess;
+    // launch A: q phases of K steps (+ the copy phase if nothing follows)
+    if (q > 0) {
+        hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, cs, p.d_bar);
+        const int nph = (int)q, ph0 = 0, cbA = rem ? 0 : cb;
+        void *args[] = {&p.d_inst, &p.d_items, (void *)&ni, (void *)&LX, (void *)&LY, (void *)&LZ,
+                        (void *)&nph, (void *)&ph0, (void *)&cbA, &p.d_bar, &p.d_err,
+                        (void *)&spin, (void *)&wall};
+        le = hipLaunchKernel(kA, dim3(grid), dim3(threads), args, ldsA, cs);
+    }
+    // launch B: one phase of the remaining steps (+ the copy phase)
+    if (le == hipSuccess && rem) {
+        hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, cs, p.d_bar);
+        const int nph = 1, ph0 = (int)q, cbB = cb;
+        void *args[] = {&p.d_inst, &p.d_items, (void *)&ni, (void *)&LX, (void *)&LY, (void *)&LZ,
+                        (void *)&nph, (void *)&ph0, (void *)&cbB, &p.d_bar, &p.d_err,
+                        (void *)&spin, (void *)&wall};
+        le = hipLaunchKernel(kB, dim3(grid), dim3(threads), args, ldsB, cs);
+    }
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(cs, &g);
+    if (le != hipSuccess || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        release(p);
+        return hip_fail(le != hipSuccess ? le : e, "capture batched 3D launch");
+    }
+    p.graph = g;
+    if ((e = hipGraphInstantiate(&p.exec, g, nullptr, nullptr, 0)) != hipSuccess) {
+        release(p);
+        return hip_fail(e, "instantiate batched 3D graph");
+    }
+    p.info.grid = grid;
+    p.info.items = p.n_items;
+    p.info.tb_depth = K;
+    p.info.tile_x = LX;
+    p.info.tile_y = LY;
+    p.info.blocks = (int32_t)phases;
+    p.info.copy_back = cb;
+    p.info.lds_bytes = (int64_t)ldsA;
+    return AC_OK;
+}
+
 }  // namespace
 
 // Reports (and clears) a barrier timeout of any cached batched plan on this
@@ -490,6 +742,55 @@ ac_status ac_step_batched_tuned(const ac_instance2d *inst, int32_t n_inst, int64
 ac_status ac_step_batched(const ac_instance2d *inst, int32_t n_inst, int64_t nsteps,
                           int32_t dtype, void *stream) {
     return ac_step_batched_tuned(inst, n_inst, nsteps, dtype, nullptr, nullptr, stream);
+}
+
+ac_status ac_step_batched_3d(const ac_instance3d *inst, int32_t n_inst, int64_t nsteps,
+                             int32_t dtype, const ac_tune *tune, ac_batch_info *info,
+                             void *stream) {
+    g_err.clear();
+    std::vector<double> alpha, r;
+    ac_status s = validate_batch3(inst, n_inst, nsteps, dtype, &alpha, &r);
+    if (s != AC_OK) return s;
+    if (nsteps == 0 || n_inst == 0) {
+        if (info) std::memset(info, 0, sizeof *info);
+        return AC_OK;
+    }
+    DevInfo dev;
+    hipError_t e = device_info(&dev);
+    if (e != hipSuccess) return hip_fail(e, "device query");
+    int device = 0;
+    if ((e = hipGetDevice(&device)) != hipSuccess) return hip_fail(e, "hipGetDevice");
+    ac_tune t{};
+    if (tune) t = *tune;
+    std::lock_guard<std::mutex> lock(g_mu);
+    auto it = g_plans.begin();
+    for (; it != g_plans.end(); ++it)
+        if (key_equal3(*it, inst, n_inst, nsteps, dtype, t, device)) break;
+    if (it == g_plans.end()) {
+        Plan p;
+        p.dim = 3;
+        p.inst3.assign(inst, inst + n_inst);
+        p.nsteps = nsteps;
+        p.dtype = dtype;
+        p.tune = t;
+        p.active = nullptr;
+        p.device = device;
+        if ((s = build_plan3d(p, inst, n_inst, nsteps, dtype, t, alpha, r, dev)) != AC_OK) return s;
+        g_plans.push_front(std::move(p));
+        while (g_plans.size() > kMaxPlans) {
+            (void)hipDeviceSynchronize();
+            release(g_plans.back());
+            g_plans.pop_back();
+        }
+        it = g_plans.begin();
+    } else if (it != g_plans.begin()) {
+        g_plans.splice(g_plans.begin(), g_plans, it);
+        it = g_plans.begin();
+    }
+    if (info) *info = it->info;
+    if ((e = hipGraphLaunch(it->exec, reinterpret_cast<hipStream_t>(stream))) != hipSuccess)
+        return hip_fail(e, "batched 3D graph launch");
+    return AC_OK;
 }
 
 ac_status ac_batched_release(void) {

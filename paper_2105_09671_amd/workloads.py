@@ -98,6 +98,23 @@ def sphere256(n: int = 256) -> Grid3D:
 
 HBM_STEPS = 200
 
+SIDES3D = (24, 32, 48, 64, 96, 128)
+
+
+def batch3d_instances(n_inst: int = 64, seed: int = 8, sides=SIDES3D,
+                      m_range=(3, 8)) -> list[Grid3D]:
+    """Seeded table of independent 3D instances: nx, ny, nz drawn from
+    ``sides``, m uniform on ``m_range``, random (stream 2000 + b) or a sphere
+    of radius 0.3 centred in (0, nx h) x (0, ny h) x (0, nz h), h = 1 / min side."""
+    out = []
+    for b in range(n_inst):
+        nx, ny, nz = (sides[inputs.draw_int(seed, b, k, 0, len(sides) - 1)] for k in range(3))
+        m = inputs.draw_int(seed, b, 3, m_range[0], m_range[1])
+        kind = ("random", "sphere")[inputs.draw_int(seed, b, 4, 0, 1)]
+        h = 1.0 / min(nx, ny, nz)
+        out.append(Grid3D(nx, ny, nz, h, dt_of(h), eps_m(h, m), kind, seed * 1000 + b))
+    return out
+
 
 def hbm16k(n: int = 16384) -> Grid2D:
     return unit_grid2d(n, 4, "random", seed=5)

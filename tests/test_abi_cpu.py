@@ -170,3 +170,24 @@ def test_precision_trace_stability_gate(lib):
     assert e2(lib, dt=0.3 * H * H) == L.AC_ERR_UNSTABLE
     assert lib.ac_err_3d(A, B, C, D, 8, 8, 8, H, 0.2 * H * H, EPS, 10, R, E, None) == L.AC_ERR_UNSTABLE
     assert lib.ac_err_3d(A, B, C, D, 8, 0, 8, H, DT, EPS, 10, R, E, None) == L.AC_ERR_INVALID_ARG
+
+
+def _inst3(phi, work, n3=(8, 8, 8), h=H, dt=DT, eps=EPS):
+    return L.AcInstance3D(phi, work, *n3, h, dt, eps)
+
+
+@pytest.mark.parametrize("bad", [dict(n3=(8, 0, 8)), dict(work=A + 16), dict(dt=0.2 * H * H),
+                                 dict(eps=-1.0)])
+def test_batched3d_validation_before_hip(lib, bad):
+    kw = dict(phi=A, work=B)
+    kw.update(bad)
+    arr = (L.AcInstance3D * 2)(_inst3(C, D), _inst3(**kw))
+    st = lib.ac_step_batched_3d(arr, 2, 10, 0, None, None, None)
+    assert st in (L.AC_ERR_INVALID_ARG, L.AC_ERR_UNSTABLE)
+    assert b"instance 1" in lib.ac_last_error()
+
+
+def test_batched3d_rejects_overlap_between_instances(lib):
+    arr = (L.AcInstance3D * 2)(_inst3(A, B), _inst3(C, A + 256))
+    assert lib.ac_step_batched_3d(arr, 2, 10, 0, None, None, None) == L.AC_ERR_INVALID_ARG
+    assert b"overlap" in lib.ac_last_error()
