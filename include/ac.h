@@ -147,15 +147,17 @@ typedef struct {
 /* Advance every instance by nsteps.  Every instance is validated as in
  * ac_step_2d (argument errors name the instance index) and no two buffers of
  * the batch may overlap.  On first use of an instance table the library
- * uploads it, sizes the persistent grid to what the device holds at once,
- * captures [barrier reset, persistent kernel] into a hipGraph on a private
- * stream and caches it (the 64 most recent tables are kept); calls with the
- * same table (same pointers, sizes and parameters) and nsteps replay the
- * graph on `stream`.  The launch shape comes from `tune`, else from the
- * autotuner's table (ac_autotune_batched), else the 2D defaults.  Grid
- * barriers wait a bounded time; a timeout (e.g. if other work kept some
- * workgroups from becoming resident) ends the kernel early and is reported by
- * the next ac_check().  info (may be NULL) receives the launch description. */
+ * uploads it and its tile list, captures the whole call into a hipGraph on a
+ * private stream and caches it (the 64 most recent tables are kept); calls
+ * with the same table (same pointers, sizes and parameters) and nsteps replay
+ * the graph on `stream`.  By default the graph holds one launch per temporal
+ * block, one workgroup per tile of every instance; ac_batched_set_persistent
+ * switches to one persistent launch (workgroups sized to what the device
+ * holds, tiles taken from ticket counters, a bounded-wait phase barrier per
+ * temporal block; a timeout ends the kernel early and is reported by
+ * ac_check).  The launch shape comes from `tune`, else from the autotuner's
+ * table (ac_autotune_batched), else 64 x 128 tiles (FP64: 64 x 64).  Each
+ * instance gets exactly what ac_step_2d computes for it, bit for bit. */
 ac_status ac_step_batched(const ac_instance2d *inst, int32_t n_inst, int64_t nsteps,
                           int32_t dtype, void *stream);
 ac_status ac_step_batched_tuned(const ac_instance2d *inst, int32_t n_inst, int64_t nsteps,
@@ -191,6 +193,16 @@ ac_status ac_step_batched_3d(const ac_instance3d *inst, int32_t n_inst, int64_t 
 
 /* Free every cached batched plan (synchronises the device). */
 ac_status ac_batched_release(void);
+
+/* How batched calls execute (drops cached plans).  on = 0 (the default): the
+ * cached hipGraph holds one launch per temporal block (one workgroup per tile,
+ * the ordering between blocks is the kernel boundary).  on != 0: one
+ * persistent launch whose workgroups take tiles from ticket counters and meet
+ * at a phase barrier per temporal block.  Same results bit for bit; on
+ * MI355X the barrier's per-workgroup device-scope cache release and acquire
+ * cost more than the launch boundaries (measured figures in the design
+ * notes). */
+void ac_batched_set_persistent(int32_t on);
 
 /* Polls a grid barrier makes before giving up (default 2e7, about 2 s;
  * negative restores the default).  Drops cached plans.  A diagnostic control:

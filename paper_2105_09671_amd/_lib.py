@@ -87,6 +87,7 @@ SIGNATURES = {
     "ac_step_batched": ([ctypes.POINTER(AcInstance2D), _i32, _i64, _i32, _vp], _i32),
     "ac_step_batched_tuned": ([ctypes.POINTER(AcInstance2D), _i32, _i64, _i32,
                                ctypes.POINTER(AcTune), ctypes.POINTER(AcBatchInfo), _vp], _i32),
+    "ac_batched_set_persistent": ([_i32], None),
     "ac_step_batched_3d": ([ctypes.POINTER(AcInstance3D), _i32, _i64, _i32,
                             ctypes.POINTER(AcTune), ctypes.POINTER(AcBatchInfo), _vp], _i32),
     "ac_step_batched_masked": ([ctypes.POINTER(AcInstance2D), _i32, _i64, _i32,

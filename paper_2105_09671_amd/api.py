@@ -178,6 +178,13 @@ class Batch:
         return {k: getattr(best, k) for k, _ in best._fields_}
 
 
+def batched_persistent(on: bool) -> None:
+    """Choose how batched calls execute: one persistent launch with a phase
+    barrier (True) or a captured graph of one launch per phase (False, the
+    default).  Results are bitwise the same."""
+    L.lib().ac_batched_set_persistent(1 if on else 0)
+
+
 class Batch3D:
     """Independent 3D grids packed into one phi and one work buffer; ``fields``
     are (nz, ny, nx) arrays, ``params`` (h, dt, eps) per grid."""

@@ -183,6 +183,41 @@ batched_kernel(const BatchInst *__restrict__ inst, const int4 *__restrict__ item
     }
 }
 
+// Phase-graph mode: one launch per phase (captured as consecutive graph nodes),
+// one workgroup per item, no waiting inside the kernel.  Workgroup g runs on
+// XCD g mod 8 and takes item (g mod 8) * per + g / 8, so each XCD's workgroups
+// cover one contiguous slice of the list (neighbouring tiles share an L2).
+// The ordering between phases is the kernel boundary, whose cache release and
+// acquire the command processor performs once per launch, where the
+// persistent kernel's barrier has every workgroup do its own.
+template <typename T, int LXC, bool INPLACE>
+__global__ void __launch_bounds__(1024)
+batched_phase_kernel(const BatchInst *__restrict__ inst, const int4 *__restrict__ items,
+                     int n_items, int LX, int LY, int K, int k, int phase, int copy,
+                     const int *__restrict__ n_active)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    if (n_active) n_items = *n_active;
+    const int per = (n_items + 7) / 8;
+    const int i = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+    if ((int)(blockIdx.x >> 3) >= per || i >= n_items) return;     // whole workgroup
+    const int4 it = items[i];
+    const BatchInst I = inst[it.x];
+    if (!copy) {
+        const T *src = static_cast<const T *>((phase & 1) ? I.work : I.phi);
+        T *dst = static_cast<T *>((phase & 1) ? I.phi : I.work);
+        if constexpr (INPLACE)
+            tile2d_body<T, 64, Rows<T>::value, true, INPLACE_LB, INPLACE_D>(
+                src, dst, I.nx, I.ny, (T)I.alpha, (T)I.r, 64, LY, K, k, it.y, it.z, smem_raw);
+        else
+            tile2d_body<T, LXC>(src, dst, I.nx, I.ny, (T)I.alpha, (T)I.r, LX, LY, K, k, it.y, it.z,
+                                smem_raw);
+    } else {
+        copy_tile<T>(static_cast<const T *>(I.work), static_cast<T *>(I.phi), I.nx, I.ny,
+                     LX - 2 * K, LY - 2 * K, it.y, it.z);
+    }
+}
+
 // Copy the output region of one 3D item (xy tile, z segment) from src to dst.
 template <typename T>
 __device__ void copy_tile3d(const T *src, T *dst, int nx, int ny, int nz, int OX, int OY, int LZ,
@@ -247,11 +282,36 @@ batched3d_kernel(const BatchInst *__restrict__ inst, const int4 *__restrict__ it
     }
 }
 
+// Phase-graph mode for 3D batches: one launch per phase, one workgroup per item
+// (XCD-aware slices as in batched_phase_kernel).  copy: the final copy phase.
+template <typename T, int K, int CPT>
+__global__ void __launch_bounds__(512)
+batched3d_phase_kernel(const BatchInst *__restrict__ inst, const int4 *__restrict__ items,
+                       int n_items, int LX, int LY, int LZ, int phase, int copy)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int per = (n_items + 7) / 8;
+    const int i = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+    if ((int)(blockIdx.x >> 3) >= per || i >= n_items) return;     // whole workgroup
+    const int4 it = items[i];
+    const BatchInst I = inst[it.x];
+    if (!copy) {
+        const T *src = static_cast<const T *>((phase & 1) ? I.work : I.phi);
+        T *dst = static_cast<T *>((phase & 1) ? I.phi : I.work);
+        stream3d_body<T, K, CPT>(src, dst, I.nx, I.ny, I.nz, (T)I.alpha, (T)I.r, LX, LY, LZ,
+                                 I.tiles_x, it.y, it.z, smem_raw);
+    } else {
+        copy_tile3d<T>(static_cast<const T *>(I.work), static_cast<T *>(I.phi), I.nx, I.ny, I.nz,
+                       LX - 2 * K, LY - 2 * K, LZ, I.tiles_x, it.y, it.z);
+    }
+}
+
 // ---------------------------------------------------------------- host ----
 
 namespace {
 
 long long g_spin_limit = 20000000;   // ~2 s of polling per barrier
+bool g_persistent = false;           // false: a graph of one launch per phase
 
 struct Plan {
     // key
@@ -313,6 +373,22 @@ void release(Plan &p) {
 
 template <typename T, int LXC, bool INPLACE = false>
 const void *kernel_ptr() { return (const void *)batched_kernel<T, LXC, INPLACE>; }
+
+template <typename T, int LXC, bool INPLACE = false>
+const void *phase_kernel_ptr() { return (const void *)batched_phase_kernel<T, LXC, INPLACE>; }
+
+const void *select_phase_kernel(int32_t dtype, int LX, bool inplace) {
+    if (dtype == AC_F64) {
+        if (inplace) return phase_kernel_ptr<double, 64, true>();
+        if (LX == 64) return phase_kernel_ptr<double, 64>();
+        if (LX == 128) return phase_kernel_ptr<double, 128>();
+        return phase_kernel_ptr<double, 0>();
+    }
+    if (inplace) return phase_kernel_ptr<float, 64, true>();
+    if (LX == 64) return phase_kernel_ptr<float, 64>();
+    if (LX == 128) return phase_kernel_ptr<float, 128>();
+    return phase_kernel_ptr<float, 0>();
+}
 
 // the tile body the single-grid plan chose: in place (64-wide tiles) or two buffers
 const void *select_kernel(int32_t dtype, int LX, bool inplace) {
@@ -426,7 +502,7 @@ ac_status build_plan(Plan &p, const ac_instance2d *inst, int32_t n, int64_t nste
         release(p);
         return hip_fail(e, "begin capture");
     }
-    hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, cs, p.d_bar);
+    if (g_persistent) hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, cs, p.d_bar);
     if (p.active)
         hipLaunchKernelGGL(batch_compact_kernel, dim3(1), dim3(1024), 0, cs, p.d_items, p.n_items,
                            p.active, p.d_compact, p.d_count);
@@ -445,7 +521,22 @@ ac_status build_plan(Plan &p, const ac_instance2d *inst, int32_t n, int64_t nste
     void *args[] = {&p.d_inst, &list, (void *)&ni, (void *)&LX, (void *)&LY, (void *)&K,
                     (void *)&nblocks, (void *)&base, (void *)&rem, (void *)&cb, (void *)&cnt,
                     &p.d_bar, &p.d_err, (void *)&spin, (void *)&wall};
-    hipError_t le = hipLaunchKernel(kern, dim3(grid), dim3(threads), args, lds, cs);
+    hipError_t le = hipSuccess;
+    int phase_grid = 8 * ((ni + 7) / 8);
+    if (g_persistent) {
+        le = hipLaunchKernel(kern, dim3(grid), dim3(threads), args, lds, cs);
+    } else {
+        const void *pk = select_phase_kernel(dtype, LX, tp.kernel == AC_KERNEL_2D_INPLACE);
+        set_lds_limit(pk, lds);
+        for (int b = 0; b <= nblocks && le == hipSuccess; ++b) {
+            const int copy = b == nblocks;
+            if (copy && !cb) break;
+            const int k = copy ? 0 : base + (b < rem ? 1 : 0);
+            void *pargs[] = {&p.d_inst, &list, (void *)&ni, (void *)&LX, (void *)&LY, (void *)&K,
+                             (void *)&k, (void *)&b, (void *)&copy, (void *)&cnt};
+            le = hipLaunchKernel(pk, dim3(phase_grid), dim3(threads), pargs, lds, cs);
+        }
+    }
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(cs, &g);
     if (le != hipSuccess || e != hipSuccess) {
@@ -458,7 +549,7 @@ ac_status build_plan(Plan &p, const ac_instance2d *inst, int32_t n, int64_t nste
         release(p);
         return hip_fail(e, "instantiate batched graph");
     }
-    p.info.grid = grid;
+    p.info.grid = g_persistent ? grid : phase_grid;
     p.info.items = p.n_items;
     p.info.tb_depth = K;
     p.info.tile_x = LX;
@@ -520,6 +611,25 @@ const void *kernel3_cpt(int cpt) {
     if (cpt <= 2) return (const void *)batched3d_kernel<T, K, 2>;
     if (cpt <= 4) return (const void *)batched3d_kernel<T, K, 4>;
     return nullptr;
+}
+
+template <typename T, int K>
+const void *phase3_cpt(int cpt) {
+    if (cpt <= 1) return (const void *)batched3d_phase_kernel<T, K, 1>;
+    if (cpt <= 2) return (const void *)batched3d_phase_kernel<T, K, 2>;
+    if (cpt <= 4) return (const void *)batched3d_phase_kernel<T, K, 4>;
+    return nullptr;
+}
+
+template <typename T>
+const void *phase3_of(int K, int cpt) {
+    switch (K) {
+    case 1: return phase3_cpt<T, 1>(cpt);
+    case 2: return phase3_cpt<T, 2>(cpt);
+    case 3: return phase3_cpt<T, 3>(cpt);
+    case 4: return phase3_cpt<T, 4>(cpt);
+    default: return nullptr;
+    }
 }
 
 template <typename T>
@@ -612,8 +722,25 @@ ac_status build_plan3d(Plan &p, const ac_instance3d *inst, int32_t n, int64_t ns
     const long long wall = g_spin_limit == 0 ? 0 : 2000LL * clock_khz;
     const int ni = p.n_items;
     hipError_t le = hipSuccess;
+    const int phase_grid = 8 * ((ni + 7) / 8);
+    if (!g_persistent) {
+        // one launch per phase: q of K steps, one of the remaining steps, a copy
+        const void *pA = f64 ? phase3_of<double>(K, cpt) : phase3_of<float>(K, cpt);
+        const void *pB = rem ? (f64 ? phase3_of<double>((int)rem, cpt) : phase3_of<float>((int)rem, cpt))
+                             : nullptr;
+        set_lds_limit(pA, ldsA);
+        if (pB) set_lds_limit(pB, ldsB);
+        for (int64_t b = 0; b < phases + cb && le == hipSuccess; ++b) {
+            const int ph = (int)b, copy = b == phases;
+            const bool last_rem = rem && b == phases - 1;
+            void *pargs[] = {&p.d_inst, &p.d_items, (void *)&ni, (void *)&LX, (void *)&LY,
+                             (void *)&LZ, (void *)&ph, (void *)&copy};
+            le = hipLaunchKernel(last_rem ? pB : pA, dim3(phase_grid), dim3(threads), pargs,
+                                 last_rem ? ldsB : ldsA, cs);
+        }
+    }
     // launch A: q phases of K steps (+ the copy phase if nothing follows)
-    if (q > 0) {
+    if (g_persistent && q > 0) {
         hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, cs, p.d_bar);
         const int nph = (int)q, ph0 = 0, cbA = rem ? 0 : cb;
         void *args[] = {&p.d_inst, &p.d_items, (void *)&ni, (void *)&LX, (void *)&LY, (void *)&LZ,
@@ -622,7 +749,7 @@ ac_status build_plan3d(Plan &p, const ac_instance3d *inst, int32_t n, int64_t ns
         le = hipLaunchKernel(kA, dim3(grid), dim3(threads), args, ldsA, cs);
     }
     // launch B: one phase of the remaining steps (+ the copy phase)
-    if (le == hipSuccess && rem) {
+    if (g_persistent && le == hipSuccess && rem) {
         hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, cs, p.d_bar);
         const int nph = 1, ph0 = (int)q, cbB = cb;
         void *args[] = {&p.d_inst, &p.d_items, (void *)&ni, (void *)&LX, (void *)&LY, (void *)&LZ,
@@ -642,7 +769,7 @@ ac_status build_plan3d(Plan &p, const ac_instance3d *inst, int32_t n, int64_t ns
         release(p);
         return hip_fail(e, "instantiate batched 3D graph");
     }
-    p.info.grid = grid;
+    p.info.grid = g_persistent ? grid : phase_grid;
     p.info.items = p.n_items;
     p.info.tb_depth = K;
     p.info.tile_x = LX;
@@ -799,6 +926,14 @@ ac_status ac_batched_release(void) {
     for (Plan &p : g_plans) release(p);
     g_plans.clear();
     return e == hipSuccess ? AC_OK : hip_fail(e, "ac_batched_release");
+}
+
+void ac_batched_set_persistent(int32_t on) {
+    std::lock_guard<std::mutex> lock(g_mu);
+    g_persistent = on != 0;
+    if (!g_plans.empty()) (void)hipDeviceSynchronize();
+    for (Plan &p : g_plans) release(p);   // the mode is baked into captured graphs
+    g_plans.clear();
 }
 
 void ac_batched_set_spin_limit(int64_t polls) {

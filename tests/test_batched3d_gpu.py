@@ -17,6 +17,13 @@ THREADS = min(32, max(1, oracle.cpus_available()))
 NP = {torch.float32: np.float32, torch.float64: np.float64}
 
 
+@pytest.fixture(params=[False, True], ids=["phase-graph", "persistent"])
+def mode(request):
+    api.batched_persistent(request.param)
+    yield request.param
+    api.batched_persistent(False)
+
+
 def _small_batch():
     shapes = [(5, 1, 1), (9, 40, 7), (33, 33, 33), (20, 17, 61), (2, 70, 45), (40, 8, 3),
               (64, 64, 24), (1, 1, 30), (26, 29, 31)]
@@ -32,7 +39,7 @@ def _small_batch():
 @pytest.mark.parametrize("nsteps,tune", [(7, None), (9, None), (4, None), (1, None),
                                          (11, dict(tb_depth=3, tile_x=32, tile_y=16, tile_z=16)),
                                          (6, dict(tb_depth=2, tile_x=16, tile_y=16, tile_z=8))])
-def test_batch3d_matches_single_and_oracle(dtype, nsteps, tune):
+def test_batch3d_matches_single_and_oracle(mode, dtype, nsteps, tune):
     fields, prm = _small_batch()
     fields = [f.astype(NP[dtype]) for f in fields]
     b = api.Batch3D(fields, prm, dtype=dtype)
@@ -48,7 +55,7 @@ def test_batch3d_matches_single_and_oracle(dtype, nsteps, tune):
     print(nsteps, tune, info)
 
 
-def test_batch3d_replay_and_workload():
+def test_batch3d_replay_and_workload(mode):
     insts = workloads.batch3d_instances(64)
     fields = [g.initial().astype(np.float32) for g in insts]
     prm = [(g.h, g.dt, g.eps) for g in insts]

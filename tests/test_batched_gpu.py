@@ -36,11 +36,18 @@ def _small_batch(seed=40):
     return fields, prm
 
 
+@pytest.fixture(params=[False, True], ids=["phase-graph", "persistent"])
+def mode(request, api):
+    api.batched_persistent(request.param)
+    yield request.param
+    api.batched_persistent(False)
+
+
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 @pytest.mark.parametrize("nsteps,tune", [(37, None), (37, dict(tb_depth=3, tile_x=64, tile_y=32)),
                                          (5, dict(tb_depth=1, tile_x=64, tile_y=32)),
                                          (1, None), (8, dict(tb_depth=8, tile_x=128, tile_y=64))])
-def test_batch_matches_single_and_oracle(api, dtype, nsteps, tune):
+def test_batch_matches_single_and_oracle(api, mode, dtype, nsteps, tune):
     fields, prm = _small_batch()
     fields = [f.astype(NP[dtype]) for f in fields]
     b = api.Batch(fields, prm, dtype=dtype)
@@ -85,6 +92,7 @@ def test_batch_order_and_replay(api):
 def test_barrier_timeout_is_reported_and_recovers(api):
     from paper_2105_09671_amd import _lib as L
     fields, prm = _small_batch(42)
+    api.batched_persistent(True)              # the barrier exists in the persistent mode
     b = api.Batch([f.astype(np.float32) for f in fields], prm)
     L.lib().ac_batched_set_spin_limit(0)      # host-forced: every barrier wait gives up at once
     try:
@@ -94,6 +102,7 @@ def test_barrier_timeout_is_reported_and_recovers(api):
         assert "timed out" in str(ei.value)
     finally:
         L.lib().ac_batched_set_spin_limit(-1)
+        api.batched_persistent(False)
     api.check()                               # flag cleared
     b2 = api.Batch([f.astype(np.float32) for f in fields], prm)
     b2.step(40, tune=dict(tb_depth=2, tile_x=64, tile_y=32))
@@ -144,7 +153,7 @@ def _ulp_sensitivity(f32, prm, nsteps, ref, seed, threads):
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-def test_batch512_sampled_against_oracle(api, dtype):
+def test_batch512_sampled_against_oracle(api, mode, dtype):
     """The full 512-instance workload, 5000 steps in one persistent launch; every
     8th instance (64 of them, all side lengths) is compared with the FP64 oracle:
     FP64 to 1e-12, FP32 to 1e-5 (random starts: the conditioning bar above)."""
@@ -177,7 +186,7 @@ def test_batch512_sampled_against_oracle(api, dtype):
     print("batch512 %s: launch %s, worst sampled rel Linf %.3g" % (dtype, info, worst))
 
 
-def test_masked_batch_steps_only_active_grids(api):
+def test_masked_batch_steps_only_active_grids(api, mode):
     fields, prm = _small_batch(45)
     fields = [f.astype(np.float32) for f in fields]
     b = api.Batch(fields, prm)
