@@ -37,17 +37,19 @@ namespace sur {
 // channels, K = KS*KS*Cin ordered (tap, ci) like the weights [Cout][tap][Cin].
 // UP: X is at low resolution and each result goes to a 2x2 block of Y.
 // Tile (32 WM) x (32 WN); 32-channel layers use WN = 1 so no MFMA lane idles.
-template <int KS, bool UP, int WM, int WN>
+template <int KS, bool UP, int WM, int WN, int TM = 2, int TN = 2>
 __global__ void __launch_bounds__(256)
 conv_fwd_kernel(View X, int lgCin, int B, int H, int W, const bf16_t *__restrict__ Wk,
                 const float *__restrict__ bias, int Cout, View Y, int relu)
 {
-    constexpr int TBM = 32 * WM, TBN = 32 * WN;
+    constexpr int TBM = 16 * TM * WM, TBN = 16 * TN * WN;
     constexpr int NA = (TBM * 4 + 255) / 256, NB = (TBN * 4 + 255) / 256;
     __shared__ __align__(16) bf16_t As[TBM * LP];
     __shared__ __align__(16) bf16_t Bs[TBN * LP];
     const int Cin = 1 << lgCin, K = KS * KS * Cin, M = B * H * W;
-    const int m0 = blockIdx.x * TBM, n0 = blockIdx.y * TBN;
+    const int mt = xcd_tile((M + TBM - 1) / TBM);
+    if (mt * TBM >= M) return;                      // padding workgroup (whole group)
+    const int m0 = mt * TBM, n0 = blockIdx.y * TBN;
     const int t = threadIdx.x;
     int arow[NA], akc[NA], pn[NA], py[NA], px[NA];
     bool aok[NA];
@@ -82,7 +84,7 @@ conv_fwd_kernel(View X, int lgCin, int B, int H, int W, const bf16_t *__restrict
         if (c >= TBN * 4 || co >= Cout || k >= K) return uint4{0, 0, 0, 0};
         return *reinterpret_cast<const uint4 *>(Wk + (size_t)co * K + k);
     };
-    floatx4 acc[2][2] = {};
+    floatx4 acc[TM][TN] = {};
     uint4 ra[NA], rb[NB];
 #pragma unroll
     for (int u = 0; u < NA; ++u) ra[u] = loadA(u, 0);
@@ -104,17 +106,17 @@ conv_fwd_kernel(View X, int lgCin, int B, int H, int W, const bf16_t *__restrict
 #pragma unroll
             for (int u = 0; u < NB; ++u) rb[u] = loadB(u, k0 + BK);
         }
-        mma_step_t<WM, WN>(As, Bs, acc);
+        mma_step_g<WM, WN, TM, TN>(As, Bs, acc);
         __syncthreads();
     }
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < TN; ++j)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 int row, col;
-                acc_coord_t<WM, WN>(i, j, q, &row, &col);
+                acc_coord_g<WM, WN, TM, TN>(i, j, q, &row, &col);
                 const int mg = m0 + row, cg = n0 + col;
                 if (mg >= M || cg >= Cout) continue;
                 float v = acc[i][j][q] + bias[cg];
@@ -149,7 +151,9 @@ conv_dgrad_kernel(View dZ, int lgCout, int B, int H, int W, const bf16_t *__rest
     __shared__ __align__(16) bf16_t As[TBM * LP];
     __shared__ __align__(16) bf16_t Bs[TBN * LP];
     const int Cout = 1 << lgCout, K = KS * KS * Cout, M = B * H * W;
-    const int m0 = blockIdx.x * TBM, n0 = blockIdx.y * TBN;
+    const int mt = xcd_tile((M + TBM - 1) / TBM);
+    if (mt * TBM >= M) return;                      // padding workgroup (whole group)
+    const int m0 = mt * TBM, n0 = blockIdx.y * TBN;
     const int t = threadIdx.x;
     int arow[NA], akc[NA], pn[NA], py[NA], px[NA];
     bool aok[NA];
@@ -296,7 +300,7 @@ conv_wgrad_kernel(View dZ, int Cout, View X, int lgCin, int B, int H, int W,
     __shared__ __align__(16) bf16_t As[TBM * LP];
     __shared__ __align__(16) bf16_t Bs[TBN * LP];
     const int Cin = 1 << lgCin, Kw = KS * KS * Cin, M = B * H * W;
-    const int m0 = blockIdx.x * TBM, n0 = blockIdx.y * TBN;
+    const int m0 = blockIdx.x * TBM, n0 = blockIdx.y * TBN;     // M tiles over Cout here
     const int p_begin = blockIdx.z * pix_per_split;
     const int p_end = min(M, p_begin + pix_per_split);
     if (p_begin >= p_end) return;
@@ -618,12 +622,12 @@ const bf16_t *wk_of(const ac_sur *s, int l) { return s->wb + s->kwoff[l]; }
 const bf16_t *wt_of(const ac_sur *s, int l) { return s->wt + s->kwoff[l]; }
 
 // Y = act(conv(X)); H, W: the resolution of X (and Y unless up)
-template <int KS, bool UP, int WM, int WN>
+template <int KS, bool UP, int WM, int WN, int TM = 2, int TN = 2>
 void launch_fwd(ac_sur *s, int l, View X, int lgcin, int B, int H, int W, View Y, bool relu) {
     const LayerDef &L = kLayers[l];
-    const int M = B * H * W;
-    dim3 grid((M + 32 * WM - 1) / (32 * WM), (L.cout + 32 * WN - 1) / (32 * WN));
-    hipLaunchKernelGGL((conv_fwd_kernel<KS, UP, WM, WN>), grid, dim3(256), 0, s->st, X, lgcin, B,
+    const int M = B * H * W, TBM = 16 * TM * WM, TBN = 16 * TN * WN;
+    dim3 grid(xcd_grid((M + TBM - 1) / TBM), (L.cout + TBN - 1) / TBN);
+    hipLaunchKernelGGL((conv_fwd_kernel<KS, UP, WM, WN, TM, TN>), grid, dim3(256), 0, s->st, X, lgcin, B,
                        H, W, wk_of(s, l), bias_of(s, l), L.cout, Y, (int)relu);
 }
 
@@ -660,7 +664,7 @@ template <int KS, int WM, int WN>
 void launch_dgrad(ac_sur *s, int l, View dZ, int lgcout, int B, int H, int W, int cin, View dX,
                   View mask, int mask_c0) {
     const int M = B * H * W;
-    dim3 gd((M + 32 * WM - 1) / (32 * WM), (cin + 32 * WN - 1) / (32 * WN));
+    dim3 gd(xcd_grid((M + 32 * WM - 1) / (32 * WM)), (cin + 32 * WN - 1) / (32 * WN));
     hipLaunchKernelGGL((conv_dgrad_kernel<KS, WM, WN>), gd, dim3(256), 0, s->st, dZ, lgcout, B, H, W,
                        wt_of(s, l), cin, dX, mask, mask_c0, 0);
 }
