@@ -260,6 +260,35 @@ def hbm_resident(api, torch, workloads) -> dict:
     return out
 
 
+def only(name: str) -> dict:
+    """One secondary workload alone (for profiling its kernels): one warm-up
+    call, one timed call."""
+    import torch
+    from paper_2105_09671_amd import api, workloads
+    if name == "batch512":
+        insts = workloads.batch_instances(512)
+        b = api.Batch([g.initial().astype("float32") for g in insts], [(g.h, g.dt, g.eps) for g in insts])
+        b.step(5000)
+        t = timed(lambda: b.step(5000), 1)
+        return {"workload": name, "GLUPS": round(b.cells * 5000 / t / 1e9, 2), "ms": round(t * 1e3, 2)}
+    if name == "sep256c":
+        g3 = workloads.sep256c()
+        p3 = torch.from_numpy(g3.initial()).float().cuda()
+        api.step3d(p3, g3.h, g3.dt, g3.eps, 200)
+        t = timed(lambda: api.step3d(p3, g3.h, g3.dt, g3.eps, 2000), 1)
+        return {"workload": name, "GLUPS": round(256 ** 3 * 2000 / t / 1e9, 2), "ms": round(t * 1e3, 2)}
+    if name == "sur256":
+        import numpy as np
+        from paper_2105_09671_amd import sur_train
+        from paper_2105_09671_amd.surrogate import Surrogate
+        net = Surrogate(256, 256)
+        net.set_weights(np.load(os.path.join(ROOT, "paper_2105_09671_amd", "weights", "sur256.npz"))["weights"])
+        res = sur_train.evaluate(net, list(range(100000, 100256)))
+        net.close()
+        return {"workload": name, "plain_ms": res["plain_ms"], "surrogate_ms": res["surrogate_ms"]}
+    raise SystemExit("bench.py --only: unknown workload %r" % name)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -270,6 +299,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=10.0, help="seconds of oracle work")
     ap.add_argument("--copy-ref", action="store_true",
                     help="also run a 256 MiB device copy (counter scale reference)")
+    ap.add_argument("--only", default="", choices=["", "batch512", "sep256c", "sur256"],
+                    help="run one secondary workload alone (to profile its kernels)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -283,6 +314,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.only:
+        print(json.dumps(only(args.only)))
+        return
     g = workloads.circle2048()
     phi0 = g.initial()
     phi_init = torch.from_numpy(phi0.astype("float32")).cuda()
