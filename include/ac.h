@@ -156,8 +156,10 @@ typedef struct {
  * holds, tiles taken from ticket counters, a bounded-wait phase barrier per
  * temporal block; a timeout ends the kernel early and is reported by
  * ac_check).  The launch shape comes from `tune`, else from the autotuner's
- * table (ac_autotune_batched), else 64 x 128 tiles (FP64: 64 x 64).  Each
- * instance gets exactly what ac_step_2d computes for it, bit for bit. */
+ * table (ac_autotune_batched), else 64 x 128 tiles (FP64: 64 x 64).  A call
+ * longer than 2048 temporal blocks runs, in the graph mode, as repeated
+ * 2048-block graphs plus a remainder.  Each instance gets exactly what
+ * ac_step_2d computes for it, bit for bit. */
 ac_status ac_step_batched(const ac_instance2d *inst, int32_t n_inst, int64_t nsteps,
                           int32_t dtype, void *stream);
 ac_status ac_step_batched_tuned(const ac_instance2d *inst, int32_t n_inst, int64_t nsteps,

@@ -312,6 +312,7 @@ namespace {
 
 long long g_spin_limit = 20000000;   // ~2 s of polling per barrier
 bool g_persistent = false;           // false: a graph of one launch per phase
+constexpr int64_t kMaxGraphBlocks = 2048;   // temporal blocks per captured graph
 
 struct Plan {
     // key
@@ -815,6 +816,22 @@ ac_status ac_step_batched_masked(const ac_instance2d *inst, int32_t n_inst, int6
     std::vector<double> alpha, r;
     ac_status s = validate_batch(inst, n_inst, nsteps, dtype, &alpha, &r);
     if (s != AC_OK) return s;
+    // a graph holds one launch per temporal block: long calls run as repeated
+    // chunks of kMaxGraphBlocks blocks (an even count, so each ends in phi)
+    // and a remainder; the update of a cell does not depend on the blocking
+    if (!g_persistent) {
+        const int64_t depth = (tune && tune->tb_depth) ? tune->tb_depth : (dtype == AC_F64 ? 5 : 8);
+        const int64_t chunk = kMaxGraphBlocks * depth;
+        if (nsteps > chunk) {
+            for (int64_t done = 0; done < nsteps;) {
+                const int64_t n = nsteps - done > chunk ? chunk : nsteps - done;
+                if ((s = ac_step_batched_masked(inst, n_inst, n, dtype, tune, active, info, stream)) != AC_OK)
+                    return s;
+                done += n;
+            }
+            return AC_OK;
+        }
+    }
     if (nsteps == 0 || n_inst == 0) {
         if (info) std::memset(info, 0, sizeof *info);
         return AC_OK;
@@ -878,6 +895,19 @@ ac_status ac_step_batched_3d(const ac_instance3d *inst, int32_t n_inst, int64_t 
     std::vector<double> alpha, r;
     ac_status s = validate_batch3(inst, n_inst, nsteps, dtype, &alpha, &r);
     if (s != AC_OK) return s;
+    if (!g_persistent) {       // bounded graphs, as for 2D batches
+        const int64_t depth = (tune && tune->tb_depth) ? tune->tb_depth : (dtype == AC_F64 ? 3 : 4);
+        const int64_t chunk = kMaxGraphBlocks * depth;
+        if (nsteps > chunk) {
+            for (int64_t done = 0; done < nsteps;) {
+                const int64_t n = nsteps - done > chunk ? chunk : nsteps - done;
+                if ((s = ac_step_batched_3d(inst, n_inst, n, dtype, tune, info, stream)) != AC_OK)
+                    return s;
+                done += n;
+            }
+            return AC_OK;
+        }
+    }
     if (nsteps == 0 || n_inst == 0) {
         if (info) std::memset(info, 0, sizeof *info);
         return AC_OK;

@@ -76,3 +76,17 @@ def test_batch3d_replay_and_workload(mode):
         g = insts[i]
         ref = oracle.step3d(g.initial(), g.h, g.dt, g.eps, 200, THREADS)
         assert D.rel_linf(b64.views()[i].cpu().numpy(), ref) <= 1e-12, i
+
+
+def test_long_3d_call_runs_as_bounded_graphs():
+    fields, prm = _small_batch()
+    fields = [f.astype(np.float32) for f in fields[:3]]
+    prm = prm[:3]
+    n = 2048 * 4 + 5
+    b = api.Batch3D(fields, prm)
+    b.step(n)
+    api.check()
+    for v, f, (h, dt, eps) in zip(b.views(), fields, prm):
+        one = torch.from_numpy(f).cuda()
+        api.step3d(one, h, dt, eps, n)
+        assert torch.equal(v, one)

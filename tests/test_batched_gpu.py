@@ -209,3 +209,19 @@ def test_masked_batch_steps_only_active_grids(api, mode):
     ref.step(46)
     assert torch.equal(b.views()[1], ref.views()[1])
     assert info1["items"] > 0
+
+
+def test_long_call_runs_as_bounded_graphs(api):
+    """More temporal blocks than one captured graph holds: the call runs as
+    repeated graph chunks plus a remainder, bit for bit the single-grid result."""
+    fields, prm = _small_batch(46)
+    fields = [f.astype(np.float32) for f in fields[:4]]
+    prm = prm[:4]
+    n = 2048 * 8 + 37
+    b = api.Batch(fields, prm)
+    b.step(n)
+    api.check()
+    for v, f, (h, dt, eps) in zip(b.views(), fields, prm):
+        one = torch.from_numpy(f).cuda()
+        api.step2d(one, h, dt, eps, n)
+        assert torch.equal(v, one)
