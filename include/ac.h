@@ -257,6 +257,12 @@ ac_status ac_sur_set_weights(ac_sur *s, const float *host, int64_t n);
 ac_status ac_sur_get_weights(ac_sur *s, float *host, int64_t n);
 /* phi_out (may be NULL: kept internally) = phi_in + U(phi_in) */
 ac_status ac_sur_forward(ac_sur *s, const float *phi_in, float *phi_out, int32_t batch);
+/* inference only: phi_out (required, device, batch*H*W floats, not aliasing
+ * phi_in) = phi_in + U(phi_in), the same network as ac_sur_forward with the
+ * 1x1 head and the residual fused into the last 3x3 layer's epilogue (equal to
+ * ac_sur_forward up to FP32 summation order).  Keeps no activations for a
+ * backward pass: ac_sur_loss after it fails until the next ac_sur_forward. */
+ac_status ac_sur_infer(ac_sur *s, const float *phi_in, float *phi_out, int32_t batch);
 /* after ac_sur_forward on the same batch: mean squared error against target;
  * stores d loss / d out for the backward pass; loss_dev (may be NULL) receives
  * the loss as a device float */

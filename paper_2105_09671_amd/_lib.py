@@ -109,6 +109,7 @@ SIGNATURES = {
     "ac_sur_set_weights": ([_vp, ctypes.POINTER(ctypes.c_float), _i64], _i32),
     "ac_sur_get_weights": ([_vp, ctypes.POINTER(ctypes.c_float), _i64], _i32),
     "ac_sur_forward": ([_vp, _vp, _vp, _i32], _i32),
+    "ac_sur_infer": ([_vp, _vp, _vp, _i32], _i32),
     "ac_sur_loss": ([_vp, _vp, _i32, _vp], _i32),
     "ac_sur_backward": ([_vp, _i32], _i32),
     "ac_sur_get_grads": ([_vp, ctypes.POINTER(ctypes.c_float), _i64], _i32),

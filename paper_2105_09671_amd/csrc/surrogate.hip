@@ -37,10 +37,16 @@ namespace sur {
 // channels, K = KS*KS*Cin ordered (tap, ci) like the weights [Cout][tap][Cin].
 // UP: X is at low resolution and each result goes to a 2x2 block of Y.
 // Tile (32 WM) x (32 WN); 32-channel layers use WN = 1 so no MFMA lane idles.
-template <int KS, bool UP, int WM, int WN, int TM = 2, int TN = 2>
+// HEAD (inference): the layer has 32 output channels, all in one workgroup
+// column and one wave; instead of storing them the epilogue rounds each
+// activation to BF16 (as a store and reload would), applies the 1x1 head and
+// the residual, and writes out[p] = phi[p] + hb + sum_c a_c wh[c].
+template <int KS, bool UP, int WM, int WN, int TM = 2, int TN = 2, bool HEAD = false>
 __global__ void __launch_bounds__(256)
 conv_fwd_kernel(View X, int lgCin, int B, int H, int W, const bf16_t *__restrict__ Wk,
-                const float *__restrict__ bias, int Cout, View Y, int relu)
+                const float *__restrict__ bias, int Cout, View Y, int relu,
+                const float *__restrict__ wh, const float *__restrict__ hb,
+                const float *__restrict__ phi, float *__restrict__ out)
 {
     constexpr int TBM = 16 * TM * WM, TBN = 16 * TN * WN;
     constexpr int NA = (TBM * 4 + 255) / 256, NB = (TBN * 4 + 255) / 256;
@@ -108,6 +114,29 @@ conv_fwd_kernel(View X, int lgCin, int B, int H, int W, const bf16_t *__restrict
         }
         mma_step_g<WM, WN, TM, TN>(As, Bs, acc);
         __syncthreads();
+    }
+    if constexpr (HEAD) {
+        static_assert(WN == 1 && 16 * TN == 32, "head epilogue needs the 32 channels in one wave");
+        // lanes with equal lane / 16 hold the 32 channels of one pixel row
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                int row = 0, col = 0;
+                float part = 0.f;
+#pragma unroll
+                for (int j = 0; j < TN; ++j) {
+                    acc_coord_g<WM, WN, TM, TN>(i, j, q, &row, &col);
+                    float v = acc[i][j][q] + bias[col];
+                    v = v > 0.f ? v : 0.f;
+                    part += bf2f(f2bf(v)) * wh[col];
+                }
+#pragma unroll
+                for (int m = 1; m < 16; m <<= 1) part += __shfl_xor(part, m, 64);
+                const int mg = m0 + row;
+                if ((threadIdx.x & 15) == 0 && mg < M) out[mg] = phi[mg] + (hb[0] + part);
+            }
+        return;
     }
 #pragma unroll
     for (int i = 0; i < TM; ++i)
@@ -628,7 +657,9 @@ void launch_fwd(ac_sur *s, int l, View X, int lgcin, int B, int H, int W, View Y
     const int M = B * H * W, TBM = 16 * TM * WM, TBN = 16 * TN * WN;
     dim3 grid(xcd_grid((M + TBM - 1) / TBM), (L.cout + TBN - 1) / TBN);
     hipLaunchKernelGGL((conv_fwd_kernel<KS, UP, WM, WN, TM, TN>), grid, dim3(256), 0, s->st, X, lgcin, B,
-                       H, W, wk_of(s, l), bias_of(s, l), L.cout, Y, (int)relu);
+                       H, W, wk_of(s, l), bias_of(s, l), L.cout, Y, (int)relu,
+                       (const float *)nullptr, (const float *)nullptr, (const float *)nullptr,
+                       (float *)nullptr);
 }
 
 void conv_fwd(ac_sur *s, int l, View X, int B, int H, int W, View Y, bool relu, bool up) {
@@ -855,6 +886,40 @@ ac_status ac_sur_forward(ac_sur *s, const float *phi_in, float *phi_out, int32_t
     s->have_loss = false;
     s->last_batch = batch;
     s->last_phi = phi_in;
+    return AC_OK;
+}
+
+ac_status ac_sur_infer(ac_sur *s, const float *phi_in, float *phi_out, int32_t batch) {
+    g_err.clear();
+    if (!s || !phi_in || !phi_out) return fail(AC_ERR_INVALID_ARG, "null handle, input or output");
+    if (batch < 1 || batch > s->Bmax) return fail(AC_ERR_INVALID_ARG, "batch %d outside 1..%d", batch, s->Bmax);
+    const int B = batch, H = s->H, W = s->W, H2 = H / 2, W2 = W / 2, H4 = H / 4, W4 = W / 4;
+    const int n1 = B * H * W;
+    hipLaunchKernelGGL(pack_input_kernel, grid1(n1), dim3(256), 0, s->st, phi_in, s->x0, n1);
+    conv_fwd(s, L_E1A, V(s->x0, 8), B, H, W, V(s->e1a, 32), true, false);
+    conv_fwd(s, L_E1B, V(s->e1a, 32), B, H, W, V(s->cat1, 64, 32), true, false);
+    hipLaunchKernelGGL(pool_kernel, grid1((long long)n1 / 4 * 4), dim3(256), 0, s->st, V(s->cat1, 64, 32),
+                       32, B, H, W, V(s->p1, 32));
+    conv_fwd(s, L_E2A, V(s->p1, 32), B, H2, W2, V(s->e2a, 64), true, false);
+    conv_fwd(s, L_E2B, V(s->e2a, 64), B, H2, W2, V(s->cat2, 128, 64), true, false);
+    hipLaunchKernelGGL(pool_kernel, grid1((long long)n1 / 16 * 8), dim3(256), 0, s->st, V(s->cat2, 128, 64),
+                       64, B, H2, W2, V(s->p2, 64));
+    conv_fwd(s, L_BT, V(s->p2, 64), B, H4, W4, V(s->bt, 128), true, false);
+    conv_fwd(s, L_U2, V(s->bt, 128), B, H4, W4, V(s->cat2, 128, 0), false, true);
+    conv_fwd(s, L_D2, V(s->cat2, 128), B, H2, W2, V(s->d2, 64), true, false);
+    conv_fwd(s, L_U1, V(s->d2, 64), B, H2, W2, V(s->cat1, 64, 0), false, true);
+    // last 3x3 layer with the head and the residual in its epilogue
+    const LayerDef &L = kLayers[L_D1];
+    const int M = n1;
+    dim3 grid(xcd_grid((M + 127) / 128), (L.cout + 31) / 32);
+    hipLaunchKernelGGL((conv_fwd_kernel<3, false, 4, 1, 2, 2, true>), grid, dim3(256), 0, s->st,
+                       V(s->cat1, 64), lg2(L.cin), B, H, W, wk_of(s, L_D1), bias_of(s, L_D1), L.cout,
+                       V(s->d1, 32), 1, s->w32 + s->woff[L_HEAD], s->w32 + s->boff[L_HEAD], phi_in,
+                       phi_out);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "surrogate inference");
+    s->have_fwd = false;             // activations are not those of a forward for backward
+    s->have_loss = false;
     return AC_OK;
 }
 

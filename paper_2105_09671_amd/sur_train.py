@@ -125,7 +125,7 @@ def validate(net: Surrogate, data: torch.Tensor, kinds) -> dict:
             for s in range(0, len(idx), B):
                 sub = torch.tensor(idx[s:s + B], device="cuda")
                 x = data[sub, k].contiguous()
-                net.forward(x, pred[:len(sub)])
+                net.infer(x, pred[:len(sub)])
                 se += float(((pred[:len(sub)] - data[sub, k + 1]) ** 2).sum().item())
                 n += len(sub) * HW * HW
             row.append(se / n)
@@ -141,18 +141,18 @@ FORWARD_FLOP = 2 * sum(ci * co * k * k * (HW // f) ** 2 for ci, co, k, f in [
 
 
 def forward_rate(net: Surrogate, n: int, reps: int = 3) -> dict:
-    """Time the forward pass alone on n grids: ms per call and TFLOP/s."""
+    """Time the inference forward pass alone on n grids: ms per call and TFLOP/s."""
     x = torch.zeros(n, HW, HW, device="cuda")
     y = torch.empty_like(x)
     B = net.batch_max
     for s in range(0, n, B):
-        net.forward(x[s:s + B], y[s:s + B])
+        net.infer(x[s:s + B], y[s:s + B])
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(reps):
         for s in range(0, n, B):
-            net.forward(x[s:s + B], y[s:s + B])
+            net.infer(x[s:s + B], y[s:s + B])
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
@@ -196,7 +196,7 @@ def evaluate(net: Surrogate, seeds, T_blocks: int = 20, sample_every: int = 16,
     fb.step_masked(K_STEPS, active)                     # builds the plan; steps nothing
     pred = torch.empty_like(state)
     B = net.batch_max
-    net.forward(state[:min(N, B)].contiguous(), pred[:min(N, B)])   # warm-up
+    net.infer(state[:min(N, B)].contiguous(), pred[:min(N, B)])     # warm-up
     torch.cuda.synchronize()
     # book-keeping on the host: which grids are trusted, sampled, stepped
     trusted = np.ones(N, dtype=bool)
@@ -218,7 +218,7 @@ def evaluate(net: Surrogate, seeds, T_blocks: int = 20, sample_every: int = 16,
             x = state.index_select(0, dev(tidx))
             out = torch.empty_like(x)
         for s in range(0, nt, B):
-            net.forward(x[s:s + B], out[s:s + B])
+            net.infer(x[s:s + B], out[s:s + B])
         act = ~trusted
         act[samp] = True
         active.copy_(torch.from_numpy(act.astype(np.int32)))

@@ -81,6 +81,19 @@ class Surrogate:
         L.check(L.lib().ac_sur_forward(self._h, phi.data_ptr(), out.data_ptr(), b), "ac_sur_forward")
         return out
 
+    def infer(self, phi: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """forward() for inference: the head and residual run in the last
+        layer's epilogue; no activations are kept for backward()."""
+        b = self._check(phi)
+        if out is None:
+            out = torch.empty_like(phi)
+        else:
+            self._check(out)
+            if out.data_ptr() == phi.data_ptr():
+                raise ValueError("out must not alias phi")
+        L.check(L.lib().ac_sur_infer(self._h, phi.data_ptr(), out.data_ptr(), b), "ac_sur_infer")
+        return out
+
     def loss(self, target: torch.Tensor) -> torch.Tensor:
         b = self._check(target)
         L.check(L.lib().ac_sur_loss(self._h, target.data_ptr(), b, self._loss.data_ptr()), "ac_sur_loss")

@@ -57,10 +57,42 @@ def test_forward_matches_oracle(sur, B, hw):
     net.close()
 
 
+@pytest.mark.parametrize("B,hw", [(3, 20), (2, 32), (1, 64)])
+def test_infer_matches_forward_and_oracle(sur, B, hw):
+    """The fused inference path (head and residual in the last layer's
+    epilogue) against the unfused forward: the same BF16 activations, so only
+    the FP32 order of the 32-term head sum differs; and against the oracle to
+    the forward's own bar.  B*hw*hw = 1200 leaves a ragged last 128-row tile."""
+    w, phi, _ = _case(62, B, hw)
+    net = sur.Surrogate(B, hw)
+    net.set_weights(w.astype(np.float32))
+    x = torch.from_numpy(phi.astype(np.float32)).cuda()
+    a = net.forward(x).cpu().numpy().astype(np.float64)
+    y = torch.full_like(x, float("nan"))
+    b = net.infer(x, y).cpu().numpy().astype(np.float64)
+    scale = max(1.0, float(np.max(np.abs(a - phi))))
+    assert np.all(np.isfinite(b))
+    assert np.max(np.abs(a - b)) <= 1e-5 * scale
+    ref = S.forward(w, phi)
+    U, Ur = b - phi, ref - phi
+    assert _rel(U, Ur) <= 1e-2
+    assert np.max(np.abs(U - Ur)) <= 5e-2 * np.max(np.abs(Ur))
+    # a smaller batch on the same handle, and no backward state left behind
+    b1 = net.infer(x[:1].contiguous()).cpu().numpy().astype(np.float64)
+    assert np.array_equal(b1, b[:1])
+    from paper_2105_09671_amd import _lib as L
+    with pytest.raises(L.AcError):
+        net.loss(x)
+    with pytest.raises(ValueError):
+        net.infer(x, x)
+    net.close()
+
+
 def test_zero_weights_give_phi(sur):
     net = sur.Surrogate(2, 16)
     x = torch.from_numpy(inputs.random_field((2, 16, 16), 61).astype(np.float32)).cuda()
     assert torch.equal(net.forward(x), x)
+    assert torch.equal(net.infer(x), x)
     net.close()
 
 
