@@ -36,9 +36,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 NSTEPS = 20000
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_tile2d_inplace_circle2048_fp32.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_tile2d_reg_circle2048_fp32.json")
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2105_09671_amd", "csrc", f)
-               for f in ("stencil2d.hip", "tile2d.h", "ac_internal.h")]
+               for f in ("stencil2d.hip", "reg2d.h", "ac_internal.h")]
 
 
 def log(*a):
@@ -359,8 +359,8 @@ def main():
     achieved = alg_bytes / avg_launch / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
-            "kernel": ("tile2d_inplace_kernel<float>" if plan["kernel"] == 3
-                       else "tile2d_kernel<float,%d>" % plan["tile_x"]),
+            "kernel": {4: "tile2d_reg_kernel<float>", 3: "tile2d_inplace_kernel<float>"}.get(
+                plan["kernel"], "tile2d_kernel<float,%d>" % plan["tile_x"]),
             "algorithmic_bytes_per_launch": int(alg_bytes),
             "avg_launch_us": round(avg_launch * 1e6, 3), "launches_timed": launches}
 

@@ -60,6 +60,8 @@ typedef enum { AC_F32 = 0, AC_F64 = 1 } ac_dtype;
  *   tb_depth  time steps fused per launch (temporal blocking), 1..8
  *   tile_x/y  loaded tile extent in cells, including the tb_depth halo
  *   tile_z    2D: unused; 3D: z-extent of one streamed column segment
+ *   kernel    2D tiled kernel; AC_KERNEL_2D_REG needs tile_x = 64 and tile_y a
+ *             multiple of 16 up to 256, AC_KERNEL_2D_INPLACE tile_x = 64
  * Any valid choice gives bitwise the same result: every cell is always
  * updated by the same expression from the same neighbour values. */
 typedef struct {
@@ -67,6 +69,7 @@ typedef struct {
     int32_t tile_x;
     int32_t tile_y;
     int32_t tile_z;
+    int32_t kernel;   /* 2D tiled: 0 = choose, or AC_KERNEL_2D_TILED / _INPLACE / _REG */
 } ac_tune;
 
 /* 2D step, 5-point stencil (section 2.1, Eq. pytorchACeq).  phi, work: nx*ny
@@ -98,7 +101,9 @@ enum {
     AC_KERNEL_2D_RESIDENT = 0, /* whole grid in one workgroup's LDS, all steps in one launch */
     AC_KERNEL_2D_TILED = 1,    /* LDS tiles, tb_depth steps per launch */
     AC_KERNEL_3D_STREAM = 2,   /* z-streamed tiles, tb_depth levels per launch */
-    AC_KERNEL_2D_INPLACE = 3   /* 64-wide LDS tiles updated in place, tb_depth steps per launch */
+    AC_KERNEL_2D_INPLACE = 3,  /* 64-wide LDS tiles updated in place, tb_depth steps per launch */
+    AC_KERNEL_2D_REG = 4       /* 64-wide tiles held in registers (16 rows per wave), x
+                                * neighbours by cross-lane shifts, tb_depth steps per launch */
 };
 
 /* What a stepping call with the same arguments launches (filled by ac_plan_*). */

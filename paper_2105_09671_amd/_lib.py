@@ -23,7 +23,8 @@ AC_F32, AC_F64 = 0, 1
 
 class AcTune(ctypes.Structure):
     _fields_ = [("tb_depth", ctypes.c_int32), ("tile_x", ctypes.c_int32),
-                ("tile_y", ctypes.c_int32), ("tile_z", ctypes.c_int32)]
+                ("tile_y", ctypes.c_int32), ("tile_z", ctypes.c_int32),
+                ("kernel", ctypes.c_int32)]
 
 
 class AcPlan(ctypes.Structure):
@@ -61,7 +62,7 @@ class AcBatchInfo(ctypes.Structure):
 AC_TUNE_2D, AC_TUNE_3D, AC_TUNE_BATCHED = 2, 3, 4
 
 KERNEL_NAMES = {0: "tile2d_kernel (resident)", 1: "tile2d_kernel", 2: "stream3d_kernel",
-                3: "tile2d_inplace_kernel"}
+                3: "tile2d_inplace_kernel", 4: "tile2d_reg_kernel"}
 
 
 class AcError(RuntimeError):

@@ -57,7 +57,7 @@ def _tune(tune):
     if isinstance(tune, L.AcTune):
         return ctypes.byref(tune)
     t = L.AcTune(int(tune.get("tb_depth", 0)), int(tune.get("tile_x", 0)),
-                 int(tune.get("tile_y", 0)), int(tune.get("tile_z", 0)))
+                 int(tune.get("tile_y", 0)), int(tune.get("tile_z", 0)), int(tune.get("kernel", 0)))
     return ctypes.byref(t)
 
 

@@ -82,24 +82,37 @@ Chunks plan_chunks(int64_t nsteps, int64_t k) {
 // A plan fixes the kernel, its launch shape and the launch sequence of one
 // call.  Built on the host from the device limits; executing it makes no other
 // decision, so ac_plan_* reports exactly what ac_step_* will launch.
-// Steady-state throughput of the in-place 2D kernel on MI355X (GLUPS on a
-// 16384^2 grid, where every CU runs many tiles back to back), by depth and
-// tile height.
+// Steady-state throughput of the tiled 2D kernels on MI355X (GLUPS on a
+// 16384^2 grid in FP32, 16384 x 8192 in FP64, where every CU runs many tiles
+// back to back), by depth and tile height.
 struct TileRate { int K, LY; double glups; };
-static const TileRate kRateF32[] = {{6, 64, 1603}, {7, 64, 1617}, {8, 64, 1645},
-                                    {6, 128, 1682}, {7, 128, 1707}, {8, 128, 1732}};
-static const TileRate kRateF64[] = {{3, 32, 666}, {4, 32, 749}, {5, 32, 758}, {6, 32, 730},
-                                    {3, 64, 661}, {4, 64, 719}, {5, 64, 731}, {6, 64, 725}};
+static const TileRate kRegF32[] = {{4, 64, 1923}, {4, 128, 2056}, {4, 192, 2019},
+                                   {5, 64, 2287}, {5, 128, 2255}, {5, 192, 1936},
+                                   {6, 64, 2359}, {6, 128, 2564}, {6, 192, 2538},
+                                   {7, 64, 2448}, {7, 128, 2637}, {7, 192, 2531},
+                                   {8, 64, 2405}, {8, 128, 2718}, {8, 192, 2537}};
+static const TileRate kRegF64[] = {{4, 64, 1273}, {4, 128, 1269}, {4, 192, 1256},
+                                   {5, 64, 1343}, {5, 128, 1254}, {5, 192, 1219},
+                                   {6, 64, 1371}, {6, 128, 1485}, {6, 192, 1482},
+                                   {7, 64, 1364}, {7, 128, 1540}, {7, 192, 1503},
+                                   {8, 64, 1352}, {8, 128, 1550}, {8, 192, 1559}};
+static const TileRate kInplaceF32[] = {{6, 64, 1603}, {7, 64, 1617}, {8, 64, 1645},
+                                       {6, 128, 1682}, {7, 128, 1707}, {8, 128, 1732}};
+static const TileRate kInplaceF64[] = {{3, 32, 666}, {4, 32, 749}, {5, 32, 758}, {6, 32, 730},
+                                       {3, 64, 661}, {4, 64, 719}, {5, 64, 731}, {6, 64, 725}};
 
 // Predicted time of a launch ~ (rounds of resident tiles) x (time of one full
 // round), a full round taking S tiles of OX*OY*K updates at the steady rate
 // (S = resident tiles on the device).  A grid whose tile count just exceeds a
 // multiple of S pays a whole extra round, so the depth and tile height are
 // chosen per grid.
-void choose_tile2d(int nx, int ny, size_t elem, const ac::DevInfo &dev, int *K, int *LY) {
-    const TileRate *tab = elem == 8 ? kRateF64 : kRateF32;
-    const int n = elem == 8 ? (int)(sizeof kRateF64 / sizeof *kRateF64)
-                            : (int)(sizeof kRateF32 / sizeof *kRateF32);
+void choose_tile2d(int nx, int ny, size_t elem, bool reg, const ac::DevInfo &dev, int *K, int *LY) {
+    const bool f64 = elem == 8;
+    const TileRate *tab = reg ? (f64 ? kRegF64 : kRegF32) : (f64 ? kInplaceF64 : kInplaceF32);
+    const int n = reg ? (f64 ? (int)(sizeof kRegF64 / sizeof *kRegF64)
+                             : (int)(sizeof kRegF32 / sizeof *kRegF32))
+                      : (f64 ? (int)(sizeof kInplaceF64 / sizeof *kInplaceF64)
+                             : (int)(sizeof kInplaceF32 / sizeof *kInplaceF32));
     double best = -1.0;
     *K = tab[0].K;
     *LY = tab[0].LY;
@@ -108,7 +121,8 @@ void choose_tile2d(int nx, int ny, size_t elem, const ac::DevInfo &dev, int *K, 
         const int OX = 64 - 2 * k, OY = ly - 2 * k;
         const int64_t tiles = (int64_t)((nx + OX - 1) / OX) * ((ny + OY - 1) / OY);
         if ((ny + OY - 1) / OY > 65535) continue;
-        const int per_cu = ac::tile2d_inplace_blocks_per_cu(ly, elem);
+        const int per_cu = reg ? ac::tile2d_reg_blocks_per_cu(ly, elem)
+                               : ac::tile2d_inplace_blocks_per_cu(ly, elem);
         const int64_t slots = (int64_t)std::max(per_cu, 1) * std::max(dev.cus, 1);
         const int64_t rounds = (tiles + slots - 1) / slots;
         const double round_time = (double)slots * OX * OY * k / tab[i].glups;
@@ -135,18 +149,21 @@ ac_status make_plan2d(int nx, int ny, int64_t nsteps, size_t elem, const ac_tune
         p->lds_bytes = (int64_t)ac::tile2d_lds_bytes(nx, ny, elem);
         return AC_OK;
     }
-    const bool f64 = elem == 8;
-    int K = 0, LX = 64, LY = 0;
+    int K = 0, LX = 64, LY = 0, kern = 0;
     if (tune) {
         K = tune->tb_depth;
         if (tune->tile_x > 0) LX = tune->tile_x;
         if (tune->tile_y > 0) LY = tune->tile_y;
+        kern = tune->kernel;
     }
+    if (kern != 0 && kern != AC_KERNEL_2D_TILED && kern != AC_KERNEL_2D_INPLACE &&
+        kern != AC_KERNEL_2D_REG)
+        return fail(AC_ERR_UNSUPPORTED, "kernel %d is not a tiled 2D kernel", kern);
     if (!K || !LY) {
-        // default: the (depth, tile height) of the in-place kernel with the best
-        // predicted time on this grid
+        // default: the (depth, tile height) with the best predicted time on
+        // this grid, for the register kernel unless another one is asked for
         int dK = 0, dLY = 0;
-        choose_tile2d(nx, ny, elem, dev, &dK, &dLY);
+        choose_tile2d(nx, ny, elem, kern == 0 || kern == AC_KERNEL_2D_REG, dev, &dK, &dLY);
         if (!K) K = dK;
         if (!LY) LY = dLY;
     }
@@ -154,22 +171,36 @@ ac_status make_plan2d(int nx, int ny, int64_t nsteps, size_t elem, const ac_tune
     if (LX < 2 * K + 1 || LY < 2 * K + 1 || LX > 4096 || LY > 4096)
         return fail(AC_ERR_UNSUPPORTED, "tile %dx%d too small/large for depth %d", LX, LY, K);
     const int rch = ac::rows_per_chunk(elem);
-    // 64-wide tiles of at most 16 row chunks run in place (one LDS buffer)
-    const bool inplace = LX == 64 && (LY + rch - 1) / rch <= 16;
-    const size_t lds = inplace ? ac::tile2d_inplace_lds_bytes(LY, elem) : ac::tile2d_lds_bytes(LX, LY, elem);
+    // 64-wide tiles of whole 16-row wave blocks (at most 16 waves) run from
+    // registers; other 64-wide tiles of at most 16 row chunks in place in LDS
+    const bool reg_ok = LX == 64 && LY % ac::kRegRows == 0 && LY / ac::kRegRows <= 16;
+    const bool inplace_ok = LX == 64 && (LY + rch - 1) / rch <= 16;
+    int kernel = AC_KERNEL_2D_TILED;
+    if (kern == AC_KERNEL_2D_REG || kern == AC_KERNEL_2D_INPLACE) {
+        if (!(kern == AC_KERNEL_2D_REG ? reg_ok : inplace_ok))
+            return fail(AC_ERR_UNSUPPORTED, "tile %dx%d does not fit kernel %d", LX, LY, kern);
+        kernel = kern;
+    } else if (kern == 0) {
+        kernel = reg_ok ? AC_KERNEL_2D_REG : inplace_ok ? AC_KERNEL_2D_INPLACE : AC_KERNEL_2D_TILED;
+    }
+    const size_t lds = kernel == AC_KERNEL_2D_REG ? ac::tile2d_reg_lds_bytes(LY, elem)
+                       : kernel == AC_KERNEL_2D_INPLACE ? ac::tile2d_inplace_lds_bytes(LY, elem)
+                                                        : ac::tile2d_lds_bytes(LX, LY, elem);
     if (lds > dev.lds_per_block)
         return fail(AC_ERR_UNSUPPORTED, "tile %dx%d needs %zu B LDS > %zu", LX, LY, lds,
                     dev.lds_per_block);
     const int64_t gy = (ny + (LY - 2 * K) - 1) / (LY - 2 * K);
     if (gy > 65535) return fail(AC_ERR_UNSUPPORTED, "grid of %lld tile rows exceeds 65535", (long long)gy);
     const Chunks c = plan_chunks(nsteps, K);
-    p->kernel = inplace ? AC_KERNEL_2D_INPLACE : AC_KERNEL_2D_TILED;
+    p->kernel = kernel;
     p->tb_depth = K;
     p->tile_x = LX;
     p->tile_y = LY;
-    // one wave per row chunk of the widest sub-step (in place: of the tile), at most 16
-    p->threads = inplace ? ac::tile2d_inplace_threads(LY, elem)
-                         : 64 * std::max(1, std::min(16, (LY - 2 + rch - 1) / rch));
+    // register kernel: one wave per 16 rows; in place: one wave per row chunk
+    // of the tile; two buffers: per row chunk of the widest sub-step, at most 16
+    p->threads = kernel == AC_KERNEL_2D_REG       ? 64 * (LY / ac::kRegRows)
+                 : kernel == AC_KERNEL_2D_INPLACE ? ac::tile2d_inplace_threads(LY, elem)
+                                                  : 64 * std::max(1, std::min(16, (LY - 2 + rch - 1) / rch));
     p->launches = nsteps > 0 ? c.n : 0;
     p->copy_back = nsteps > 0 && c.copy_back;
     p->lds_bytes = (int64_t)lds;
@@ -243,7 +274,8 @@ ac_status run2d(T *phi, T *work, int nx, int ny, double alpha_d, double r_d, int
     T *src = phi, *dst = work;
     for (int64_t i = 0; i < c.n; ++i) {
         const int k = (int)(c.base + (i < c.rem ? 1 : 0));
-        e = p.kernel == AC_KERNEL_2D_INPLACE
+        e = p.kernel == AC_KERNEL_2D_REG ? ac::launch_tile2d_reg<T>(src, dst, nx, ny, alpha, r, t, k, stream)
+            : p.kernel == AC_KERNEL_2D_INPLACE
                 ? ac::launch_tile2d_inplace<T>(src, dst, nx, ny, alpha, r, t, k, stream)
                 : ac::launch_tile2d<T>(src, dst, nx, ny, alpha, r, t, k, stream);
         if (e != hipSuccess) return hip_fail(e, "tiled 2D launch");

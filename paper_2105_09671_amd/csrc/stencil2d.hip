@@ -21,6 +21,7 @@
 // A sub-step deals chunks of rows (16 in FP32, 8 in FP64) round-robin to the
 // waves; in a chunk each lane issues all LDS reads of its column before any
 // arithmetic, and the 64 lanes of a wave touch 64 consecutive LDS words.
+#include "reg2d.h"
 #include "tile2d.h"
 
 namespace ac {
@@ -87,6 +88,46 @@ template hipError_t launch_tile2d_inplace<float>(const float *, float *, int, in
                                                  const Tile2D &, int, hipStream_t);
 template hipError_t launch_tile2d_inplace<double>(const double *, double *, int, int, double,
                                                   double, const Tile2D &, int, hipStream_t);
+
+// Register-resident variant (reg2d.h): 64-wide tiles, kRegRows rows per wave.
+template <typename T>
+__global__ void __launch_bounds__(1024)
+tile2d_reg_kernel(const T *src, T *dst, int nx, int ny, T alpha, T r, int halo, int ksteps)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    reg2d_body<T, kRegRows>(src, dst, nx, ny, alpha, r, halo, ksteps, blockIdx.x, blockIdx.y,
+                            reinterpret_cast<T *>(smem_raw));
+}
+
+int tile2d_reg_blocks_per_cu(int LY, size_t elem) {
+    const void *k = elem == 8 ? (const void *)tile2d_reg_kernel<double>
+                              : (const void *)tile2d_reg_kernel<float>;
+    const int nw = LY / kRegRows;
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, 64 * nw, tile2d_reg_lds_bytes(LY, elem)) !=
+        hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return n;
+}
+
+template <typename T>
+hipError_t launch_tile2d_reg(const T *src, T *dst, int nx, int ny, T alpha, T r, const Tile2D &t,
+                             int ksteps, hipStream_t stream)
+{
+    const int nw = t.LY / kRegRows;
+    const int OX = 64 - 2 * t.halo, OY = t.LY - 2 * t.halo;
+    dim3 grid((nx + OX - 1) / OX, (ny + OY - 1) / OY);
+    hipLaunchKernelGGL(tile2d_reg_kernel<T>, grid, dim3(64 * nw), tile2d_reg_lds_bytes(t.LY, sizeof(T)),
+                       stream, src, dst, nx, ny, alpha, r, t.halo, ksteps);
+    return hipGetLastError();
+}
+
+template hipError_t launch_tile2d_reg<float>(const float *, float *, int, int, float, float,
+                                             const Tile2D &, int, hipStream_t);
+template hipError_t launch_tile2d_reg<double>(const double *, double *, int, int, double, double,
+                                              const Tile2D &, int, hipStream_t);
 
 size_t tile2d_lds_bytes(int LX, int LY, size_t elem) {
     return 2 * (size_t)lds_pitch(LX) * lds_rows(LY, elem) * elem;

@@ -82,11 +82,13 @@ static ac_status sweep(const std::vector<ac_tune> &cands, hipStream_t st, F fn, 
 
 static std::vector<ac_tune> cands2d() {
     std::vector<ac_tune> v;
-    // 64-wide tiles run in place with one wave per 16 (FP32) or 8 (FP64) rows;
-    // heights that are multiples of 4 waves keep the SIMDs of a CU balanced
-    const int tiles[][2] = {{64, 32}, {64, 64}, {64, 128}, {128, 64}};
+    // 64-wide tiles from registers (one wave per 16 rows) and in place in LDS
+    // (one wave per 16 FP32 or 8 FP64 rows), and a two-buffer LDS tile
+    const int tiles[][3] = {{64, 64, AC_KERNEL_2D_REG}, {64, 128, AC_KERNEL_2D_REG},
+                            {64, 256, AC_KERNEL_2D_REG}, {64, 64, AC_KERNEL_2D_INPLACE},
+                            {64, 128, AC_KERNEL_2D_INPLACE}, {128, 64, AC_KERNEL_2D_TILED}};
     for (int k : {3, 4, 5, 6, 7, 8})
-        for (auto &t : tiles) v.push_back(ac_tune{k, t[0], t[1], 0});
+        for (auto &t : tiles) v.push_back(ac_tune{k, t[0], t[1], 0, t[2]});
     return v;
 }
 
@@ -195,9 +197,10 @@ ac_status ac_tune_save(const char *path) {
     for (auto &kv : g_table) {
         const ac_tune &t = kv.second;
         std::fprintf(f, " {\"kind\": %d, \"dtype\": %d, \"cls\": %d, \"tb_depth\": %d, "
-                        "\"tile_x\": %d, \"tile_y\": %d, \"tile_z\": %d}%s\n",
+                        "\"tile_x\": %d, \"tile_y\": %d, \"tile_z\": %d, \"kernel\": %d}%s\n",
                      std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first),
-                     t.tb_depth, t.tile_x, t.tile_y, t.tile_z, ++i < g_table.size() ? "," : "");
+                     t.tb_depth, t.tile_x, t.tile_y, t.tile_z, t.kernel,
+                     ++i < g_table.size() ? "," : "");
     }
     std::fprintf(f, "]}\n");
     return std::fclose(f) == 0 ? AC_OK : fail(AC_ERR_INVALID_ARG, "write failed: %s", path);
@@ -213,10 +216,12 @@ ac_status ac_tune_load(const char *path) {
     std::map<std::tuple<int, int, int>, ac_tune> loaded;
     while (std::fgets(line, sizeof line, f)) {
         int kind, dtype, cls;
-        ac_tune t;
+        ac_tune t{};
+        // "kernel" is optional (tables written before it existed choose the kernel)
         if (std::sscanf(line, " {\"kind\": %d, \"dtype\": %d, \"cls\": %d, \"tb_depth\": %d, "
-                              "\"tile_x\": %d, \"tile_y\": %d, \"tile_z\": %d}",
-                        &kind, &dtype, &cls, &t.tb_depth, &t.tile_x, &t.tile_y, &t.tile_z) == 7) {
+                              "\"tile_x\": %d, \"tile_y\": %d, \"tile_z\": %d, \"kernel\": %d",
+                        &kind, &dtype, &cls, &t.tb_depth, &t.tile_x, &t.tile_y, &t.tile_z,
+                        &t.kernel) >= 7) {
             loaded[std::make_tuple(kind, dtype, cls)] = t;
             ++n;
         }

@@ -132,8 +132,8 @@ def test_tune_table_json_roundtrip(lib, tmp_path):
     assert lib.ac_tune_count() == 0
     src = tmp_path / "in.json"
     src.write_text('{"arch": "gfx950", "entries": [\n'
-                   ' {"kind": 2, "dtype": 0, "cls": 22, "tb_depth": 8, "tile_x": 64, "tile_y": 64, "tile_z": 0},\n'
-                   ' {"kind": 3, "dtype": 1, "cls": 24, "tb_depth": 3, "tile_x": 32, "tile_y": 16, "tile_z": 32}\n'
+                   ' {"kind": 2, "dtype": 0, "cls": 22, "tb_depth": 8, "tile_x": 64, "tile_y": 64, "tile_z": 0, "kernel": 4},\n'
+                   ' {"kind": 3, "dtype": 1, "cls": 24, "tb_depth": 3, "tile_x": 32, "tile_y": 16, "tile_z": 32, "kernel": 0}\n'
                    ']}\n')
     assert lib.ac_tune_load(str(src).encode()) == L.AC_OK
     assert lib.ac_tune_count() == 2
@@ -142,7 +142,14 @@ def test_tune_table_json_roundtrip(lib, tmp_path):
     lib.ac_tune_clear()
     assert lib.ac_tune_load(str(out).encode()) == L.AC_OK
     assert lib.ac_tune_count() == 2
-    assert out.read_text() == src.read_text().replace("gfx950", "gfx950")
+    assert out.read_text() == src.read_text()
+    # a table without the kernel field loads with the kernel left to the plan
+    old = tmp_path / "old.json"
+    old.write_text(src.read_text().replace(', "kernel": 4', "").replace(', "kernel": 0', ""))
+    lib.ac_tune_clear()
+    assert lib.ac_tune_load(str(old).encode()) == L.AC_OK
+    assert lib.ac_tune_save(str(out).encode()) == L.AC_OK
+    assert out.read_text() == src.read_text().replace('"kernel": 4', '"kernel": 0')
     bad = tmp_path / "bad.json"
     bad.write_text("{}")
     assert lib.ac_tune_load(str(bad).encode()) == L.AC_ERR_INVALID_ARG

@@ -74,9 +74,15 @@ def test_2d_tile_shapes_bitwise(api, dtype):
     h, dt, eps = _par(128, 5)
     phi0 = inputs.random_field((150, 170), seed=22).astype(NP[dtype])
     base = _run2d(api, phi0, h, dt, eps, 20, dtype, tune=dict(tb_depth=1, tile_x=-1))
-    for tx, ty, k in [(64, 64, 4), (128, 32, 3), (256, 16, 2), (96, 40, 8), (64, 17, 8)]:
-        got = _run2d(api, phi0, h, dt, eps, 20, dtype, tune=dict(tb_depth=k, tile_x=tx, tile_y=ty))
-        assert np.array_equal(got, base), (tx, ty, k)
+    # kernel 0: the plan's choice; 4: registers, 3: in place in LDS, 1: two LDS buffers
+    for tx, ty, k, kern in [(64, 64, 4, 0), (128, 32, 3, 0), (256, 16, 2, 0), (96, 40, 8, 0),
+                            (64, 17, 8, 0), (64, 16, 7, 4), (64, 48, 5, 4), (64, 256, 8, 4),
+                            (64, 128, 1, 4), (64, 64, 4, 3), (64, 64, 4, 1)]:
+        tune = dict(tb_depth=k, tile_x=tx, tile_y=ty, kernel=kern)
+        if kern:
+            assert api.plan2d(170, 150, 20, dtype, tune)["kernel"] == kern
+        got = _run2d(api, phi0, h, dt, eps, 20, dtype, tune=tune)
+        assert np.array_equal(got, base), (tx, ty, k, kern)
     res = _run2d(api, phi0, h, dt, eps, 20, dtype)       # LDS-resident path
     assert np.array_equal(res, base)
 
@@ -91,6 +97,23 @@ def test_2d_edge_shapes(api, shape, nsteps):
     for tune in (None, dict(tb_depth=3, tile_x=-1)):
         got = _run2d(api, phi0, h, dt, eps, nsteps, torch.float64, tune=tune)
         assert D.rel_linf(got, ref) <= 1e-12, tune
+
+
+def test_2d_plan_kernels(api):
+    from paper_2105_09671_amd import _lib as L
+    # large grids default to the register kernel
+    for dt_ in (torch.float32, torch.float64):
+        p = api.plan2d(2048, 2048, 100, dt_)
+        assert p["kernel"] == 4 and p["tile_x"] == 64 and p["tile_y"] % 16 == 0, p
+        assert p["threads"] == 64 * p["tile_y"] // 16
+    # 64-wide tiles whose height is not whole 16-row waves fall back to LDS
+    assert api.plan2d(2048, 2048, 100, torch.float32, dict(tb_depth=4, tile_y=40))["kernel"] == 3
+    with pytest.raises(L.AcError):
+        api.plan2d(2048, 2048, 100, torch.float32, dict(tb_depth=4, tile_y=40, kernel=4))
+    with pytest.raises(L.AcError):
+        api.plan2d(2048, 2048, 100, torch.float32, dict(tb_depth=4, tile_x=128, kernel=4))
+    with pytest.raises(L.AcError):
+        api.plan2d(2048, 2048, 100, torch.float32, dict(kernel=2))
 
 
 def test_2d_split_equals_single_call(api):
