@@ -1,8 +1,9 @@
 // Batched stepping: many independent 2D grids (own size, h, dt, eps) advanced
 // by one persistent kernel, captured once in a hipGraph and replayed.
 //
-// Work decomposition.  Every instance is cut into the same LDS tiles as the
-// single-grid tiled kernel (tile2d.h).  One "item" is one tile of one instance;
+// Work decomposition.  Every instance is cut into the same tiles as the
+// single-grid tiled kernels, with the tile body its plan chooses (reg2d.h for
+// register tiles, tile2d.h for LDS tiles).  One "item" is one tile of one instance;
 // the item list is the same for every temporal block ("phase") of tb_depth
 // steps.  A grid of workgroups, sized to what the device holds at once, takes
 // the items of phase b from ticket counters, meets at a phase barrier, and
@@ -34,6 +35,7 @@
 #include <mutex>
 #include <vector>
 
+#include "reg2d.h"
 #include "stream3d.h"
 #include "tile2d.h"
 
@@ -130,7 +132,26 @@ __device__ void copy_tile(const T *src, T *dst, int nx, int ny, int OX, int OY, 
     }
 }
 
-template <typename T, int LXC, bool INPLACE>
+// One tile of one instance with the single-grid plan's tile body: BODY_REG
+// (registers, 64-wide), BODY_INPLACE (one LDS buffer, 64-wide) or BODY_LDS2
+// (two LDS buffers, width LXC, or LX at run time when LXC = 0).
+enum { BODY_LDS2 = 0, BODY_INPLACE = 1, BODY_REG = 2 };
+
+template <typename T, int LXC, int BODY>
+__device__ __forceinline__ void tile_item(const T *src, T *dst, const BatchInst &I, int LX, int LY,
+                                          int K, int k, int tx, int ty, unsigned char *smem)
+{
+    if constexpr (BODY == BODY_REG)
+        reg2d_body<T, kRegRows>(src, dst, I.nx, I.ny, (T)I.alpha, (T)I.r, K, k, tx, ty,
+                                reinterpret_cast<T *>(smem));
+    else if constexpr (BODY == BODY_INPLACE)
+        tile2d_body<T, 64, Rows<T>::value, true, INPLACE_LB, INPLACE_D>(
+            src, dst, I.nx, I.ny, (T)I.alpha, (T)I.r, 64, LY, K, k, tx, ty, smem);
+    else
+        tile2d_body<T, LXC>(src, dst, I.nx, I.ny, (T)I.alpha, (T)I.r, LX, LY, K, k, tx, ty, smem);
+}
+
+template <typename T, int LXC, int BODY>
 __global__ void __launch_bounds__(1024)
 batched_kernel(const BatchInst *__restrict__ inst, const int4 *__restrict__ items, int n_items,
                int LX, int LY, int K, int nblocks, int base, int rem, int copy_back,
@@ -161,13 +182,7 @@ batched_kernel(const BatchInst *__restrict__ inst, const int4 *__restrict__ item
             if (b < nblocks) {
                 const T *src = static_cast<const T *>((b & 1) ? I.work : I.phi);
                 T *dst = static_cast<T *>((b & 1) ? I.phi : I.work);
-                if constexpr (INPLACE)
-                    tile2d_body<T, 64, Rows<T>::value, true, INPLACE_LB, INPLACE_D>(
-                        src, dst, I.nx, I.ny, (T)I.alpha, (T)I.r, 64, LY, K, k, it.y, it.z,
-                        smem_raw);
-                else
-                    tile2d_body<T, LXC>(src, dst, I.nx, I.ny, (T)I.alpha, (T)I.r, LX, LY, K, k,
-                                        it.y, it.z, smem_raw);
+                tile_item<T, LXC, BODY>(src, dst, I, LX, LY, K, k, it.y, it.z, smem_raw);
             } else {   // odd number of single-step phases: the result sits in work
                 copy_tile<T>(static_cast<const T *>(I.work), static_cast<T *>(I.phi), I.nx, I.ny,
                              LX - 2 * K, LY - 2 * K, it.y, it.z);
@@ -190,7 +205,7 @@ batched_kernel(const BatchInst *__restrict__ inst, const int4 *__restrict__ item
 // The ordering between phases is the kernel boundary, whose cache release and
 // acquire the command processor performs once per launch, where the
 // persistent kernel's barrier has every workgroup do its own.
-template <typename T, int LXC, bool INPLACE>
+template <typename T, int LXC, int BODY>
 __global__ void __launch_bounds__(1024)
 batched_phase_kernel(const BatchInst *__restrict__ inst, const int4 *__restrict__ items,
                      int n_items, int LX, int LY, int K, int k, int phase, int copy,
@@ -206,12 +221,7 @@ batched_phase_kernel(const BatchInst *__restrict__ inst, const int4 *__restrict_
     if (!copy) {
         const T *src = static_cast<const T *>((phase & 1) ? I.work : I.phi);
         T *dst = static_cast<T *>((phase & 1) ? I.phi : I.work);
-        if constexpr (INPLACE)
-            tile2d_body<T, 64, Rows<T>::value, true, INPLACE_LB, INPLACE_D>(
-                src, dst, I.nx, I.ny, (T)I.alpha, (T)I.r, 64, LY, K, k, it.y, it.z, smem_raw);
-        else
-            tile2d_body<T, LXC>(src, dst, I.nx, I.ny, (T)I.alpha, (T)I.r, LX, LY, K, k, it.y, it.z,
-                                smem_raw);
+        tile_item<T, LXC, BODY>(src, dst, I, LX, LY, K, k, it.y, it.z, smem_raw);
     } else {
         copy_tile<T>(static_cast<const T *>(I.work), static_cast<T *>(I.phi), I.nx, I.ny,
                      LX - 2 * K, LY - 2 * K, it.y, it.z);
@@ -372,37 +382,45 @@ void release(Plan &p) {
     p.d_bar = nullptr; p.d_err = nullptr;
 }
 
-template <typename T, int LXC, bool INPLACE = false>
-const void *kernel_ptr() { return (const void *)batched_kernel<T, LXC, INPLACE>; }
+template <typename T, int LXC, int BODY = BODY_LDS2>
+const void *kernel_ptr() { return (const void *)batched_kernel<T, LXC, BODY>; }
 
-template <typename T, int LXC, bool INPLACE = false>
-const void *phase_kernel_ptr() { return (const void *)batched_phase_kernel<T, LXC, INPLACE>; }
+template <typename T, int LXC, int BODY = BODY_LDS2>
+const void *phase_kernel_ptr() { return (const void *)batched_phase_kernel<T, LXC, BODY>; }
 
-const void *select_phase_kernel(int32_t dtype, int LX, bool inplace) {
-    if (dtype == AC_F64) {
-        if (inplace) return phase_kernel_ptr<double, 64, true>();
-        if (LX == 64) return phase_kernel_ptr<double, 64>();
-        if (LX == 128) return phase_kernel_ptr<double, 128>();
-        return phase_kernel_ptr<double, 0>();
-    }
-    if (inplace) return phase_kernel_ptr<float, 64, true>();
-    if (LX == 64) return phase_kernel_ptr<float, 64>();
-    if (LX == 128) return phase_kernel_ptr<float, 128>();
-    return phase_kernel_ptr<float, 0>();
+// the tile body the single-grid plan chose (AC_KERNEL_2D_*)
+int body_of(int plan_kernel) {
+    return plan_kernel == AC_KERNEL_2D_REG       ? BODY_REG
+           : plan_kernel == AC_KERNEL_2D_INPLACE ? BODY_INPLACE
+                                                 : BODY_LDS2;
 }
 
-// the tile body the single-grid plan chose: in place (64-wide tiles) or two buffers
-const void *select_kernel(int32_t dtype, int LX, bool inplace) {
-    if (dtype == AC_F64) {
-        if (inplace) return kernel_ptr<double, 64, true>();
-        if (LX == 64) return kernel_ptr<double, 64>();
-        if (LX == 128) return kernel_ptr<double, 128>();
-        return kernel_ptr<double, 0>();
-    }
-    if (inplace) return kernel_ptr<float, 64, true>();
-    if (LX == 64) return kernel_ptr<float, 64>();
-    if (LX == 128) return kernel_ptr<float, 128>();
-    return kernel_ptr<float, 0>();
+template <typename T>
+const void *phase_kernel_of(int LX, int body) {
+    if (body == BODY_REG) return phase_kernel_ptr<T, 64, BODY_REG>();
+    if (body == BODY_INPLACE) return phase_kernel_ptr<T, 64, BODY_INPLACE>();
+    if (LX == 64) return phase_kernel_ptr<T, 64>();
+    if (LX == 128) return phase_kernel_ptr<T, 128>();
+    return phase_kernel_ptr<T, 0>();
+}
+
+template <typename T>
+const void *kernel_of(int LX, int body) {
+    if (body == BODY_REG) return kernel_ptr<T, 64, BODY_REG>();
+    if (body == BODY_INPLACE) return kernel_ptr<T, 64, BODY_INPLACE>();
+    if (LX == 64) return kernel_ptr<T, 64>();
+    if (LX == 128) return kernel_ptr<T, 128>();
+    return kernel_ptr<T, 0>();
+}
+
+const void *select_phase_kernel(int32_t dtype, int LX, int plan_kernel) {
+    return dtype == AC_F64 ? phase_kernel_of<double>(LX, body_of(plan_kernel))
+                           : phase_kernel_of<float>(LX, body_of(plan_kernel));
+}
+
+const void *select_kernel(int32_t dtype, int LX, int plan_kernel) {
+    return dtype == AC_F64 ? kernel_of<double>(LX, body_of(plan_kernel))
+                           : kernel_of<float>(LX, body_of(plan_kernel));
 }
 
 // Validate every instance (no HIP call) and check no two buffers overlap.
@@ -441,10 +459,10 @@ ac_status build_plan(Plan &p, const ac_instance2d *inst, int32_t n, int64_t nste
     // launch shape: the single-grid tiled plan for the same tune (forced tiled)
     ac_tune t = tune;
     if (t.tile_x == 0) t.tile_x = 64;
-    // default: 64 x 128 in-place tiles (8 waves), fastest measured on the 512-grid
-    // and 256 x 256^2 batches
-    if (t.tile_y == 0) t.tile_y = dtype == AC_F64 ? 64 : 128;
-    if (t.tb_depth == 0) t.tb_depth = dtype == AC_F64 ? 5 : 8;
+    // default: depth 6 on 64 x 64 register tiles (4 waves), fastest measured on
+    // the 512-grid batch in both precisions (FP32 2200 GLUPS, FP64 1370)
+    if (t.tile_y == 0) t.tile_y = 64;
+    if (t.tb_depth == 0) t.tb_depth = 6;
     ac_plan tp;
     ac_status s = make_plan2d(4096, 4096, nsteps, elem, &t, dev, &tp);
     if (s != AC_OK) return s;
@@ -464,7 +482,7 @@ ac_status build_plan(Plan &p, const ac_instance2d *inst, int32_t n, int64_t nste
         return fail(AC_ERR_UNSUPPORTED, "%zu tiles x %lld phases exceed the 32-bit work counters",
                     items.size(), (long long)c.n);
     // workgroup size and LDS follow the tile body the plan chose
-    const void *kern = select_kernel(dtype, LX, tp.kernel == AC_KERNEL_2D_INPLACE);
+    const void *kern = select_kernel(dtype, LX, tp.kernel);
     const size_t lds = (size_t)tp.lds_bytes;
     const int threads = tp.threads;
     set_lds_limit(kern, lds);
@@ -527,7 +545,7 @@ ac_status build_plan(Plan &p, const ac_instance2d *inst, int32_t n, int64_t nste
     if (g_persistent) {
         le = hipLaunchKernel(kern, dim3(grid), dim3(threads), args, lds, cs);
     } else {
-        const void *pk = select_phase_kernel(dtype, LX, tp.kernel == AC_KERNEL_2D_INPLACE);
+        const void *pk = select_phase_kernel(dtype, LX, tp.kernel);
         set_lds_limit(pk, lds);
         for (int b = 0; b <= nblocks && le == hipSuccess; ++b) {
             const int copy = b == nblocks;
