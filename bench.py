@@ -364,6 +364,20 @@ def main():
             "algorithmic_bytes_per_launch": int(alg_bytes),
             "avg_launch_us": round(avg_launch * 1e6, 3), "launches_timed": launches}
 
+    # the same launches against the instruction-issue bound of the register
+    # kernel: 9 VALU instructions per computed cell (halo recomputation
+    # included), 256 CUs x 64 lanes x 2.4 GHz with packed FP32 off
+    roof_alu = None
+    if plan["kernel"] == 4:
+        K, LX, LY = plan["tb_depth"], plan["tile_x"], plan["tile_y"]
+        tiles = -(-g.nx // (LX - 2 * K)) * -(-g.ny // (LY - 2 * K))
+        computed = tiles * LX * LY * NSTEPS / plan["launches"]
+        peak = 256 * 64 * 2.4e9 / 9 / 1e9
+        ach = computed / avg_launch / 1e9
+        roof_alu = {"bound": "alu", "achieved": round(ach, 1), "peak": round(peak, 1),
+                    "unit": "G computed cell-updates/s", "frac": round(ach / peak, 4),
+                    "valu_per_cell": 9, "useful_fraction": round(cells / (tiles * LX * LY), 4)}
+
     # correctness check of the timed workload: one fresh solve, radius vs the law
     phi.copy_(phi_init)
     api.step2d(phi, g.h, g.dt, g.eps, NSTEPS)
@@ -388,7 +402,7 @@ def main():
         "config": {"workload": "circle2048: 2D 2048x2048, h=1/2048, dt=0.1h^2, eps_4, "
                                "circle R0=0.25, 20000 explicit steps per solve",
                    "nx": g.nx, "ny": g.ny, "nsteps": NSTEPS, "plan": plan},
-        "roofline": roof, "cpu_baseline": cpu, "radius_check": check, "extra": extra,
+        "roofline": roof, "roofline_alu": roof_alu, "cpu_baseline": cpu, "radius_check": check, "extra": extra,
     }
     print(json.dumps(line), flush=True)
 
