@@ -60,8 +60,10 @@ typedef enum { AC_F32 = 0, AC_F64 = 1 } ac_dtype;
  *   tb_depth  time steps fused per launch (temporal blocking), 1..8
  *   tile_x/y  loaded tile extent in cells, including the tb_depth halo
  *   tile_z    2D: unused; 3D: z-extent of one streamed column segment
- *   kernel    2D tiled kernel; AC_KERNEL_2D_REG needs tile_x = 64 and tile_y a
- *             multiple of 16 up to 256, AC_KERNEL_2D_INPLACE tile_x = 64
+ *   kernel    0 = choose; 2D: AC_KERNEL_2D_TILED / _INPLACE / _REG (_REG needs
+ *             tile_x = 64 and tile_y a multiple of 16 up to 256, _INPLACE
+ *             tile_x = 64); 3D: AC_KERNEL_3D_STREAM / _REG (_REG needs tile_x =
+ *             64, tile_y a multiple of 4 up to 32 and tb_depth <= 4)
  * Any valid choice gives bitwise the same result: every cell is always
  * updated by the same expression from the same neighbour values. */
 typedef struct {
@@ -102,8 +104,10 @@ enum {
     AC_KERNEL_2D_TILED = 1,    /* LDS tiles, tb_depth steps per launch */
     AC_KERNEL_3D_STREAM = 2,   /* z-streamed tiles, tb_depth levels per launch */
     AC_KERNEL_2D_INPLACE = 3,  /* 64-wide LDS tiles updated in place, tb_depth steps per launch */
-    AC_KERNEL_2D_REG = 4       /* 64-wide tiles held in registers (16 rows per wave), x
+    AC_KERNEL_2D_REG = 4,      /* 64-wide tiles held in registers (16 rows per wave), x
                                 * neighbours by cross-lane shifts, tb_depth steps per launch */
+    AC_KERNEL_3D_REG = 5       /* z-streamed 64-wide tiles held in registers (4 rows per
+                                * wave), tb_depth 1..4 levels per launch */
 };
 
 /* What a stepping call with the same arguments launches (filled by ac_plan_*). */

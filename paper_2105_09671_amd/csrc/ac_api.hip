@@ -101,6 +101,12 @@ static const TileRate kInplaceF32[] = {{6, 64, 1603}, {7, 64, 1617}, {8, 64, 164
 static const TileRate kInplaceF64[] = {{3, 32, 666}, {4, 32, 749}, {5, 32, 758}, {6, 32, 730},
                                        {3, 64, 661}, {4, 64, 719}, {5, 64, 731}, {6, 64, 725}};
 
+// 3D: the register kernel is the default from 3/4 of a round of resident
+// workgroups on (measured on MI355X: 256^3 FP32, 0.57 rounds, runs 8 % faster
+// on the LDS kernel; 320^3 FP32 (1.1 rounds) and 256^3 FP64 (0.78) run 9-19 %
+// faster on the register kernel, and 1024^3 FP32 27 %)
+static const int64_t kReg3dMinRoundsNum = 3, kReg3dMinRoundsDen = 4;
+
 // Predicted time of a launch ~ (rounds of resident tiles) x (time of one full
 // round), a full round taking S tiles of OX*OY*K updates at the steady rate
 // (S = resident tiles on the device).  A grid whose tile count just exceeds a
@@ -211,9 +217,29 @@ ac_status make_plan3d(int nx, int ny, int nz, int64_t nsteps, size_t elem, const
                       const ac::DevInfo &dev, ac_plan *p) {
     std::memset(p, 0, sizeof *p);
     const bool f64 = elem == 8;
-    // defaults measured on MI355X at 256^3: depth 4 / 32x32x32 in FP32,
-    // depth 3 / 32x16x32 in FP64
-    int K = f64 ? 3 : 4, LX = 32, LY = f64 ? 16 : 32, LZ = 32, threads = f64 ? 256 : 512;
+    const int kern = tune ? tune->kernel : 0;
+    if (kern != 0 && kern != AC_KERNEL_3D_STREAM && kern != AC_KERNEL_3D_REG)
+        return fail(AC_ERR_UNSUPPORTED, "kernel %d is not a 3D kernel", kern);
+    const bool shape_given = tune && (tune->tile_x > 0 || tune->tile_y > 0);
+    // the register kernel (64 x 32 tiles: 8 waves of 4 rows) is the default when
+    // the grid yields at least 3/4 of a round of its workgroups (z segments of
+    // 32 planes); smaller grids keep the LDS kernel's 32-wide tiles, which make
+    // more workgroups of the same grid
+    bool reg = kern == AC_KERNEL_3D_REG;
+    if (kern == 0 && !shape_given) {
+        const int rk = tune && tune->tb_depth ? tune->tb_depth : (f64 ? 3 : 4);
+        if (rk <= ac::kReg3dMaxDepth) {
+            const int64_t wgs = (int64_t)((nx + 63 - 2 * rk) / (64 - 2 * rk)) *
+                                ((ny + 31 - 2 * rk) / (32 - 2 * rk)) * ((nz + 31) / 32);
+            const int per_cu = ac::reg3d_blocks_per_cu(rk, 32, elem);
+            reg = wgs * kReg3dMinRoundsDen >=
+                  kReg3dMinRoundsNum * (int64_t)std::max(per_cu, 1) * std::max(dev.cus, 1);
+        }
+    }
+    // LDS-kernel defaults measured on MI355X at 256^3: depth 4 / 32x32x32 in
+    // FP32, depth 3 / 32x16x32 in FP64; register kernel: depth 4 FP32, 3 FP64
+    int K = f64 ? 3 : 4, LX = reg ? 64 : 32, LY = reg ? 32 : (f64 ? 16 : 32), LZ = 32;
+    int threads = f64 ? 256 : 512;
     if (tune) {
         if (tune->tb_depth) K = tune->tb_depth;
         if (tune->tile_x > 0) LX = tune->tile_x;
@@ -223,6 +249,16 @@ ac_status make_plan3d(int nx, int ny, int nz, int64_t nsteps, size_t elem, const
     if (K < 1 || K > 8) return fail(AC_ERR_UNSUPPORTED, "tb_depth must be 1..8, got %d", K);
     if (LX < 2 * K + 1 || LY < 2 * K + 1 || LZ < 1)
         return fail(AC_ERR_UNSUPPORTED, "tile %dx%dx%d too small for depth %d", LX, LY, LZ, K);
+    if (reg) {
+        if (LX != 64 || LY % ac::kReg3dRows || LY / ac::kReg3dRows > ac::kReg3dMaxWaves ||
+            K > ac::kReg3dMaxDepth)
+            return fail(AC_ERR_UNSUPPORTED,
+                        "3D register tiles need tile_x 64, tile_y a multiple of %d up to %d and "
+                        "depth <= %d (got %dx%d, depth %d)",
+                        ac::kReg3dRows, ac::kReg3dRows * ac::kReg3dMaxWaves, ac::kReg3dMaxDepth, LX,
+                        LY, K);
+        threads = 64 * (LY / ac::kReg3dRows);
+    }
     if (!tune || tune->tile_z <= 0) {
         // longer z segments re-stream fewer halo planes (2K per segment) but
         // leave fewer workgroups: lengthen them only while the grid still has
@@ -233,15 +269,15 @@ ac_status make_plan3d(int nx, int ny, int nz, int64_t nsteps, size_t elem, const
         while (LZ < 128 && xy * ((nz + 2 * LZ - 1) / (2 * LZ)) >= 32LL * dev.cus) LZ *= 2;
     }
     ac::Tile3D t{LX, LY, LZ, K, threads};
-    if (ac::stream3d_cells_per_thread(t) > 4)
+    if (!reg && ac::stream3d_cells_per_thread(t) > 4)
         return fail(AC_ERR_UNSUPPORTED, "tile %dx%d has more than 4 cells per thread", LX, LY);
-    const size_t lds = ac::stream3d_lds_bytes(t, elem);
+    const size_t lds = reg ? ac::reg3d_lds_bytes(K, LY, elem) : ac::stream3d_lds_bytes(t, elem);
     if (lds > dev.lds_per_block)
         return fail(AC_ERR_UNSUPPORTED, "3D tile needs %zu B LDS > %zu", lds, dev.lds_per_block);
     const int64_t gz = (nz + LZ - 1) / LZ;
     if (gz > 65535) return fail(AC_ERR_UNSUPPORTED, "%lld z segments exceed 65535", (long long)gz);
     const Chunks c = plan_chunks(nsteps, K);
-    p->kernel = AC_KERNEL_3D_STREAM;
+    p->kernel = reg ? AC_KERNEL_3D_REG : AC_KERNEL_3D_STREAM;
     p->tb_depth = K;
     p->tile_x = LX;
     p->tile_y = LY;
@@ -298,7 +334,9 @@ ac_status run3d(T *phi, T *work, int nx, int ny, int nz, double alpha_d, double 
     hipError_t e;
     for (int64_t i = 0; i < c.n; ++i) {
         t.K = (int)(c.base + (i < c.rem ? 1 : 0));
-        e = ac::launch_stream3d<T>(src, dst, nx, ny, nz, alpha, r, t, stream);
+        e = p.kernel == AC_KERNEL_3D_REG
+                ? ac::launch_reg3d<T>(src, dst, nx, ny, nz, alpha, r, t, stream)
+                : ac::launch_stream3d<T>(src, dst, nx, ny, nz, alpha, r, t, stream);
         if (e != hipSuccess) return hip_fail(e, "3D launch");
         T *tmp = src; src = dst; dst = tmp;
     }

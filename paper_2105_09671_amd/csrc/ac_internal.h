@@ -88,6 +88,16 @@ hipError_t launch_stream3d(const T *src, T *dst, int nx, int ny, int nz, T alpha
                            const Tile3D &t, hipStream_t stream);
 size_t stream3d_lds_bytes(const Tile3D &t, size_t elem);
 int stream3d_cells_per_thread(const Tile3D &t);
+// register-resident 3D variant: LX = 64, kReg3dRows rows per wave, at most
+// kReg3dMaxWaves waves, depth 1..4; LDS row exchange [2][K][2 rows][waves][64]
+constexpr int kReg3dRows = 4, kReg3dMaxWaves = 8, kReg3dMaxDepth = 4;
+inline size_t reg3d_lds_bytes(int K, int LY, size_t elem) {
+    return (size_t)4 * K * (LY / kReg3dRows) * 64 * elem;
+}
+template <typename T>
+hipError_t launch_reg3d(const T *src, T *dst, int nx, int ny, int nz, T alpha, T r,
+                        const Tile3D &t, hipStream_t stream);
+int reg3d_blocks_per_cu(int K, int LY, size_t elem);   // 0 if the query fails
 
 // Raise a kernel's dynamic-LDS limit when it asks for more than 64 KiB; a
 // runtime that rejects the attribute leaves the launch to report any problem.

@@ -666,8 +666,13 @@ ac_status build_plan3d(Plan &p, const ac_instance3d *inst, int32_t n, int64_t ns
                        int32_t dtype, const ac_tune &tune, const std::vector<double> &alpha,
                        const std::vector<double> &r, const DevInfo &dev) {
     const size_t elem = elem_size(dtype);
+    // the batched 3D kernels use the LDS tile body
+    ac_tune tl = tune;
+    if (tl.kernel == 0) tl.kernel = AC_KERNEL_3D_STREAM;
+    if (tl.kernel != AC_KERNEL_3D_STREAM)
+        return fail(AC_ERR_UNSUPPORTED, "batched 3D runs the LDS z-streaming kernel only");
     ac_plan tp;
-    ac_status s = make_plan3d(256, 256, 256, nsteps, elem, &tune, dev, &tp);
+    ac_status s = make_plan3d(256, 256, 256, nsteps, elem, &tl, dev, &tp);
     if (s != AC_OK) return s;
     const int LX = tp.tile_x, LY = tp.tile_y, LZ = tp.tile_z, K = tp.tb_depth, threads = tp.threads;
     if (K > 4) return fail(AC_ERR_UNSUPPORTED, "batched 3D supports tb_depth 1..4, got %d", K);

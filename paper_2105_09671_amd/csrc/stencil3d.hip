@@ -21,6 +21,7 @@
 //
 // LDS holds two sets (even/odd iteration) of K planes of LX*LY values so one
 // barrier per iteration separates producers from consumers.
+#include "reg3d.h"
 #include "stream3d.h"
 
 namespace ac {
@@ -84,6 +85,67 @@ hipError_t launch_stream3d(const T *src, T *dst, int nx, int ny, int nz, T alpha
     default: return hipErrorInvalidValue;
     }
 }
+
+// Register-resident variant (reg3d.h): 64-wide tiles, kReg3dRows rows per wave.
+template <typename T, int K>
+__global__ void __launch_bounds__(512)
+reg3d_kernel(const T *__restrict__ src, T *__restrict__ dst, int nx, int ny, int nz, T alpha, T r,
+             int LZ, int tiles_x)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    reg3d_body<T, K, kReg3dRows>(src, dst, nx, ny, nz, alpha, r, LZ, tiles_x, blockIdx.x,
+                                 blockIdx.y, reinterpret_cast<T *>(smem_raw));
+}
+
+template <typename T, int K>
+static const void *reg3d_ptr() { return (const void *)reg3d_kernel<T, K>; }
+
+template <typename T>
+static const void *reg3d_kernel_of(int K) {
+    switch (K) {
+    case 1: return reg3d_ptr<T, 1>();
+    case 2: return reg3d_ptr<T, 2>();
+    case 3: return reg3d_ptr<T, 3>();
+    case 4: return reg3d_ptr<T, 4>();
+    default: return nullptr;
+    }
+}
+
+int reg3d_blocks_per_cu(int K, int LY, size_t elem) {
+    const void *k = elem == 8 ? reg3d_kernel_of<double>(K) : reg3d_kernel_of<float>(K);
+    if (!k) return 0;
+    const size_t lds = reg3d_lds_bytes(K, LY, elem);
+    set_lds_limit(k, lds);
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, 64 * (LY / kReg3dRows), lds) !=
+        hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return n;
+}
+
+template <typename T>
+hipError_t launch_reg3d(const T *src, T *dst, int nx, int ny, int nz, T alpha, T r,
+                        const Tile3D &t, hipStream_t stream)
+{
+    const void *k = reg3d_kernel_of<T>(t.K);
+    if (!k || t.LX != 64 || t.LY % kReg3dRows || t.LY / kReg3dRows > kReg3dMaxWaves)
+        return hipErrorInvalidValue;
+    const int OX = 64 - 2 * t.K, OY = t.LY - 2 * t.K;
+    const int tiles_x = (nx + OX - 1) / OX, tiles_y = (ny + OY - 1) / OY;
+    dim3 grid(tiles_x * tiles_y, (nz + t.LZ - 1) / t.LZ);
+    const size_t lds = reg3d_lds_bytes(t.K, t.LY, sizeof(T));
+    set_lds_limit(k, lds);
+    void *args[] = {(void *)&src, (void *)&dst, (void *)&nx,  (void *)&ny,   (void *)&nz,
+                    (void *)&alpha, (void *)&r, (void *)&t.LZ, (void *)&tiles_x};
+    return hipLaunchKernel(k, grid, dim3(64 * (t.LY / kReg3dRows)), args, lds, stream);
+}
+
+template hipError_t launch_reg3d<float>(const float *, float *, int, int, int, float, float,
+                                        const Tile3D &, hipStream_t);
+template hipError_t launch_reg3d<double>(const double *, double *, int, int, int, double, double,
+                                         const Tile3D &, hipStream_t);
 
 template hipError_t launch_stream3d<float>(const float *, float *, int, int, int, float, float,
                                            const Tile3D &, hipStream_t);

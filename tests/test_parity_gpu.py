@@ -173,6 +173,39 @@ def test_3d_all_depths(api, dtype):
     assert np.array_equal(default, outs[1])
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_3d_register_kernel(api, dtype):
+    """The register-resident 3D kernel (64-wide tiles, 4 rows per wave) at depths
+    1..4 and 1..8 waves, on a grid ragged against every tile and z segment:
+    bitwise the LDS kernel, and the oracle to the usual bar."""
+    h, dt, eps = _par(64, 4)
+    phi0 = inputs.random_field((37, 45, 70), seed=34).astype(NP[dtype])
+    ref = oracle.step3d(phi0.astype(np.float64), h, dt, eps, 13)
+    base = _run3d(api, phi0, h, dt, eps, 13, dtype,
+                  tune=dict(tb_depth=2, tile_x=24, tile_y=24, tile_z=8, kernel=2))
+    assert D.rel_linf(base, ref) <= TOL[dtype]
+    for k, ly, lz in [(1, 4, 5), (2, 16, 8), (3, 8, 16), (4, 32, 8), (4, 12, 64), (3, 32, 37)]:
+        tune = dict(tb_depth=k, tile_x=64, tile_y=ly, tile_z=lz, kernel=5)
+        p = api.plan3d(70, 45, 37, 13, dtype, tune)
+        assert p["kernel"] == 5 and p["threads"] == 64 * ly // 4, p
+        got = _run3d(api, phi0, h, dt, eps, 13, dtype, tune=tune)
+        assert np.array_equal(got, base), (k, ly, lz)
+
+
+def test_3d_plan_kernels(api):
+    from paper_2105_09671_amd import _lib as L
+    # large grids run on register tiles, grids of too few 64-wide tiles on LDS
+    for dt_ in (torch.float32, torch.float64):
+        assert api.plan3d(1024, 1024, 1024, 100, dt_)["kernel"] == 5
+        assert api.plan3d(96, 96, 96, 100, dt_)["kernel"] == 2
+        assert api.plan3d(96, 96, 96, 100, dt_, dict(kernel=5))["kernel"] == 5
+        assert api.plan3d(1024, 1024, 1024, 100, dt_, dict(kernel=2))["kernel"] == 2
+    for bad in (dict(kernel=5, tb_depth=5), dict(kernel=5, tile_x=32), dict(kernel=5, tile_y=36),
+                dict(kernel=5, tile_y=30), dict(kernel=4)):
+        with pytest.raises(L.AcError):
+            api.plan3d(256, 256, 256, 100, torch.float32, bad)
+
+
 @pytest.mark.parametrize("shape", [(1, 1, 1), (1, 1, 9), (9, 1, 1), (1, 7, 1), (2, 3, 4),
                                    (5, 70, 3), (40, 2, 66)])
 @pytest.mark.parametrize("nsteps", [1, 4])
@@ -180,7 +213,8 @@ def test_3d_edge_shapes(api, shape, nsteps):
     h, dt, eps = _par(32, 4)
     phi0 = inputs.random_field(shape, seed=32, amp=0.8)
     ref = oracle.step3d(phi0, h, dt, eps, nsteps)
-    for tune in (None, dict(tb_depth=2, tile_x=12, tile_y=12, tile_z=2)):
+    for tune in (None, dict(tb_depth=2, tile_x=12, tile_y=12, tile_z=2),
+                 dict(tb_depth=3, tile_x=64, tile_y=8, tile_z=2, kernel=5)):
         got = _run3d(api, phi0, h, dt, eps, nsteps, torch.float64, tune)
         assert D.rel_linf(got, ref) <= 1e-12, tune
 
@@ -189,8 +223,10 @@ def test_3d_edge_shapes(api, shape, nsteps):
 def test_3d_invariants(api, dtype):
     h, dt, eps = _par(48, 3)
     tune = dict(tb_depth=3, tile_x=24, tile_y=20, tile_z=16)
+    reg = dict(tb_depth=3, tile_x=64, tile_y=16, tile_z=16, kernel=5)
     for v in (1.0, -1.0, 0.0):
         c = np.full((20, 30, 40), v, dtype=NP[dtype])
+        assert np.array_equal(_run3d(api, c, h, dt, eps, 9, dtype, reg), c)
         assert np.array_equal(_run3d(api, c, h, dt, eps, 9, dtype, tune), c)
     phi0 = inputs.random_field((20, 30, 40), seed=33, amp=1.0).astype(NP[dtype])
     out = _run3d(api, phi0, h, dt, eps, 12, dtype, tune)
@@ -201,6 +237,7 @@ def test_3d_invariants(api, dtype):
         f[ax] = slice(None, None, -1)
         f = tuple(f)
         assert np.array_equal(_run3d(api, phi0[f], h, dt, eps, 12, dtype, tune), out[f])
+    assert np.array_equal(_run3d(api, phi0, h, dt, eps, 12, dtype, reg), out)
 
 
 def test_api_rejects_cpu_tensor(api):
