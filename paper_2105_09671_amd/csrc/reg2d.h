@@ -11,7 +11,10 @@
 //     buffered by step parity, so one barrier per step suffices).
 // The tile is loaded once from HBM and its exact interior stored once per
 // launch, as in the LDS-tiled kernels; after s fused steps the cells within s
-// of a non-domain tile edge are no longer exact, hence the halo >= steps.
+// of a non-domain tile edge are no longer exact, hence the halo >= steps.  The
+// interior is written with non-temporal stores: nothing in the launch reads it
+// again, and streaming it out shortens the cache write-back at the kernel
+// boundary.
 //
 // Zero-Neumann boundary (section 2): where a neighbour lies outside the domain
 // the cell itself is used.  The selects exist only in the edge variants: EX
@@ -119,7 +122,7 @@ __device__ __forceinline__ void reg2d_body(const T *__restrict__ src, T *__restr
 #pragma unroll
         for (int q = 0; q < RCH; ++q) {
             const int y = y0 + q;
-            if (y >= oy0 && y < oy1) dst[(size_t)y * nx + x] = v[q];
+            if (y >= oy0 && y < oy1) __builtin_nontemporal_store(v[q], dst + (size_t)y * nx + x);
         }
     }
 }
