@@ -11,6 +11,7 @@
 #include <string>
 
 #include "ac_internal.h"
+#include "reg2d.h"
 
 namespace ac {
 
@@ -125,7 +126,9 @@ void choose_tile2d(int nx, int ny, size_t elem, bool reg, const ac::DevInfo &dev
     for (int i = 0; i < n; ++i) {
         const int k = tab[i].K, ly = tab[i].LY;
         const int OX = 64 - 2 * k, OY = ly - 2 * k;
-        const int64_t tiles = (int64_t)((nx + OX - 1) / OX) * ((ny + OY - 1) / OY);
+        // register tiles sit flush against the domain edges (reg2d.h)
+        const int64_t tiles = reg ? (int64_t)ac::reg2d_tiles_1d(nx, 64, k) * ac::reg2d_tiles_1d(ny, ly, k)
+                                  : (int64_t)((nx + OX - 1) / OX) * ((ny + OY - 1) / OY);
         if ((ny + OY - 1) / OY > 65535) continue;
         const int per_cu = reg ? ac::tile2d_reg_blocks_per_cu(ly, elem)
                                : ac::tile2d_inplace_blocks_per_cu(ly, elem);

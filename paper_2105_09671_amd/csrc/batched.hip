@@ -120,11 +120,23 @@ __device__ __forceinline__ bool phase_sync(unsigned *done, unsigned mine, unsign
     return s_ok != 0;
 }
 
-// Copy the output region of one tile from src to dst (final odd-count fix-up).
-template <typename T>
-__device__ void copy_tile(const T *src, T *dst, int nx, int ny, int OX, int OY, int tx, int ty) {
-    const int x0 = tx * OX, y0 = ty * OY;
-    const int x1 = min(x0 + OX, nx), y1 = min(y0 + OY, ny);
+// Copy the output region of one tile from src to dst (final odd-count fix-up):
+// the region of the register tiling (reg2d.h) when REG, else the uniform
+// tiling of the LDS bodies.
+template <typename T, bool REG>
+__device__ void copy_tile(const T *src, T *dst, int nx, int ny, int LX, int LY, int K, int tx,
+                          int ty) {
+    int x0, x1, y0, y1;
+    if constexpr (REG) {
+        int ld;
+        reg2d_tile_span(tx, reg2d_tiles_1d(nx, LX, K), nx, LX, K, &ld, &x0, &x1);
+        reg2d_tile_span(ty, reg2d_tiles_1d(ny, LY, K), ny, LY, K, &ld, &y0, &y1);
+    } else {
+        x0 = tx * (LX - 2 * K);
+        y0 = ty * (LY - 2 * K);
+        x1 = min(x0 + LX - 2 * K, nx);
+        y1 = min(y0 + LY - 2 * K, ny);
+    }
     const int w = x1 - x0;
     for (int i = threadIdx.x; i < w * (y1 - y0); i += blockDim.x) {
         const int y = y0 + i / w, x = x0 + i % w;
@@ -184,8 +196,9 @@ batched_kernel(const BatchInst *__restrict__ inst, const int4 *__restrict__ item
                 T *dst = static_cast<T *>((b & 1) ? I.phi : I.work);
                 tile_item<T, LXC, BODY>(src, dst, I, LX, LY, K, k, it.y, it.z, smem_raw);
             } else {   // odd number of single-step phases: the result sits in work
-                copy_tile<T>(static_cast<const T *>(I.work), static_cast<T *>(I.phi), I.nx, I.ny,
-                             LX - 2 * K, LY - 2 * K, it.y, it.z);
+                copy_tile<T, BODY == BODY_REG>(static_cast<const T *>(I.work),
+                                               static_cast<T *>(I.phi), I.nx, I.ny, LX, LY, K,
+                                               it.y, it.z);
             }
             if (threadIdx.x == 0) s_ticket = next;
             __syncthreads();                      // LDS is reused by the next item
@@ -223,8 +236,8 @@ batched_phase_kernel(const BatchInst *__restrict__ inst, const int4 *__restrict_
         T *dst = static_cast<T *>((phase & 1) ? I.phi : I.work);
         tile_item<T, LXC, BODY>(src, dst, I, LX, LY, K, k, it.y, it.z, smem_raw);
     } else {
-        copy_tile<T>(static_cast<const T *>(I.work), static_cast<T *>(I.phi), I.nx, I.ny,
-                     LX - 2 * K, LY - 2 * K, it.y, it.z);
+        copy_tile<T, BODY == BODY_REG>(static_cast<const T *>(I.work), static_cast<T *>(I.phi),
+                                       I.nx, I.ny, LX, LY, K, it.y, it.z);
     }
 }
 
@@ -472,7 +485,10 @@ ac_status build_plan(Plan &p, const ac_instance2d *inst, int32_t n, int64_t nste
     std::vector<int4> items;
     for (int32_t i = 0; i < n; ++i) {
         hi[i] = BatchInst{inst[i].phi, inst[i].work, inst[i].nx, inst[i].ny, alpha[i], r[i]};
-        const int tx = (inst[i].nx + OX - 1) / OX, ty = (inst[i].ny + OY - 1) / OY;
+        // register tiles sit flush against the domain edges (reg2d.h)
+        const bool reg = tp.kernel == AC_KERNEL_2D_REG;
+        const int tx = reg ? reg2d_tiles_1d(inst[i].nx, LX, K) : (inst[i].nx + OX - 1) / OX;
+        const int ty = reg ? reg2d_tiles_1d(inst[i].ny, LY, K) : (inst[i].ny + OY - 1) / OY;
         for (int y = 0; y < ty; ++y)
             for (int x = 0; x < tx; ++x) items.push_back(int4{i, x, y, 0});
     }

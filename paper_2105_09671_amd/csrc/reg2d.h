@@ -16,12 +16,24 @@
 // again, and streaming it out shortens the cache write-back at the kernel
 // boundary.
 //
-// Zero-Neumann boundary (section 2): where a neighbour lies outside the domain
-// the cell itself is used.  The selects exist only in the edge variants: EX
-// for tiles that reach x = 0 or x = nx-1 (block-uniform), EY for waves whose
-// rows reach y = 0 or y = ny-1 (wave-uniform).  Cells outside the domain are
-// loaded from the clamped address, so every load stays in bounds and every
-// value stays finite; no exact cell ever reads them.
+// Tiling (reg2d_tile_span): along each axis the first tile starts at the
+// domain's first cell and, when the domain is longer than a tile, the last
+// one ends at its last cell; the tiles between step by L - 2 halo.  So a
+// domain edge always falls on a tile edge, and the zero-Neumann boundary
+// (section 2: a neighbour outside the domain is the cell itself) costs almost
+// nothing:
+//   * y: the first row of a tile's first wave, or the last row of its last
+//     wave, takes the row itself as its outer neighbour, which is the
+//     Neumann value at y = 0 and y = ny-1;
+//   * x: at x = 0 (lane 0 of a first tile) and x = nx-1 (lane 63 of a last
+//     tile) the DPP shift keeps the lane's own value instead of a neighbour's,
+//     one move that cannot fold into the add (10 VALU instructions per cell
+//     there against 9).
+// Only a domain smaller than one tile (nx < 64, or ny shorter than the tile)
+// has cells beyond its edge inside the tile; there the edge variant replaces
+// the neighbour by a select.  Cells outside the domain are loaded from the
+// clamped address, so every load stays in bounds and every value stays
+// finite; no exact cell ever reads them.
 //
 // Every cell is updated by update2d from the same neighbour values as in the
 // LDS kernels, so the result is bitwise that of any other 2D plan.
@@ -49,30 +61,76 @@ __device__ __forceinline__ double wave_shift(double v) {
     return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
 }
 
+// The same shift, but the lane with no source lane (lane 0 for a right shift,
+// lane 63 for a left one) keeps its own value: the Neumann neighbour of a
+// domain edge that sits on the wave's first or last lane.
+template <int CTRL>
+__device__ __forceinline__ float wave_shift_keep(float v) {
+    const int i = __builtin_bit_cast(int, v);
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(i, i, CTRL, 0xf, 0xf, false));
+}
+
+template <int CTRL>
+__device__ __forceinline__ double wave_shift_keep(double v) {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const int l = (int)(unsigned)u, h = (int)(unsigned)(u >> 32);
+    const int lo = __builtin_amdgcn_update_dpp(l, l, CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(h, h, CTRL, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+// Placement of tile i of nt along an axis of n cells, tiles of L cells with a
+// `halo`-wide ring: loaded cells [*ld, *ld + L), exact output [*o0, *o1).
+__host__ __device__ inline int reg2d_tiles_1d(int n, int L, int halo) {
+    return n <= L ? 1 : 1 + (n - L + (L - 2 * halo) - 1) / (L - 2 * halo);
+}
+
+__host__ __device__ inline void reg2d_tile_span(int i, int nt, int n, int L, int halo, int *ld,
+                                                int *o0, int *o1) {
+    const int O = L - 2 * halo;
+    *ld = i == 0 ? 0 : (i == nt - 1 ? n - L : i * O);
+    *o0 = i == 0 ? 0 : i * O + halo;
+    *o1 = i == nt - 1 ? n : i * O + halo + O;
+}
+
+// x-edge handling of a tile: none, its lane 0 is x = 0, its lane 63 is
+// x = nx-1, or the domain is narrower than the tile (selects).
+enum { REG_X_IN = 0, REG_X_LEFT = 1, REG_X_RIGHT = 2, REG_X_SEL = 3 };
+
 // One step of a wave's RCH rows, in place.  hu / hd: the rows just above and
 // below the wave's rows (old values).  x: this lane's column; y0: the wave's
-// first row.
-template <typename T, int RCH, bool EX, bool EY>
+// first row.  EY: the domain ends inside the wave's rows at y = ny-1.
+template <typename T, int RCH, int EX, bool EY>
 __device__ __forceinline__ void reg2d_substep(T v[RCH], T hu, T hd, int x, int nx, int y0, int ny,
                                               T alpha, T r)
 {
-    const bool atL = EX && x == 0, atR = EX && x == nx - 1;
+    const bool atL = EX == REG_X_SEL && x == 0, atR = EX == REG_X_SEL && x == nx - 1;
     T prev = hu;
 #pragma unroll
     for (int q = 0; q < RCH; ++q) {
         const T c = v[q];
         T up = prev, dn = q + 1 < RCH ? v[q + 1] : hd;
-        T l = wave_shift<kDppWaveShr1>(c), rr = wave_shift<kDppWaveShl1>(c);
-        if (EX) {
+        T l = EX == REG_X_LEFT ? wave_shift_keep<kDppWaveShr1>(c) : wave_shift<kDppWaveShr1>(c);
+        T rr = EX == REG_X_RIGHT ? wave_shift_keep<kDppWaveShl1>(c) : wave_shift<kDppWaveShl1>(c);
+        if (EX == REG_X_SEL) {
             l = atL ? c : l;
             rr = atR ? c : rr;
         }
-        if (EY) {
-            up = y0 + q == 0 ? c : up;
-            dn = y0 + q == ny - 1 ? c : dn;
-        }
+        if (EY) dn = y0 + q == ny - 1 ? c : dn;
         prev = c;
         v[q] = update2d<T>(c, l, rr, up, dn, alpha, r);
+    }
+}
+
+template <typename T, int RCH, bool EY>
+__device__ __forceinline__ void reg2d_substep_x(int ex, T v[RCH], T hu, T hd, int x, int nx, int y0,
+                                                int ny, T alpha, T r)
+{
+    switch (ex) {
+    case REG_X_IN: reg2d_substep<T, RCH, REG_X_IN, EY>(v, hu, hd, x, nx, y0, ny, alpha, r); break;
+    case REG_X_LEFT: reg2d_substep<T, RCH, REG_X_LEFT, EY>(v, hu, hd, x, nx, y0, ny, alpha, r); break;
+    case REG_X_RIGHT: reg2d_substep<T, RCH, REG_X_RIGHT, EY>(v, hu, hd, x, nx, y0, ny, alpha, r); break;
+    default: reg2d_substep<T, RCH, REG_X_SEL, EY>(v, hu, hd, x, nx, y0, ny, alpha, r); break;
     }
 }
 
@@ -88,20 +146,29 @@ __device__ __forceinline__ void reg2d_body(const T *__restrict__ src, T *__restr
     const int tx = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int NW = blockDim.x >> 6;
-    const int OX = 64 - 2 * halo, OY = NW * RCH - 2 * halo;
-    const int ox0 = tile_x * OX, oy0 = tile_y * OY;
-    const int lx0 = ox0 - halo;
+    const int LY = NW * RCH;
+    const int ntx = reg2d_tiles_1d(nx, 64, halo), nty = reg2d_tiles_1d(ny, LY, halo);
+    int lx0, ox0, ox1, ly0, oy0, oy1;
+    reg2d_tile_span(tile_x, ntx, nx, 64, halo, &lx0, &ox0, &ox1);
+    reg2d_tile_span(tile_y, nty, ny, LY, halo, &ly0, &oy0, &oy1);
     const int x = lx0 + tx;
-    const int y0 = oy0 - halo + w * RCH;
-    const int xc = min(max(x, 0), nx - 1);
+    const int y0 = ly0 + w * RCH;
+    const int xc = min(x, nx - 1);
     T v[RCH];
 #pragma unroll
     for (int q = 0; q < RCH; ++q) {
-        const int yc = min(max(y0 + q, 0), ny - 1);
+        const int yc = min(y0 + q, ny - 1);
         v[q] = src[(size_t)yc * nx + xc];
     }
-    const bool edgeX = lx0 <= 0 || lx0 + 63 >= nx - 1;
-    const bool edgeY = y0 <= 0 || y0 + RCH - 1 >= ny - 1;
+    // x edges: a domain narrower than the tile needs selects; otherwise the
+    // first tile's lane 0 is x = 0 and the last tile's lane 63 is x = nx-1
+    // (both for nx = 64 exactly, which takes the select path too)
+    const int ex = nx < 64 || (ntx == 1) ? REG_X_SEL
+                   : tile_x == 0         ? REG_X_LEFT
+                   : tile_x == ntx - 1   ? REG_X_RIGHT
+                                         : REG_X_IN;
+    // y: a domain shorter than the tile ends inside the wave holding ny-1
+    const bool edgeY = ny < LY && y0 <= ny - 1 && y0 + RCH - 1 >= ny - 1;
     for (int s = 0; s < ksteps; ++s) {
         T *b = xb + (s & 1) * 2 * NW * 64;
         b[w * 64 + tx] = v[0];
@@ -109,15 +176,9 @@ __device__ __forceinline__ void reg2d_body(const T *__restrict__ src, T *__restr
         __syncthreads();
         const T hu = w > 0 ? b[(NW + w - 1) * 64 + tx] : v[0];
         const T hd = w + 1 < NW ? b[(w + 1) * 64 + tx] : v[RCH - 1];
-        if (edgeX) {
-            if (edgeY) reg2d_substep<T, RCH, true, true>(v, hu, hd, x, nx, y0, ny, alpha, r);
-            else       reg2d_substep<T, RCH, true, false>(v, hu, hd, x, nx, y0, ny, alpha, r);
-        } else {
-            if (edgeY) reg2d_substep<T, RCH, false, true>(v, hu, hd, x, nx, y0, ny, alpha, r);
-            else       reg2d_substep<T, RCH, false, false>(v, hu, hd, x, nx, y0, ny, alpha, r);
-        }
+        if (edgeY) reg2d_substep_x<T, RCH, true>(ex, v, hu, hd, x, nx, y0, ny, alpha, r);
+        else       reg2d_substep_x<T, RCH, false>(ex, v, hu, hd, x, nx, y0, ny, alpha, r);
     }
-    const int ox1 = min(ox0 + OX, nx), oy1 = min(oy0 + OY, ny);
     if (x >= ox0 && x < ox1) {
 #pragma unroll
         for (int q = 0; q < RCH; ++q) {

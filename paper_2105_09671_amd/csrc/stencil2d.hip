@@ -128,8 +128,8 @@ hipError_t launch_tile2d_reg(const T *src, T *dst, int nx, int ny, T alpha, T r,
                              int ksteps, hipStream_t stream)
 {
     const int nw = t.LY / kRegRows;
-    const int OX = 64 - 2 * t.halo, OY = t.LY - 2 * t.halo;
-    const int64_t tx = (nx + OX - 1) / OX, tiles = tx * ((ny + OY - 1) / OY);
+    const int64_t tx = reg2d_tiles_1d(nx, 64, t.halo),
+                  tiles = tx * reg2d_tiles_1d(ny, t.LY, t.halo);
     if (tiles > INT_MAX - 8) return hipErrorInvalidValue;
     dim3 grid((unsigned)((tiles + 7) / 8 * 8));
     hipLaunchKernelGGL(tile2d_reg_kernel<T>, grid, dim3(64 * nw), tile2d_reg_lds_bytes(t.LY, sizeof(T)),
