@@ -99,6 +99,26 @@ def test_2d_edge_shapes(api, shape, nsteps):
         assert D.rel_linf(got, ref) <= 1e-12, tune
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_2d_register_tiling_sizes(api, dtype):
+    """Register tiles sit flush against the domain edges: the first tile starts
+    at 0, the last ends at n, the ones between step by L - 2K.  Sizes around
+    every change of the tile count (depth 7, 64 x 32 tiles: 50 x 18 outputs),
+    with 19 steps so the last launch is shorter: bitwise the two-buffer LDS
+    kernel (uniform tiling) and the oracle."""
+    h, dt, eps = _par(64, 4)
+    for ny, nx in [(32, 64), (33, 65), (31, 63), (50, 114), (51, 115), (64, 128), (46, 164),
+                   (47, 165), (32, 200), (200, 64), (18, 70), (100, 1)]:
+        phi0 = inputs.random_field((ny, nx), seed=35 + nx + ny, amp=0.9).astype(NP[dtype])
+        ref = oracle.step2d(phi0.astype(np.float64), h, dt, eps, 19)
+        reg = _run2d(api, phi0, h, dt, eps, 19, dtype,
+                     tune=dict(tb_depth=7, tile_x=64, tile_y=32, kernel=4))
+        lds = _run2d(api, phi0, h, dt, eps, 19, dtype,
+                     tune=dict(tb_depth=7, tile_x=64, tile_y=32, kernel=1))
+        assert np.array_equal(reg, lds), (ny, nx)
+        assert D.rel_linf(reg, ref) <= TOL[dtype], (ny, nx)
+
+
 def test_2d_plan_kernels(api):
     from paper_2105_09671_amd import _lib as L
     # large grids default to the register kernel
