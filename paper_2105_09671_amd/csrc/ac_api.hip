@@ -85,18 +85,19 @@ Chunks plan_chunks(int64_t nsteps, int64_t k) {
 // decision, so ac_plan_* reports exactly what ac_step_* will launch.
 // Steady-state throughput of the tiled 2D kernels on MI355X (GLUPS on a
 // 16384^2 grid in FP32, 16384 x 8192 in FP64, where every CU runs many tiles
-// back to back), by depth and tile height.
+// back to back), by depth and tile height.  Register tiles of 6 or 10 waves
+// (heights 96, 160) measured 10-25 % slower than 4, 8 or 12 and are left out.
 struct TileRate { int K, LY; double glups; };
-static const TileRate kRegF32[] = {{4, 64, 1923}, {4, 128, 2056}, {4, 192, 2019},
-                                   {5, 64, 2287}, {5, 128, 2255}, {5, 192, 1936},
-                                   {6, 64, 2359}, {6, 128, 2564}, {6, 192, 2538},
-                                   {7, 64, 2448}, {7, 128, 2637}, {7, 192, 2531},
-                                   {8, 64, 2405}, {8, 128, 2718}, {8, 192, 2537}};
-static const TileRate kRegF64[] = {{4, 64, 1273}, {4, 128, 1269}, {4, 192, 1256},
-                                   {5, 64, 1343}, {5, 128, 1254}, {5, 192, 1219},
-                                   {6, 64, 1371}, {6, 128, 1485}, {6, 192, 1482},
-                                   {7, 64, 1364}, {7, 128, 1540}, {7, 192, 1503},
-                                   {8, 64, 1352}, {8, 128, 1550}, {8, 192, 1559}};
+static const TileRate kRegF32[] = {{4, 64, 1564}, {4, 128, 1495}, {4, 192, 1536},
+                                   {5, 64, 2053}, {5, 128, 1916}, {5, 192, 2125},
+                                   {6, 64, 2345}, {6, 128, 2507}, {6, 192, 2565},
+                                   {7, 64, 2478}, {7, 128, 2608}, {7, 192, 2605},
+                                   {8, 64, 2461}, {8, 128, 2587}, {8, 192, 2553}};
+static const TileRate kRegF64[] = {{4, 64, 983}, {4, 128, 932}, {4, 192, 945},
+                                   {5, 64, 1208}, {5, 128, 1185}, {5, 192, 1224},
+                                   {6, 64, 1392}, {6, 128, 1358}, {6, 192, 1398},
+                                   {7, 64, 1389}, {7, 128, 1494}, {7, 192, 1518},
+                                   {8, 64, 1409}, {8, 128, 1555}, {8, 192, 1569}};
 static const TileRate kInplaceF32[] = {{6, 64, 1603}, {7, 64, 1617}, {8, 64, 1645},
                                        {6, 128, 1682}, {7, 128, 1707}, {8, 128, 1732}};
 static const TileRate kInplaceF64[] = {{3, 32, 666}, {4, 32, 749}, {5, 32, 758}, {6, 32, 730},
@@ -108,11 +109,13 @@ static const TileRate kInplaceF64[] = {{3, 32, 666}, {4, 32, 749}, {5, 32, 758},
 // faster on the register kernel, and 1024^3 FP32 27 %)
 static const int64_t kReg3dMinRoundsNum = 3, kReg3dMinRoundsDen = 4;
 
-// Predicted time of a launch ~ (rounds of resident tiles) x (time of one full
-// round), a full round taking S tiles of OX*OY*K updates at the steady rate
-// (S = resident tiles on the device).  A grid whose tile count just exceeds a
-// multiple of S pays a whole extra round, so the depth and tile height are
-// chosen per grid.
+// Predicted time of a launch ~ the tiles of the busiest CU (ceil(tiles / CUs);
+// the dispatcher spreads workgroups evenly) x the time of one tile at the
+// steady per-CU rate measured for that pair.  A grid whose tile count just
+// exceeds a multiple of the CU count gives some CUs one tile more, so the
+// depth and tile height are chosen per grid.  (Charging a partial round as a
+// full round of resident slots, as an earlier model did, preferred tall tiles
+// on 2048^2 that measure 5 % slower.)
 void choose_tile2d(int nx, int ny, size_t elem, bool reg, const ac::DevInfo &dev, int *K, int *LY) {
     const bool f64 = elem == 8;
     const TileRate *tab = reg ? (f64 ? kRegF64 : kRegF32) : (f64 ? kInplaceF64 : kInplaceF32);
@@ -120,6 +123,7 @@ void choose_tile2d(int nx, int ny, size_t elem, bool reg, const ac::DevInfo &dev
                              : (int)(sizeof kRegF32 / sizeof *kRegF32))
                       : (f64 ? (int)(sizeof kInplaceF64 / sizeof *kInplaceF64)
                              : (int)(sizeof kInplaceF32 / sizeof *kInplaceF32));
+    const int64_t cus = std::max(dev.cus, 1);
     double best = -1.0;
     *K = tab[0].K;
     *LY = tab[0].LY;
@@ -130,12 +134,9 @@ void choose_tile2d(int nx, int ny, size_t elem, bool reg, const ac::DevInfo &dev
         const int64_t tiles = reg ? (int64_t)ac::reg2d_tiles_1d(nx, 64, k) * ac::reg2d_tiles_1d(ny, ly, k)
                                   : (int64_t)((nx + OX - 1) / OX) * ((ny + OY - 1) / OY);
         if ((ny + OY - 1) / OY > 65535) continue;
-        const int per_cu = reg ? ac::tile2d_reg_blocks_per_cu(ly, elem)
-                               : ac::tile2d_inplace_blocks_per_cu(ly, elem);
-        const int64_t slots = (int64_t)std::max(per_cu, 1) * std::max(dev.cus, 1);
-        const int64_t rounds = (tiles + slots - 1) / slots;
-        const double round_time = (double)slots * OX * OY * k / tab[i].glups;
-        const double rate = (double)nx * ny * k / (rounds * round_time);
+        const int64_t busiest = (tiles + cus - 1) / cus;
+        const double t = (double)busiest * OX * OY * k / (tab[i].glups / (double)cus);
+        const double rate = (double)nx * ny * k / t;
         if (rate > best) {
             best = rate;
             *K = k;

@@ -65,7 +65,6 @@ hipError_t launch_tile2d_inplace(const T *src, T *dst, int nx, int ny, T alpha, 
                                  const Tile2D &t, int ksteps, hipStream_t stream);
 size_t tile2d_inplace_lds_bytes(int LY, size_t elem);
 int tile2d_inplace_threads(int LY, size_t elem);
-int tile2d_inplace_blocks_per_cu(int LY, size_t elem);   // 0 if the query fails
 
 // register-resident variant (LX = 64, kRegRows rows per wave held in VGPRs,
 // LY / kRegRows waves of at most 16)
@@ -73,7 +72,6 @@ constexpr int kRegRows = 16;
 template <typename T>
 hipError_t launch_tile2d_reg(const T *src, T *dst, int nx, int ny, T alpha, T r, const Tile2D &t,
                              int ksteps, hipStream_t stream);
-int tile2d_reg_blocks_per_cu(int LY, size_t elem);       // 0 if the query fails
 // LDS of the register kernel's row exchange: [2 parities][2 rows][waves][64]
 inline size_t tile2d_reg_lds_bytes(int LY, size_t elem) {
     return (size_t)4 * (LY / kRegRows) * 64 * elem;

@@ -59,20 +59,6 @@ int tile2d_inplace_threads(int LY, size_t elem) {
     return 64 * ((LY + rch - 1) / rch);
 }
 
-int tile2d_inplace_blocks_per_cu(int LY, size_t elem) {
-    const void *k = elem == 8 ? (const void *)tile2d_inplace_kernel<double>
-                              : (const void *)tile2d_inplace_kernel<float>;
-    const size_t lds = tile2d_inplace_lds_bytes(LY, elem);
-    set_lds_limit(k, lds);
-    int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, tile2d_inplace_threads(LY, elem), lds) !=
-        hipSuccess) {
-        (void)hipGetLastError();
-        return 0;
-    }
-    return n;
-}
-
 template <typename T>
 hipError_t launch_tile2d_inplace(const T *src, T *dst, int nx, int ny, T alpha, T r,
                                  const Tile2D &t, int ksteps, hipStream_t stream)
@@ -108,19 +94,6 @@ tile2d_reg_kernel(const T *src, T *dst, int nx, int ny, T alpha, T r, int halo, 
     if (t >= tiles) return;                         // whole workgroup
     reg2d_body<T, kRegRows>(src, dst, nx, ny, alpha, r, halo, ksteps, t % tiles_x, t / tiles_x,
                             reinterpret_cast<T *>(smem_raw));
-}
-
-int tile2d_reg_blocks_per_cu(int LY, size_t elem) {
-    const void *k = elem == 8 ? (const void *)tile2d_reg_kernel<double>
-                              : (const void *)tile2d_reg_kernel<float>;
-    const int nw = LY / kRegRows;
-    int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, 64 * nw, tile2d_reg_lds_bytes(LY, elem)) !=
-        hipSuccess) {
-        (void)hipGetLastError();
-        return 0;
-    }
-    return n;
 }
 
 template <typename T>
