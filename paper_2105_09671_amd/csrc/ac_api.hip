@@ -103,11 +103,11 @@ static const TileRate kInplaceF32[] = {{6, 64, 1603}, {7, 64, 1617}, {8, 64, 164
 static const TileRate kInplaceF64[] = {{3, 32, 666}, {4, 32, 749}, {5, 32, 758}, {6, 32, 730},
                                        {3, 64, 661}, {4, 64, 719}, {5, 64, 731}, {6, 64, 725}};
 
-// 3D: the register kernel is the default from 3/4 of a round of resident
-// workgroups on (measured on MI355X: 256^3 FP32, 0.57 rounds, runs 8 % faster
-// on the LDS kernel; 320^3 FP32 (1.1 rounds) and 256^3 FP64 (0.78) run 9-19 %
-// faster on the register kernel, and 1024^3 FP32 27 %)
-static const int64_t kReg3dMinRoundsNum = 3, kReg3dMinRoundsDen = 4;
+// 3D: the register kernel is the default from half a round of resident
+// workgroups on (measured on MI355X with flush tiles: 256^3 FP32, 0.57 rounds,
+// 740 GLUPS against 715 on the LDS kernel; 192^3, 0.25 rounds, 387 against
+// 509; 512^3 FP32 1254 against 817, 1024^3 1288 against 970)
+static const int64_t kReg3dMinRoundsNum = 1, kReg3dMinRoundsDen = 2;
 
 // Predicted time of a launch ~ the tiles of the busiest CU (ceil(tiles / CUs);
 // the dispatcher spreads workgroups evenly) x the time of one tile at the
@@ -226,15 +226,18 @@ ac_status make_plan3d(int nx, int ny, int nz, int64_t nsteps, size_t elem, const
         return fail(AC_ERR_UNSUPPORTED, "kernel %d is not a 3D kernel", kern);
     const bool shape_given = tune && (tune->tile_x > 0 || tune->tile_y > 0);
     // the register kernel (64 x 32 tiles: 8 waves of 4 rows) is the default when
-    // the grid yields at least 3/4 of a round of its workgroups (z segments of
+    // the grid yields at least half a round of its workgroups (z segments of
     // 32 planes); smaller grids keep the LDS kernel's 32-wide tiles, which make
     // more workgroups of the same grid
     bool reg = kern == AC_KERNEL_3D_REG;
-    if (kern == 0 && !shape_given) {
+    const bool plane32 = (int64_t)nx * ny <= INT_MAX;   // the register kernel's in-plane offsets
+    if (reg && !plane32)
+        return fail(AC_ERR_UNSUPPORTED, "3D register tiles need nx * ny < 2^31 (%d x %d)", nx, ny);
+    if (kern == 0 && !shape_given && plane32) {
         const int rk = tune && tune->tb_depth ? tune->tb_depth : (f64 ? 3 : 4);
         if (rk <= ac::kReg3dMaxDepth) {
-            const int64_t wgs = (int64_t)((nx + 63 - 2 * rk) / (64 - 2 * rk)) *
-                                ((ny + 31 - 2 * rk) / (32 - 2 * rk)) * ((nz + 31) / 32);
+            const int64_t wgs = (int64_t)ac::reg2d_tiles_1d(nx, 64, rk) *
+                                ac::reg2d_tiles_1d(ny, 32, rk) * ((nz + 31) / 32);
             const int per_cu = ac::reg3d_blocks_per_cu(rk, 32, elem);
             reg = wgs * kReg3dMinRoundsDen >=
                   kReg3dMinRoundsNum * (int64_t)std::max(per_cu, 1) * std::max(dev.cus, 1);

@@ -19,11 +19,14 @@
 // address; cells outside the domain are never exact and never read by an
 // exact cell.
 //
-// Zero-Neumann boundary (section 2): x and y edges as in the 2D register
-// kernel (EX block-uniform, EY wave-uniform variants); the z edges p = 0 and
-// p = nz-1 are a uniform branch per plane and level, so interior planes carry
-// no selects.  update3d pairs the neighbour sum per axis, so the result is
-// bitwise that of the LDS 3D kernel.
+// Zero-Neumann boundary (section 2): the xy tiles sit flush against the
+// domain edges (reg2d_tile_span), so the x and y edges cost what they cost
+// in the 2D register kernel (nothing in y, one DPP move that keeps the lane's
+// own value in x; selects only for a domain smaller than one tile); the z
+// edges p = 0 and p = nz-1 are a uniform branch per plane and level, so
+// interior planes carry no selects.  In-plane offsets are 32-bit (the plan
+// requires nx * ny < 2^31).  update3d pairs the neighbour sum per axis, so
+// the result is bitwise that of the LDS 3D kernel.
 #pragma once
 
 #include "reg2d.h"
@@ -34,31 +37,57 @@ constexpr int kReg3dPD = 2;   // level-0 planes loaded ahead of use
 
 // Level s of plane p for the wave's RCH rows: c = cur (level s-1 of plane p),
 // zm = prv (plane p-1), zp = nw (plane p+1), hu / hd the rows beyond the wave.
-template <typename T, int RCH, bool EX, bool EY, bool EZ>
+// EX: x-edge handling as in the 2D register kernel (REG_X_*); EY: the domain
+// ends inside the wave's rows at y = ny-1; EZ: plane p is a z edge.
+template <typename T, int RCH, int EX, bool EY, bool EZ>
 __device__ __forceinline__ void reg3d_level(const T cur[RCH], const T prv[RCH], const T nw[RCH],
                                             T hu, T hd, T res[RCH], int x, int nx, int y0, int ny,
                                             bool zlo, bool zhi, T alpha, T r)
 {
-    const bool atL = EX && x == 0, atR = EX && x == nx - 1;
+    const bool atL = EX == REG_X_SEL && x == 0, atR = EX == REG_X_SEL && x == nx - 1;
 #pragma unroll
     for (int q = 0; q < RCH; ++q) {
         const T c = cur[q];
         T up = q > 0 ? cur[q - 1] : hu, dn = q + 1 < RCH ? cur[q + 1] : hd;
         T zm = prv[q], zp = nw[q];
-        T l = wave_shift<kDppWaveShr1>(c), rr = wave_shift<kDppWaveShl1>(c);
-        if (EX) {
+        T l = EX == REG_X_LEFT ? wave_shift_keep<kDppWaveShr1>(c) : wave_shift<kDppWaveShr1>(c);
+        T rr = EX == REG_X_RIGHT ? wave_shift_keep<kDppWaveShl1>(c) : wave_shift<kDppWaveShl1>(c);
+        if (EX == REG_X_SEL) {
             l = atL ? c : l;
             rr = atR ? c : rr;
         }
-        if (EY) {
-            up = y0 + q == 0 ? c : up;
-            dn = y0 + q == ny - 1 ? c : dn;
-        }
+        if (EY) dn = y0 + q == ny - 1 ? c : dn;
         if (EZ) {
             zm = zlo ? c : zm;
             zp = zhi ? c : zp;
         }
         res[q] = update3d<T>(c, l, rr, up, dn, zm, zp, alpha, r);
+    }
+}
+
+template <typename T, int RCH, bool EY, bool EZ>
+__device__ __forceinline__ void reg3d_level_x(int ex, const T cur[RCH], const T prv[RCH],
+                                              const T nw[RCH], T hu, T hd, T res[RCH], int x,
+                                              int nx, int y0, int ny, bool zlo, bool zhi, T alpha,
+                                              T r)
+{
+    switch (ex) {
+    case REG_X_IN:
+        reg3d_level<T, RCH, REG_X_IN, EY, EZ>(cur, prv, nw, hu, hd, res, x, nx, y0, ny, zlo, zhi,
+                                              alpha, r);
+        break;
+    case REG_X_LEFT:
+        reg3d_level<T, RCH, REG_X_LEFT, EY, EZ>(cur, prv, nw, hu, hd, res, x, nx, y0, ny, zlo, zhi,
+                                                alpha, r);
+        break;
+    case REG_X_RIGHT:
+        reg3d_level<T, RCH, REG_X_RIGHT, EY, EZ>(cur, prv, nw, hu, hd, res, x, nx, y0, ny, zlo,
+                                                 zhi, alpha, r);
+        break;
+    default:
+        reg3d_level<T, RCH, REG_X_SEL, EY, EZ>(cur, prv, nw, hu, hd, res, x, nx, y0, ny, zlo, zhi,
+                                               alpha, r);
+        break;
     }
 }
 
@@ -74,21 +103,27 @@ __device__ __forceinline__ void reg3d_body(const T *__restrict__ src, T *__restr
     const int tx = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int NW = blockDim.x >> 6;
-    const int OX = 64 - 2 * K, OY = NW * RCH - 2 * K;
-    const int ox0 = (tile % tiles_x) * OX, oy0 = (tile / tiles_x) * OY;
-    const int ox1 = min(ox0 + OX, nx), oy1 = min(oy0 + OY, ny);
+    const int LY = NW * RCH;
+    // xy tiles sit flush against the domain edges as in the 2D register kernel
+    const int tile_x = tile % tiles_x, tile_y = tile / tiles_x;
+    const int nty = reg2d_tiles_1d(ny, LY, K);
+    int lx0, ox0, ox1, ly0, oy0, oy1;
+    reg2d_tile_span(tile_x, tiles_x, nx, 64, K, &lx0, &ox0, &ox1);
+    reg2d_tile_span(tile_y, nty, ny, LY, K, &ly0, &oy0, &oy1);
     const int oz0 = zseg * LZ, oz1 = min(oz0 + LZ, nz);
-    const int lx0 = ox0 - K;
     const int x = lx0 + tx;
-    const int y0 = oy0 - K + w * RCH;
-    const int xc = min(max(x, 0), nx - 1);
-    const bool edgeX = lx0 <= 0 || lx0 + 63 >= nx - 1;
-    const bool edgeY = y0 <= 0 || y0 + RCH - 1 >= ny - 1;
+    const int y0 = ly0 + w * RCH;
+    const int xc = min(x, nx - 1);
+    const int ex = nx < 64 || tiles_x == 1 ? REG_X_SEL
+                   : tile_x == 0           ? REG_X_LEFT
+                   : tile_x == tiles_x - 1 ? REG_X_RIGHT
+                                           : REG_X_IN;
+    const bool edgeY = ny < LY && y0 <= ny - 1 && y0 + RCH - 1 >= ny - 1;
     const bool xout = x >= ox0 && x < ox1;
     const size_t pstride = (size_t)nx * ny;
     int gxy[RCH];
 #pragma unroll
-    for (int q = 0; q < RCH; ++q) gxy[q] = min(max(y0 + q, 0), ny - 1) * nx + xc;
+    for (int q = 0; q < RCH; ++q) gxy[q] = min(y0 + q, ny - 1) * nx + xc;
 
     T cur[K][RCH], prv[K][RCH], pf[PD][RCH];
 #pragma unroll
@@ -134,19 +169,14 @@ __device__ __forceinline__ void reg3d_body(const T *__restrict__ src, T *__restr
                                     : cur[s - 1][RCH - 1];
             const bool zlo = p == 0, zhi = p == nz - 1;
             T res[RCH];
-#define AC_REG3D_LEVEL(EX_, EY_)                                                                   \
-    if (zlo || zhi)                                                                                \
-        reg3d_level<T, RCH, EX_, EY_, true>(cur[s - 1], prv[s - 1], nw, hu, hd, res, x, nx, y0,    \
-                                            ny, zlo, zhi, alpha, r);                               \
-    else                                                                                           \
-        reg3d_level<T, RCH, EX_, EY_, false>(cur[s - 1], prv[s - 1], nw, hu, hd, res, x, nx, y0,   \
-                                             ny, false, false, alpha, r);
-            if (edgeX) {
-                if (edgeY) { AC_REG3D_LEVEL(true, true) } else { AC_REG3D_LEVEL(true, false) }
+            const bool ez = zlo || zhi;
+            if (edgeY) {
+                if (ez) reg3d_level_x<T, RCH, true, true>(ex, cur[s - 1], prv[s - 1], nw, hu, hd, res, x, nx, y0, ny, zlo, zhi, alpha, r);
+                else    reg3d_level_x<T, RCH, true, false>(ex, cur[s - 1], prv[s - 1], nw, hu, hd, res, x, nx, y0, ny, false, false, alpha, r);
             } else {
-                if (edgeY) { AC_REG3D_LEVEL(false, true) } else { AC_REG3D_LEVEL(false, false) }
+                if (ez) reg3d_level_x<T, RCH, false, true>(ex, cur[s - 1], prv[s - 1], nw, hu, hd, res, x, nx, y0, ny, zlo, zhi, alpha, r);
+                else    reg3d_level_x<T, RCH, false, false>(ex, cur[s - 1], prv[s - 1], nw, hu, hd, res, x, nx, y0, ny, false, false, alpha, r);
             }
-#undef AC_REG3D_LEVEL
 #pragma unroll
             for (int q = 0; q < RCH; ++q) {
                 prv[s - 1][q] = cur[s - 1][q];

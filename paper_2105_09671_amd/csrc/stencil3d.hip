@@ -132,8 +132,8 @@ hipError_t launch_reg3d(const T *src, T *dst, int nx, int ny, int nz, T alpha, T
     const void *k = reg3d_kernel_of<T>(t.K);
     if (!k || t.LX != 64 || t.LY % kReg3dRows || t.LY / kReg3dRows > kReg3dMaxWaves)
         return hipErrorInvalidValue;
-    const int OX = 64 - 2 * t.K, OY = t.LY - 2 * t.K;
-    const int tiles_x = (nx + OX - 1) / OX, tiles_y = (ny + OY - 1) / OY;
+    // xy tiles flush against the domain edges (reg2d_tile_span)
+    const int tiles_x = reg2d_tiles_1d(nx, 64, t.K), tiles_y = reg2d_tiles_1d(ny, t.LY, t.K);
     dim3 grid(tiles_x * tiles_y, (nz + t.LZ - 1) / t.LZ);
     const size_t lds = reg3d_lds_bytes(t.K, t.LY, sizeof(T));
     set_lds_limit(k, lds);

@@ -212,6 +212,25 @@ def test_3d_register_kernel(api, dtype):
         assert np.array_equal(got, base), (k, ly, lz)
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_3d_register_tiling_sizes(api, dtype):
+    """3D register tiles sit flush against the x and y domain edges like the 2D
+    ones.  Depth 3, 64 x 16 tiles (58 x 10 outputs), z segments of 4 planes,
+    sizes around the tile-count thresholds, 7 steps (a shorter last launch):
+    bitwise the LDS kernel and the oracle."""
+    h, dt, eps = _par(48, 4)
+    for nz, ny, nx in [(5, 16, 64), (6, 17, 65), (4, 15, 63), (5, 22, 122), (3, 23, 123),
+                       (7, 9, 70), (9, 1, 100), (2, 60, 1), (5, 26, 131)]:
+        phi0 = inputs.random_field((nz, ny, nx), seed=36 + nx + ny + nz, amp=0.9).astype(NP[dtype])
+        ref = oracle.step3d(phi0.astype(np.float64), h, dt, eps, 7)
+        reg = _run3d(api, phi0, h, dt, eps, 7, dtype,
+                     tune=dict(tb_depth=3, tile_x=64, tile_y=16, tile_z=4, kernel=5))
+        lds = _run3d(api, phi0, h, dt, eps, 7, dtype,
+                     tune=dict(tb_depth=3, tile_x=16, tile_y=16, tile_z=4, kernel=2))
+        assert np.array_equal(reg, lds), (nz, ny, nx)
+        assert D.rel_linf(reg, ref) <= TOL[dtype], (nz, ny, nx)
+
+
 def test_3d_plan_kernels(api):
     from paper_2105_09671_amd import _lib as L
     # large grids run on register tiles, grids of too few 64-wide tiles on LDS
