@@ -207,7 +207,8 @@ def extras(api, torch, workloads, params) -> dict:
     out["table3_err_fp32_vs_fp64"] = paper_suite.err_table()
     log("extra table3_err_fp32_vs_fp64", out["table3_err_fp32_vs_fp64"])
     # the fused FP32 + FP64 trace kernel on 2048^2: 24 algorithmic bytes per
-    # cell and step (read 4 + 8, write 4 + 8), one launch per step
+    # cell and step (read 4 + 8, write 4 + 8); depth-7 register tiles, so the
+    # effective fraction of 8 TB/s can exceed 1
     g = workloads.circle2048()
     p32 = torch.from_numpy(g.initial()).float().cuda()
     p64 = p32.double()
@@ -215,8 +216,9 @@ def extras(api, torch, workloads, params) -> dict:
     n = 200
     sec = timed(lambda: api.err_trace(p32, p64, g.h, g.dt, g.eps, n), 3)
     gbs = 24.0 * g.nx * g.ny * n / sec / 1e9
-    out["err_trace_2048"] = {"steps": n, "ms": round(sec * 1e3, 3), "GBps": round(gbs, 1),
-                             "frac_hbm": round(gbs / HBM_PEAK_GBS, 3)}
+    out["err_trace_2048"] = {"steps": n, "ms": round(sec * 1e3, 3), "GBps_eff": round(gbs, 1),
+                             "f_eff": round(gbs / HBM_PEAK_GBS, 3),
+                             "G_pair_updates_s": round(g.nx * g.ny * n / sec / 1e9, 1)}
     log("extra err_trace_2048", out["err_trace_2048"])
     del p32, p64
     return out

@@ -1,22 +1,27 @@
 // Precision trace: the paper's Err (section 2, Eq. ERReq) between an FP32 and
 // an FP64 run of the same explicit step, computed on the device.
 //
-// One launch advances both fields by one step (the update of update2d /
-// update3d, zero-Neumann by clamped neighbour indices) and adds the squared
-// difference of the two new states, in FP64, to that step's slot of
-// sq[nsteps]: per-lane sums, a workgroup reduction (cross-lane shuffles, then
-// LDS), one FP64 atomic per workgroup and at most 1024 workgroups.  A final one-workgroup kernel turns the slots into
-// rms[t] = sqrt(sq[t] / cells) and Err = mean over t of rms[t].  The fields are
-// read from HBM every step (no temporal blocking): this is a verification
-// path, its cost is two plain stencil passes per step.
+// 2D: register tiles (reg2d.h) holding both precisions of every cell advance
+// `depth` steps per launch; after each sub-step every wave adds the squared
+// difference of the two states, in FP64, over the cells of its tile's output
+// region -- exact at every sub-step, and each cell of the grid in exactly one
+// output region -- and a workgroup adds its per-step sums to sq[t] with one
+// FP64 atomic per step.  3D: one launch per step (the update of update3d,
+// zero-Neumann by clamped neighbour indices) with the same per-step sums;
+// rows are dealt to workgroups round-robin.  A final one-workgroup kernel
+// turns the slots into rms[t] = sqrt(sq[t] / cells) and Err = mean over t of
+// rms[t].  Both precisions are stepped by update2d / update3d, so the FP32
+// path is bitwise the product stepper and the FP64 path the FP64 stepper.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdint>
 #include <utility>
 
 #include "ac_internal.h"
+#include "reg2d.h"
 
 namespace ac {
 
@@ -56,33 +61,100 @@ __device__ inline void block_add(double v, double *slot) {
     }
 }
 
-// Rows (2D) or (plane, row) pairs (3D) are dealt to workgroups round-robin;
-// the lanes of a workgroup sweep a row in 256-wide strides.
-__global__ void __launch_bounds__(ERR_THREADS)
-err_step2d_kernel(const float *__restrict__ a32, float *__restrict__ b32,
+// 2D trace tiles: 64 x ERR_ROWS * ERR_WAVES cells, depth up to ERR_DEPTH.
+constexpr int ERR_ROWS = 16, ERR_WAVES = 8, ERR_DEPTH = 7;
+
+// Advance one register tile of both fields by ksteps <= halo steps, adding the
+// per-step squared differences over its output region to sq[0 .. ksteps).
+// The 1-D grid is XCD-banded as in the 2D register kernel.
+__global__ void __launch_bounds__(64 * ERR_WAVES)
+err_tile2d_kernel(const float *__restrict__ a32, float *__restrict__ b32,
                   const double *__restrict__ a64, double *__restrict__ b64, int nx, int ny,
-                  float alpha32, float r32, double alpha64, double r64, double *sq_t)
+                  float alpha32, float r32, double alpha64, double r64, int halo, int ksteps,
+                  int tiles_x, int tiles, double *sq)
 {
-    double acc = 0.0;
-    for (int y = blockIdx.x; y < ny; y += gridDim.x) {
-        const size_t row = (size_t)y * nx;
-        const long long up = y > 0 ? -(long long)nx : 0, dn = y < ny - 1 ? (long long)nx : 0;
-        for (int x = threadIdx.x; x < nx; x += blockDim.x) {
-            const size_t c = row + x;
-            const long long l = x > 0 ? -1 : 0, rr = x < nx - 1 ? 1 : 0;
-            const float f = update2d<float>(a32[c], a32[c + l], a32[c + rr], a32[c + up], a32[c + dn],
-                                            alpha32, r32);
-            const double d = update2d<double>(a64[c], a64[c + l], a64[c + rr], a64[c + up],
-                                              a64[c + dn], alpha64, r64);
-            b32[c] = f;
-            b64[c] = d;
-            const double e = (double)f - d;
-            acc += e * e;
+    constexpr int RCH = ERR_ROWS, NW = ERR_WAVES, LY = RCH * NW;
+    __shared__ float x32[2][2][NW][64];
+    __shared__ double x64[2][2][NW][64];
+    __shared__ double part[ERR_DEPTH][NW];
+    const int per = (tiles + 7) >> 3;
+    const int t = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+    if (t >= tiles) return;                         // whole workgroup
+    const int tx = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int tile_x = t % tiles_x, tile_y = t / tiles_x;
+    int lx0, ox0, ox1, ly0, oy0, oy1;
+    reg2d_tile_span(tile_x, tiles_x, nx, 64, halo, &lx0, &ox0, &ox1);
+    reg2d_tile_span(tile_y, reg2d_tiles_1d(ny, LY, halo), ny, LY, halo, &ly0, &oy0, &oy1);
+    const int x = lx0 + tx;
+    const int y0 = ly0 + w * RCH;
+    const int xc = min(x, nx - 1);
+    float v32[RCH];
+    double v64[RCH];
+#pragma unroll
+    for (int q = 0; q < RCH; ++q) {
+        const size_t c = (size_t)min(y0 + q, ny - 1) * nx + xc;
+        v32[q] = a32[c];
+        v64[q] = a64[c];
+    }
+    const int ex = nx < 64 || tiles_x == 1 ? REG_X_SEL
+                   : tile_x == 0           ? REG_X_LEFT
+                   : tile_x == tiles_x - 1 ? REG_X_RIGHT
+                                           : REG_X_IN;
+    const bool edgeY = ny < LY && y0 <= ny - 1 && y0 + RCH - 1 >= ny - 1;
+    const bool xout = x >= ox0 && x < ox1;
+    for (int s = 0; s < ksteps; ++s) {
+        const int pb = s & 1;
+        x32[pb][0][w][tx] = v32[0];
+        x32[pb][1][w][tx] = v32[RCH - 1];
+        x64[pb][0][w][tx] = v64[0];
+        x64[pb][1][w][tx] = v64[RCH - 1];
+        __syncthreads();
+        const float hu32 = w > 0 ? x32[pb][1][w - 1][tx] : v32[0];
+        const float hd32 = w + 1 < NW ? x32[pb][0][w + 1][tx] : v32[RCH - 1];
+        const double hu64 = w > 0 ? x64[pb][1][w - 1][tx] : v64[0];
+        const double hd64 = w + 1 < NW ? x64[pb][0][w + 1][tx] : v64[RCH - 1];
+        if (edgeY) {
+            reg2d_substep_x<float, RCH, true>(ex, v32, hu32, hd32, x, nx, y0, ny, alpha32, r32);
+            reg2d_substep_x<double, RCH, true>(ex, v64, hu64, hd64, x, nx, y0, ny, alpha64, r64);
+        } else {
+            reg2d_substep_x<float, RCH, false>(ex, v32, hu32, hd32, x, nx, y0, ny, alpha32, r32);
+            reg2d_substep_x<double, RCH, false>(ex, v64, hu64, hd64, x, nx, y0, ny, alpha64, r64);
+        }
+        double acc = 0.0;
+        if (xout) {
+#pragma unroll
+            for (int q = 0; q < RCH; ++q) {
+                const int y = y0 + q;
+                const double e = (double)v32[q] - v64[q];
+                acc += (y >= oy0 && y < oy1) ? e * e : 0.0;
+            }
+        }
+        acc = wave_sum(acc);
+        if (tx == 0) part[s][w] = acc;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < ksteps) {
+        double sum = 0.0;
+#pragma unroll
+        for (int i = 0; i < NW; ++i) sum += part[threadIdx.x][i];
+        atomicAdd(sq + threadIdx.x, sum);
+    }
+    if (xout) {
+#pragma unroll
+        for (int q = 0; q < RCH; ++q) {
+            const int y = y0 + q;
+            if (y >= oy0 && y < oy1) {
+                const size_t c = (size_t)y * nx + x;
+                __builtin_nontemporal_store(v32[q], b32 + c);
+                __builtin_nontemporal_store(v64[q], b64 + c);
+            }
         }
     }
-    block_add(acc, sq_t);
 }
 
+// 3D: (plane, row) pairs are dealt to workgroups round-robin; the lanes of a
+// workgroup sweep a row in 256-wide strides.
 __global__ void __launch_bounds__(ERR_THREADS)
 err_step3d_kernel(const float *__restrict__ a32, float *__restrict__ b32,
                   const double *__restrict__ a64, double *__restrict__ b64, int nx, int ny, int nz,
@@ -138,25 +210,28 @@ err_finish_kernel(double *sq, long long n, double cells, double *err)
     }
 }
 
-// Ping-pong both precisions through nsteps one-step launches; the final states
-// end in phi32 / phi64 (a copy back when nsteps is odd).
+// Ping-pong both precisions through ceil(nsteps / depth) launches of up to
+// `depth` steps; the final states end in phi32 / phi64 (a copy back when the
+// launch count is odd).  step(s32, d32, s64, d64, k, slots) runs k steps.
 template <typename Launch>
 ac_status run_trace(float *phi32, float *work32, double *phi64, double *work64, long long cells,
-                    int64_t nsteps, double *rms, double *err, hipStream_t st, Launch step) {
+                    int64_t nsteps, int depth, double *rms, double *err, hipStream_t st,
+                    Launch step) {
     const unsigned zb = (unsigned)std::min<long long>((nsteps + 255) / 256 + 1, 1024);
     hipLaunchKernelGGL(err_zero_kernel, dim3(zb), dim3(256), 0, st, rms, (long long)nsteps);
-    (void)cells;
     float *s32 = phi32, *d32 = work32;
     double *s64 = phi64, *d64 = work64;
-    for (int64_t t = 0; t < nsteps; ++t) {
-        step(s32, d32, s64, d64, rms + t);
+    int64_t launches = 0;
+    for (int64_t t = 0; t < nsteps; t += depth, ++launches) {
+        const int k = (int)std::min<int64_t>(depth, nsteps - t);
+        step(s32, d32, s64, d64, k, rms + t);
         std::swap(s32, d32);
         std::swap(s64, d64);
     }
     hipLaunchKernelGGL(err_finish_kernel, dim3(1), dim3(ERR_THREADS), 0, st, rms,
                        (long long)nsteps, (double)cells, err);
     hipError_t e = hipGetLastError();
-    if (e == hipSuccess && (nsteps & 1)) {
+    if (e == hipSuccess && (launches & 1)) {
         e = hipMemcpyAsync(phi32, s32, (size_t)cells * 4, hipMemcpyDeviceToDevice, st);
         if (e == hipSuccess)
             e = hipMemcpyAsync(phi64, s64, (size_t)cells * 8, hipMemcpyDeviceToDevice, st);
@@ -186,11 +261,18 @@ ac_status ac_err_2d(float *phi32, float *work32, double *phi64, double *work64, 
     if ((s = check_disjoint(phi32, work32, phi64, work64, cells)) != AC_OK) return s;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const float a32 = (float)alpha, r32 = (float)r;
-    return run_trace(phi32, work32, phi64, work64, cells, nsteps, rms, err, st,
-                     [&](const float *s32, float *d32, const double *s64, double *d64,
-                         double *slot) {
-                         hipLaunchKernelGGL(err_step2d_kernel, dim3((unsigned)std::min(ny, 1024)), dim3(ERR_THREADS), 0, st,
-                                            s32, d32, s64, d64, nx, ny, a32, r32, alpha, r, slot);
+    // depth-7 register tiles of 64 x 128 cells (the 2D stepper's plan on 2048^2)
+    const int K = ERR_DEPTH;
+    const int64_t tx = reg2d_tiles_1d(nx, 64, K),
+                  tiles = tx * reg2d_tiles_1d(ny, ERR_ROWS * ERR_WAVES, K);
+    if (tiles > INT_MAX - 8) return fail(AC_ERR_UNSUPPORTED, "grid too large for the trace tiles");
+    const dim3 grid((unsigned)((tiles + 7) / 8 * 8));
+    return run_trace(phi32, work32, phi64, work64, cells, nsteps, K, rms, err, st,
+                     [&](const float *s32, float *d32, const double *s64, double *d64, int k,
+                         double *slots) {
+                         hipLaunchKernelGGL(err_tile2d_kernel, grid, dim3(64 * ERR_WAVES), 0, st,
+                                            s32, d32, s64, d64, nx, ny, a32, r32, alpha, r, K, k,
+                                            (int)tx, (int)tiles, slots);
                      });
 }
 
@@ -209,8 +291,8 @@ ac_status ac_err_3d(float *phi32, float *work32, double *phi64, double *work64, 
     if ((s = check_disjoint(phi32, work32, phi64, work64, cells)) != AC_OK) return s;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const float a32 = (float)alpha, r32 = (float)r;
-    return run_trace(phi32, work32, phi64, work64, cells, nsteps, rms, err, st,
-                     [&](const float *s32, float *d32, const double *s64, double *d64,
+    return run_trace(phi32, work32, phi64, work64, cells, nsteps, 1, rms, err, st,
+                     [&](const float *s32, float *d32, const double *s64, double *d64, int,
                          double *slot) {
                          hipLaunchKernelGGL(err_step3d_kernel,
                                             dim3((unsigned)std::min<long long>((long long)ny * nz, 1024)), dim3(ERR_THREADS), 0, st,
