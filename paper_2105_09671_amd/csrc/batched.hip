@@ -472,10 +472,11 @@ ac_status build_plan(Plan &p, const ac_instance2d *inst, int32_t n, int64_t nste
     // launch shape: the single-grid tiled plan for the same tune (forced tiled)
     ac_tune t = tune;
     if (t.tile_x == 0) t.tile_x = 64;
-    // default: depth 6 on 64 x 64 register tiles (4 waves), fastest measured on
-    // the 512-grid batch in both precisions (FP32 2200 GLUPS, FP64 1370)
-    if (t.tile_y == 0) t.tile_y = 64;
-    if (t.tb_depth == 0) t.tb_depth = 6;
+    // default: depth 8 on 64 x 128 register tiles (8 waves), fastest measured
+    // on the 512-grid batch in both precisions (FP32 2494 GLUPS, FP64 1501;
+    // depth 6 on 64 x 64: 2439 / 1405)
+    if (t.tile_y == 0) t.tile_y = 128;
+    if (t.tb_depth == 0) t.tb_depth = 8;
     ac_plan tp;
     ac_status s = make_plan2d(4096, 4096, nsteps, elem, &t, dev, &tp);
     if (s != AC_OK) return s;
