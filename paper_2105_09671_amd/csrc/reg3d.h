@@ -65,66 +65,21 @@ __device__ __forceinline__ void reg3d_level(const T cur[RCH], const T prv[RCH], 
     }
 }
 
-template <typename T, int RCH, bool EY, bool EZ>
-__device__ __forceinline__ void reg3d_level_x(int ex, const T cur[RCH], const T prv[RCH],
-                                              const T nw[RCH], T hu, T hd, T res[RCH], int x,
-                                              int nx, int y0, int ny, bool zlo, bool zhi, T alpha,
-                                              T r)
-{
-    switch (ex) {
-    case REG_X_IN:
-        reg3d_level<T, RCH, REG_X_IN, EY, EZ>(cur, prv, nw, hu, hd, res, x, nx, y0, ny, zlo, zhi,
-                                              alpha, r);
-        break;
-    case REG_X_LEFT:
-        reg3d_level<T, RCH, REG_X_LEFT, EY, EZ>(cur, prv, nw, hu, hd, res, x, nx, y0, ny, zlo, zhi,
-                                                alpha, r);
-        break;
-    case REG_X_RIGHT:
-        reg3d_level<T, RCH, REG_X_RIGHT, EY, EZ>(cur, prv, nw, hu, hd, res, x, nx, y0, ny, zlo,
-                                                 zhi, alpha, r);
-        break;
-    default:
-        reg3d_level<T, RCH, REG_X_SEL, EY, EZ>(cur, prv, nw, hu, hd, res, x, nx, y0, ny, zlo, zhi,
-                                               alpha, r);
-        break;
-    }
-}
-
-// Advance xy tile `tile` (row-major over tiles_x columns) of z segment `zseg`
-// (LZ planes) by K steps.  xb: LDS exchange, [2 parities][K levels][2 rows]
-// [NW waves][64 lanes].
-template <typename T, int K, int RCH>
-__device__ __forceinline__ void reg3d_body(const T *__restrict__ src, T *__restrict__ dst, int nx,
-                                           int ny, int nz, T alpha, T r, int LZ, int tiles_x,
-                                           int tile, int zseg, T *xb)
+// The plane loop of one tile for one x/y edge variant (chosen once per tile,
+// so the loop carries no per-level dispatch): K levels pipelined along the z
+// segment [oz0, oz1).  xb: LDS exchange, [2 parities][K levels][2 rows][NW
+// waves][64 lanes].
+template <typename T, int K, int RCH, int EX, bool EY>
+__device__ __forceinline__ void reg3d_stream(const T *__restrict__ src, T *__restrict__ dst, int nx,
+                                             int ny, int nz, T alpha, T r, int x, int y0, bool xout,
+                                             int oy0, int oy1, int oz0, int oz1,
+                                             const int (&gxy)[RCH], T *xb)
 {
     constexpr int PD = kReg3dPD;
     const int tx = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int NW = blockDim.x >> 6;
-    const int LY = NW * RCH;
-    // xy tiles sit flush against the domain edges as in the 2D register kernel
-    const int tile_x = tile % tiles_x, tile_y = tile / tiles_x;
-    const int nty = reg2d_tiles_1d(ny, LY, K);
-    int lx0, ox0, ox1, ly0, oy0, oy1;
-    reg2d_tile_span(tile_x, tiles_x, nx, 64, K, &lx0, &ox0, &ox1);
-    reg2d_tile_span(tile_y, nty, ny, LY, K, &ly0, &oy0, &oy1);
-    const int oz0 = zseg * LZ, oz1 = min(oz0 + LZ, nz);
-    const int x = lx0 + tx;
-    const int y0 = ly0 + w * RCH;
-    const int xc = min(x, nx - 1);
-    const int ex = nx < 64 || tiles_x == 1 ? REG_X_SEL
-                   : tile_x == 0           ? REG_X_LEFT
-                   : tile_x == tiles_x - 1 ? REG_X_RIGHT
-                                           : REG_X_IN;
-    const bool edgeY = ny < LY && y0 <= ny - 1 && y0 + RCH - 1 >= ny - 1;
-    const bool xout = x >= ox0 && x < ox1;
     const size_t pstride = (size_t)nx * ny;
-    int gxy[RCH];
-#pragma unroll
-    for (int q = 0; q < RCH; ++q) gxy[q] = min(y0 + q, ny - 1) * nx + xc;
-
     T cur[K][RCH], prv[K][RCH], pf[PD][RCH];
 #pragma unroll
     for (int s = 0; s < K; ++s)
@@ -169,14 +124,12 @@ __device__ __forceinline__ void reg3d_body(const T *__restrict__ src, T *__restr
                                     : cur[s - 1][RCH - 1];
             const bool zlo = p == 0, zhi = p == nz - 1;
             T res[RCH];
-            const bool ez = zlo || zhi;
-            if (edgeY) {
-                if (ez) reg3d_level_x<T, RCH, true, true>(ex, cur[s - 1], prv[s - 1], nw, hu, hd, res, x, nx, y0, ny, zlo, zhi, alpha, r);
-                else    reg3d_level_x<T, RCH, true, false>(ex, cur[s - 1], prv[s - 1], nw, hu, hd, res, x, nx, y0, ny, false, false, alpha, r);
-            } else {
-                if (ez) reg3d_level_x<T, RCH, false, true>(ex, cur[s - 1], prv[s - 1], nw, hu, hd, res, x, nx, y0, ny, zlo, zhi, alpha, r);
-                else    reg3d_level_x<T, RCH, false, false>(ex, cur[s - 1], prv[s - 1], nw, hu, hd, res, x, nx, y0, ny, false, false, alpha, r);
-            }
+            if (zlo || zhi)
+                reg3d_level<T, RCH, EX, EY, true>(cur[s - 1], prv[s - 1], nw, hu, hd, res, x, nx, y0,
+                                                  ny, zlo, zhi, alpha, r);
+            else
+                reg3d_level<T, RCH, EX, EY, false>(cur[s - 1], prv[s - 1], nw, hu, hd, res, x, nx,
+                                                   y0, ny, false, false, alpha, r);
 #pragma unroll
             for (int q = 0; q < RCH; ++q) {
                 prv[s - 1][q] = cur[s - 1][q];
@@ -193,6 +146,70 @@ __device__ __forceinline__ void reg3d_body(const T *__restrict__ src, T *__restr
             }
         }
     }
+}
+
+template <typename T, int K, int RCH, bool EY>
+__device__ __forceinline__ void reg3d_stream_x(int ex, const T *__restrict__ src, T *__restrict__ dst,
+                                               int nx, int ny, int nz, T alpha, T r, int x, int y0,
+                                               bool xout, int oy0, int oy1, int oz0, int oz1,
+                                               const int (&gxy)[RCH], T *xb)
+{
+    switch (ex) {
+    case REG_X_IN:
+        reg3d_stream<T, K, RCH, REG_X_IN, EY>(src, dst, nx, ny, nz, alpha, r, x, y0, xout, oy0, oy1,
+                                              oz0, oz1, gxy, xb);
+        break;
+    case REG_X_LEFT:
+        reg3d_stream<T, K, RCH, REG_X_LEFT, EY>(src, dst, nx, ny, nz, alpha, r, x, y0, xout, oy0,
+                                                oy1, oz0, oz1, gxy, xb);
+        break;
+    case REG_X_RIGHT:
+        reg3d_stream<T, K, RCH, REG_X_RIGHT, EY>(src, dst, nx, ny, nz, alpha, r, x, y0, xout, oy0,
+                                                 oy1, oz0, oz1, gxy, xb);
+        break;
+    default:
+        reg3d_stream<T, K, RCH, REG_X_SEL, EY>(src, dst, nx, ny, nz, alpha, r, x, y0, xout, oy0,
+                                               oy1, oz0, oz1, gxy, xb);
+        break;
+    }
+}
+
+// Advance xy tile `tile` (row-major over tiles_x columns) of z segment `zseg`
+// (LZ planes) by K steps.  xb: the LDS row exchange of reg3d_stream.
+template <typename T, int K, int RCH>
+__device__ __forceinline__ void reg3d_body(const T *__restrict__ src, T *__restrict__ dst, int nx,
+                                           int ny, int nz, T alpha, T r, int LZ, int tiles_x,
+                                           int tile, int zseg, T *xb)
+{
+    const int tx = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int NW = blockDim.x >> 6;
+    const int LY = NW * RCH;
+    // xy tiles sit flush against the domain edges as in the 2D register kernel
+    const int tile_x = tile % tiles_x, tile_y = tile / tiles_x;
+    const int nty = reg2d_tiles_1d(ny, LY, K);
+    int lx0, ox0, ox1, ly0, oy0, oy1;
+    reg2d_tile_span(tile_x, tiles_x, nx, 64, K, &lx0, &ox0, &ox1);
+    reg2d_tile_span(tile_y, nty, ny, LY, K, &ly0, &oy0, &oy1);
+    const int oz0 = zseg * LZ, oz1 = min(oz0 + LZ, nz);
+    const int x = lx0 + tx;
+    const int y0 = ly0 + w * RCH;
+    const int xc = min(x, nx - 1);
+    const int ex = nx < 64 || tiles_x == 1 ? REG_X_SEL
+                   : tile_x == 0           ? REG_X_LEFT
+                   : tile_x == tiles_x - 1 ? REG_X_RIGHT
+                                           : REG_X_IN;
+    const bool edgeY = ny < LY && y0 <= ny - 1 && y0 + RCH - 1 >= ny - 1;
+    const bool xout = x >= ox0 && x < ox1;
+    int gxy[RCH];
+#pragma unroll
+    for (int q = 0; q < RCH; ++q) gxy[q] = min(y0 + q, ny - 1) * nx + xc;
+    if (edgeY)
+        reg3d_stream_x<T, K, RCH, true>(ex, src, dst, nx, ny, nz, alpha, r, x, y0, xout, oy0, oy1,
+                                        oz0, oz1, gxy, xb);
+    else
+        reg3d_stream_x<T, K, RCH, false>(ex, src, dst, nx, ny, nz, alpha, r, x, y0, xout, oy0, oy1,
+                                         oz0, oz1, gxy, xb);
 }
 
 }  // namespace ac
