@@ -64,6 +64,47 @@ __device__ inline void block_add(double v, double *slot) {
 // 2D trace tiles: 64 x ERR_ROWS * ERR_WAVES cells, depth up to ERR_DEPTH.
 constexpr int ERR_ROWS = 16, ERR_WAVES = 8, ERR_DEPTH = 7;
 
+// The fused steps of one trace tile for one x/y edge variant: both precisions
+// advance together; after each sub-step every wave's sum of squared
+// differences over the output cells goes to part[s][wave].
+template <int EX, bool EY>
+__device__ __forceinline__ void err_steps(float (&v32)[ERR_ROWS], double (&v64)[ERR_ROWS], int x,
+                                          int nx, int y0, int ny, bool xout, int oy0, int oy1,
+                                          float alpha32, float r32, double alpha64, double r64,
+                                          int ksteps, float (*x32)[2][ERR_WAVES][64],
+                                          double (*x64)[2][ERR_WAVES][64],
+                                          double (*part)[ERR_WAVES])
+{
+    constexpr int RCH = ERR_ROWS, NW = ERR_WAVES;
+    const int tx = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (int s = 0; s < ksteps; ++s) {
+        const int pb = s & 1;
+        x32[pb][0][w][tx] = v32[0];
+        x32[pb][1][w][tx] = v32[RCH - 1];
+        x64[pb][0][w][tx] = v64[0];
+        x64[pb][1][w][tx] = v64[RCH - 1];
+        __syncthreads();
+        const float hu32 = w > 0 ? x32[pb][1][w - 1][tx] : v32[0];
+        const float hd32 = w + 1 < NW ? x32[pb][0][w + 1][tx] : v32[RCH - 1];
+        const double hu64 = w > 0 ? x64[pb][1][w - 1][tx] : v64[0];
+        const double hd64 = w + 1 < NW ? x64[pb][0][w + 1][tx] : v64[RCH - 1];
+        reg2d_substep<float, RCH, EX, EY>(v32, hu32, hd32, x, nx, y0, ny, alpha32, r32);
+        reg2d_substep<double, RCH, EX, EY>(v64, hu64, hd64, x, nx, y0, ny, alpha64, r64);
+        double acc = 0.0;
+        if (xout) {
+#pragma unroll
+            for (int q = 0; q < RCH; ++q) {
+                const int y = y0 + q;
+                const double e = (double)v32[q] - v64[q];
+                acc += (y >= oy0 && y < oy1) ? e * e : 0.0;
+            }
+        }
+        acc = wave_sum(acc);
+        if (tx == 0) part[s][w] = acc;
+    }
+}
+
 // Advance one register tile of both fields by ksteps <= halo steps, adding the
 // per-step squared differences over its output region to sq[0 .. ksteps).
 // The 1-D grid is XCD-banded as in the 2D register kernel.
@@ -103,36 +144,25 @@ err_tile2d_kernel(const float *__restrict__ a32, float *__restrict__ b32,
                                            : REG_X_IN;
     const bool edgeY = ny < LY && y0 <= ny - 1 && y0 + RCH - 1 >= ny - 1;
     const bool xout = x >= ox0 && x < ox1;
-    for (int s = 0; s < ksteps; ++s) {
-        const int pb = s & 1;
-        x32[pb][0][w][tx] = v32[0];
-        x32[pb][1][w][tx] = v32[RCH - 1];
-        x64[pb][0][w][tx] = v64[0];
-        x64[pb][1][w][tx] = v64[RCH - 1];
-        __syncthreads();
-        const float hu32 = w > 0 ? x32[pb][1][w - 1][tx] : v32[0];
-        const float hd32 = w + 1 < NW ? x32[pb][0][w + 1][tx] : v32[RCH - 1];
-        const double hu64 = w > 0 ? x64[pb][1][w - 1][tx] : v64[0];
-        const double hd64 = w + 1 < NW ? x64[pb][0][w + 1][tx] : v64[RCH - 1];
-        if (edgeY) {
-            reg2d_substep_x<float, RCH, true>(ex, v32, hu32, hd32, x, nx, y0, ny, alpha32, r32);
-            reg2d_substep_x<double, RCH, true>(ex, v64, hu64, hd64, x, nx, y0, ny, alpha64, r64);
-        } else {
-            reg2d_substep_x<float, RCH, false>(ex, v32, hu32, hd32, x, nx, y0, ny, alpha32, r32);
-            reg2d_substep_x<double, RCH, false>(ex, v64, hu64, hd64, x, nx, y0, ny, alpha64, r64);
+#define AC_ERR_STEPS(EX_, EY_)                                                                      \
+    err_steps<EX_, EY_>(v32, v64, x, nx, y0, ny, xout, oy0, oy1, alpha32, r32, alpha64, r64,      \
+                        ksteps, x32, x64, part)
+    if (edgeY) {
+        switch (ex) {
+        case REG_X_IN: AC_ERR_STEPS(REG_X_IN, true); break;
+        case REG_X_LEFT: AC_ERR_STEPS(REG_X_LEFT, true); break;
+        case REG_X_RIGHT: AC_ERR_STEPS(REG_X_RIGHT, true); break;
+        default: AC_ERR_STEPS(REG_X_SEL, true); break;
         }
-        double acc = 0.0;
-        if (xout) {
-#pragma unroll
-            for (int q = 0; q < RCH; ++q) {
-                const int y = y0 + q;
-                const double e = (double)v32[q] - v64[q];
-                acc += (y >= oy0 && y < oy1) ? e * e : 0.0;
-            }
+    } else {
+        switch (ex) {
+        case REG_X_IN: AC_ERR_STEPS(REG_X_IN, false); break;
+        case REG_X_LEFT: AC_ERR_STEPS(REG_X_LEFT, false); break;
+        case REG_X_RIGHT: AC_ERR_STEPS(REG_X_RIGHT, false); break;
+        default: AC_ERR_STEPS(REG_X_SEL, false); break;
         }
-        acc = wave_sum(acc);
-        if (tx == 0) part[s][w] = acc;
     }
+#undef AC_ERR_STEPS
     __syncthreads();
     if ((int)threadIdx.x < ksteps) {
         double sum = 0.0;

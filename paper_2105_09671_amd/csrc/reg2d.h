@@ -122,22 +122,42 @@ __device__ __forceinline__ void reg2d_substep(T v[RCH], T hu, T hd, int x, int n
     }
 }
 
+// The fused steps of one tile for one x/y edge variant (chosen once per tile,
+// so the step loop carries no dispatch).  xb: the LDS row exchange, [2
+// parities][2 rows][NW waves][64 lanes].
+template <typename T, int RCH, int EX, bool EY>
+__device__ __forceinline__ void reg2d_steps(T (&v)[RCH], int x, int nx, int y0, int ny, T alpha, T r,
+                                            int ksteps, T *xb)
+{
+    const int tx = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int NW = blockDim.x >> 6;
+    for (int s = 0; s < ksteps; ++s) {
+        T *b = xb + (s & 1) * 2 * NW * 64;
+        b[w * 64 + tx] = v[0];
+        b[(NW + w) * 64 + tx] = v[RCH - 1];
+        __syncthreads();
+        const T hu = w > 0 ? b[(NW + w - 1) * 64 + tx] : v[0];
+        const T hd = w + 1 < NW ? b[(w + 1) * 64 + tx] : v[RCH - 1];
+        reg2d_substep<T, RCH, EX, EY>(v, hu, hd, x, nx, y0, ny, alpha, r);
+    }
+}
+
 template <typename T, int RCH, bool EY>
-__device__ __forceinline__ void reg2d_substep_x(int ex, T v[RCH], T hu, T hd, int x, int nx, int y0,
-                                                int ny, T alpha, T r)
+__device__ __forceinline__ void reg2d_steps_x(int ex, T (&v)[RCH], int x, int nx, int y0, int ny,
+                                              T alpha, T r, int ksteps, T *xb)
 {
     switch (ex) {
-    case REG_X_IN: reg2d_substep<T, RCH, REG_X_IN, EY>(v, hu, hd, x, nx, y0, ny, alpha, r); break;
-    case REG_X_LEFT: reg2d_substep<T, RCH, REG_X_LEFT, EY>(v, hu, hd, x, nx, y0, ny, alpha, r); break;
-    case REG_X_RIGHT: reg2d_substep<T, RCH, REG_X_RIGHT, EY>(v, hu, hd, x, nx, y0, ny, alpha, r); break;
-    default: reg2d_substep<T, RCH, REG_X_SEL, EY>(v, hu, hd, x, nx, y0, ny, alpha, r); break;
+    case REG_X_IN: reg2d_steps<T, RCH, REG_X_IN, EY>(v, x, nx, y0, ny, alpha, r, ksteps, xb); break;
+    case REG_X_LEFT: reg2d_steps<T, RCH, REG_X_LEFT, EY>(v, x, nx, y0, ny, alpha, r, ksteps, xb); break;
+    case REG_X_RIGHT: reg2d_steps<T, RCH, REG_X_RIGHT, EY>(v, x, nx, y0, ny, alpha, r, ksteps, xb); break;
+    default: reg2d_steps<T, RCH, REG_X_SEL, EY>(v, x, nx, y0, ny, alpha, r, ksteps, xb); break;
     }
 }
 
 // Advance tile (tile_x, tile_y) of one grid by ksteps <= halo steps (any
 // number if the tile covers the whole grid).  The workgroup has NW =
 // blockDim.x / 64 waves; the tile is 64 x NW*RCH cells including the halo.
-// xb: the LDS row exchange, [2 parities][2 rows][NW waves][64 lanes].
 template <typename T, int RCH>
 __device__ __forceinline__ void reg2d_body(const T *__restrict__ src, T *__restrict__ dst, int nx,
                                            int ny, T alpha, T r, int halo, int ksteps, int tile_x,
@@ -169,16 +189,8 @@ __device__ __forceinline__ void reg2d_body(const T *__restrict__ src, T *__restr
                                          : REG_X_IN;
     // y: a domain shorter than the tile ends inside the wave holding ny-1
     const bool edgeY = ny < LY && y0 <= ny - 1 && y0 + RCH - 1 >= ny - 1;
-    for (int s = 0; s < ksteps; ++s) {
-        T *b = xb + (s & 1) * 2 * NW * 64;
-        b[w * 64 + tx] = v[0];
-        b[(NW + w) * 64 + tx] = v[RCH - 1];
-        __syncthreads();
-        const T hu = w > 0 ? b[(NW + w - 1) * 64 + tx] : v[0];
-        const T hd = w + 1 < NW ? b[(w + 1) * 64 + tx] : v[RCH - 1];
-        if (edgeY) reg2d_substep_x<T, RCH, true>(ex, v, hu, hd, x, nx, y0, ny, alpha, r);
-        else       reg2d_substep_x<T, RCH, false>(ex, v, hu, hd, x, nx, y0, ny, alpha, r);
-    }
+    if (edgeY) reg2d_steps_x<T, RCH, true>(ex, v, x, nx, y0, ny, alpha, r, ksteps, xb);
+    else       reg2d_steps_x<T, RCH, false>(ex, v, x, nx, y0, ny, alpha, r, ksteps, xb);
     if (x >= ox0 && x < ox1) {
 #pragma unroll
         for (int q = 0; q < RCH; ++q) {
