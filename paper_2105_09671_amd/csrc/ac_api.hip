@@ -88,16 +88,16 @@ Chunks plan_chunks(int64_t nsteps, int64_t k) {
 // back to back), by depth and tile height.  Register tiles of 6 or 10 waves
 // (heights 96, 160) measured 10-25 % slower than 4, 8 or 12 and are left out.
 struct TileRate { int K, LY; double glups; };
-static const TileRate kRegF32[] = {{4, 64, 1564}, {4, 128, 1495}, {4, 192, 1536},
-                                   {5, 64, 2053}, {5, 128, 1916}, {5, 192, 2125},
-                                   {6, 64, 2345}, {6, 128, 2507}, {6, 192, 2565},
-                                   {7, 64, 2478}, {7, 128, 2608}, {7, 192, 2605},
-                                   {8, 64, 2461}, {8, 128, 2587}, {8, 192, 2553}};
-static const TileRate kRegF64[] = {{4, 64, 983}, {4, 128, 932}, {4, 192, 945},
-                                   {5, 64, 1208}, {5, 128, 1185}, {5, 192, 1224},
-                                   {6, 64, 1392}, {6, 128, 1358}, {6, 192, 1398},
-                                   {7, 64, 1389}, {7, 128, 1494}, {7, 192, 1518},
-                                   {8, 64, 1409}, {8, 128, 1555}, {8, 192, 1569}};
+static const TileRate kRegF32[] = {{4, 64, 1535}, {4, 128, 1495}, {4, 192, 1529},
+                                   {5, 64, 2129}, {5, 128, 1911}, {5, 192, 2103},
+                                   {6, 64, 2441}, {6, 128, 2259}, {6, 192, 2602},
+                                   {7, 64, 2537}, {7, 128, 2705}, {7, 192, 2783},
+                                   {8, 64, 2509}, {8, 128, 2703}, {8, 192, 2774}};
+static const TileRate kRegF64[] = {{4, 64, 974}, {4, 128, 921}, {4, 192, 918},
+                                   {5, 64, 1208}, {5, 128, 1226}, {5, 192, 1189},
+                                   {6, 64, 1390}, {6, 128, 1370}, {6, 192, 1417},
+                                   {7, 64, 1394}, {7, 128, 1527}, {7, 192, 1587},
+                                   {8, 64, 1391}, {8, 128, 1563}, {8, 192, 1613}};
 static const TileRate kInplaceF32[] = {{6, 64, 1603}, {7, 64, 1617}, {8, 64, 1645},
                                        {6, 128, 1682}, {7, 128, 1707}, {8, 128, 1732}};
 static const TileRate kInplaceF64[] = {{3, 32, 666}, {4, 32, 749}, {5, 32, 758}, {6, 32, 730},
