@@ -268,12 +268,20 @@ ac_status make_plan3d(int nx, int ny, int nz, int64_t nsteps, size_t elem, const
     }
     if (!tune || tune->tile_z <= 0) {
         // longer z segments re-stream fewer halo planes (2K per segment) but
-        // leave fewer workgroups: lengthen them only while the grid still has
-        // about eight rounds of resident workgroups (measured: 1024^3 gains
-        // 15 % at 128 planes, 256^3 loses at anything above 32)
-        const int64_t xy = (int64_t)((nx + LX - 2 * K - 1) / (LX - 2 * K)) *
-                           ((ny + LY - 2 * K - 1) / (LY - 2 * K));
-        while (LZ < 128 && xy * ((nz + 2 * LZ - 1) / (2 * LZ)) >= 32LL * dev.cus) LZ *= 2;
+        // leave fewer workgroups.  LDS tiles: lengthen them only while the grid
+        // still has about eight rounds of resident workgroups (measured: 1024^3
+        // gains 15 % at 128 planes, 256^3 loses at anything above 32).
+        // FP32 register tiles (3 workgroups per CU): while one full round
+        // remains (measured: 512^3 1446 -> 1505 GLUPS at 64 planes, 1024^3
+        // +2 % at 128; 256^3 keeps 32).  FP64 register tiles (2 per CU) keep
+        // the eight-round rule (512^3: 697 GLUPS at 32 planes, 598 at 128).
+        const int64_t xy = reg ? (int64_t)ac::reg2d_tiles_1d(nx, 64, K) * ac::reg2d_tiles_1d(ny, LY, K)
+                               : (int64_t)((nx + LX - 2 * K - 1) / (LX - 2 * K)) *
+                                     ((ny + LY - 2 * K - 1) / (LY - 2 * K));
+        const int64_t want = reg && !f64
+                                 ? (int64_t)std::max(ac::reg3d_blocks_per_cu(K, LY, elem), 1) * dev.cus
+                                 : 32LL * dev.cus;
+        while (LZ < 128 && xy * ((nz + 2 * LZ - 1) / (2 * LZ)) >= want) LZ *= 2;
     }
     ac::Tile3D t{LX, LY, LZ, K, threads};
     if (!reg && ac::stream3d_cells_per_thread(t) > 4)
