@@ -359,8 +359,12 @@ def main():
     avg_launch = sec / launches
     alg_bytes = 2 * 4 * cells * NSTEPS / plan["launches"]
     achieved = alg_bytes / avg_launch / 1e9
+    traffic = measured_traffic()
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            # the true HBM fraction: counter bytes per launch / launch time
+            "frac_meas": (round(traffic / avg_launch / 1e9 / HBM_PEAK_GBS, 4)
+                          if traffic is not None else None),
             "kernel": {4: "tile2d_reg_kernel<float>", 3: "tile2d_inplace_kernel<float>"}.get(
                 plan["kernel"], "tile2d_kernel<float,%d>" % plan["tile_x"]),
             "algorithmic_bytes_per_launch": int(alg_bytes),
