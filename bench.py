@@ -191,7 +191,7 @@ def extras(api, torch, workloads, params) -> dict:
                              "ms": round(t * 1e3, 2), "cells": b3.cells, "launch": info3}
     log("extra batch3d64_fp32", out["batch3d64_fp32"])
     del b3
-    # 64x64 FP64 phase separation, 500 steps, one LDS-resident launch
+    # 64x64 FP64 phase separation, 500 steps, one launch (the whole grid as one register tile)
     g1 = workloads.phase64()
     p1 = torch.from_numpy(g1.initial()).cuda()
     t = timed(lambda: api.step2d(p1, g1.h, g1.dt, g1.eps, 500), 5)

@@ -76,14 +76,18 @@ typedef struct {
 
 /* 2D step, 5-point stencil (section 2.1, Eq. pytorchACeq).  phi, work: nx*ny
  * elements of dtype (AC_F32 or AC_F64), 16-byte aligned.  nsteps = 0 is a
- * no-op.  Grids whose state fits one workgroup's LDS run all steps in one
- * launch; larger grids run ceil(nsteps / tb_depth) tiled launches. */
+ * no-op.  Grids up to 64 wide and 256 tall run all steps in one launch as one
+ * register tile (plan: AC_KERNEL_2D_REG with tb_depth 0); other grids whose
+ * state fits one workgroup's LDS run all steps in one launch in LDS; larger
+ * grids run ceil(nsteps / tb_depth) tiled launches. */
 ac_status ac_step_2d(void *phi, void *work, int32_t nx, int32_t ny,
                      double h, double dt, double eps, int64_t nsteps,
                      int32_t dtype, void *stream);
 
 /* As ac_step_2d with an explicit launch shape (NULL = as ac_step_2d).
- * tune->tile_x/y = -1 forces the tiled path even for small grids. */
+ * tune->tile_x/y = -1 forces the tiled path even for small grids; a tune with
+ * tb_depth or tile_y set, or a kernel other than AC_KERNEL_2D_REG, skips the
+ * whole-grid register tile. */
 ac_status ac_step_2d_tuned(void *phi, void *work, int32_t nx, int32_t ny,
                            double h, double dt, double eps, int64_t nsteps,
                            int32_t dtype, const ac_tune *tune, void *stream);
@@ -113,7 +117,7 @@ enum {
 /* What a stepping call with the same arguments launches (filled by ac_plan_*). */
 typedef struct {
     int32_t kernel;     /* AC_KERNEL_* */
-    int32_t tb_depth;   /* steps fused per launch (0 for the resident kernel) */
+    int32_t tb_depth;   /* steps fused per launch (0: all steps in one launch, whole grid) */
     int32_t tile_x, tile_y, tile_z;
     int32_t threads;    /* workgroup size */
     int64_t launches;   /* kernel launches for nsteps */

@@ -149,6 +149,24 @@ ac_status make_plan2d(int nx, int ny, int64_t nsteps, size_t elem, const ac_tune
                       const ac::DevInfo &dev, ac_plan *p) {
     std::memset(p, 0, sizeof *p);
     const bool force_tiled = tune && (tune->tile_x < 0 || tune->tile_y < 0);
+    const int want = tune ? tune->kernel : 0;
+    if (!force_tiled && nx <= 64 && ny <= ac::kRegRows * 16 &&
+        (want == 0 || want == AC_KERNEL_2D_REG) &&
+        (!tune || (!tune->tb_depth && !tune->tile_x && !tune->tile_y))) {
+        // the whole grid as one register tile (every tile edge a domain edge, no
+        // halo): all steps in one launch, phi -> work, copied back at the end
+        // (64^2 FP64, 500 steps: 0.30 ms against 0.47 ms in LDS)
+        const int nw = (ny + ac::kRegRows - 1) / ac::kRegRows;
+        p->kernel = AC_KERNEL_2D_REG;
+        p->tb_depth = 0;
+        p->tile_x = 64;
+        p->tile_y = nw * ac::kRegRows;
+        p->threads = 64 * nw;
+        p->launches = nsteps > 0 ? (nsteps + INT_MAX - 1) / INT_MAX : 0;
+        p->copy_back = (int)(p->launches & 1);
+        p->lds_bytes = (int64_t)ac::tile2d_reg_lds_bytes(p->tile_y, elem);
+        return AC_OK;
+    }
     if (!force_tiled && ac::tile2d_lds_bytes(nx, ny, elem) <= dev.lds_per_block) {
         p->kernel = AC_KERNEL_2D_RESIDENT;
         p->tb_depth = 0;
@@ -317,6 +335,23 @@ ac_status run2d(T *phi, T *work, int nx, int ny, double alpha_d, double r_d, int
             e = ac::launch_tile2d<T>(phi, phi, nx, ny, alpha, r, t, k, stream);
             if (e != hipSuccess) return hip_fail(e, "resident 2D launch");
             done += k;
+        }
+        return AC_OK;
+    }
+    if (p.kernel == AC_KERNEL_2D_REG && p.tb_depth == 0) {
+        // whole grid in one register tile (halo 0): all steps per launch
+        ac::Tile2D t{64, p.tile_y, 0, p.threads};
+        T *src = phi, *dst = work;
+        for (int64_t done = 0; done < nsteps;) {
+            const int k = (int)std::min<int64_t>(nsteps - done, INT_MAX);
+            e = ac::launch_tile2d_reg<T>(src, dst, nx, ny, alpha, r, t, k, stream);
+            if (e != hipSuccess) return hip_fail(e, "whole-grid register launch");
+            T *tmp = src; src = dst; dst = tmp;
+            done += k;
+        }
+        if (src != phi) {
+            e = hipMemcpyAsync(phi, src, (size_t)nx * ny * sizeof(T), hipMemcpyDeviceToDevice, stream);
+            if (e != hipSuccess) return hip_fail(e, "copy back");
         }
         return AC_OK;
     }

@@ -47,7 +47,10 @@ def _par(n, m):
 
 # ------------------------------------------------------------------- 2D ----
 def test_phase64_fp64_resident(api):
-    """64x64 FP64 random start, 500 steps: one LDS-resident launch."""
+    """64x64 FP64 random start, 500 steps: the whole grid as one register tile,
+    all steps in one launch."""
+    p = api.plan2d(64, 64, 500, torch.float64)
+    assert p["kernel"] == 4 and p["tb_depth"] == 0 and p["launches"] == 1, p
     g = workloads.phase64()
     phi0 = g.initial()
     got = _run2d(api, phi0, g.h, g.dt, g.eps, 500, torch.float64)
@@ -119,6 +122,22 @@ def test_2d_register_tiling_sizes(api, dtype):
         assert D.rel_linf(reg, ref) <= TOL[dtype], (ny, nx)
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_2d_whole_grid_register_tile(api, dtype):
+    """Grids up to 64 wide and 256 tall run as one register tile with every
+    step in one launch: the oracle, and bitwise the forced tiled plan."""
+    h, dt, eps = _par(64, 4)
+    for ny, nx in [(64, 64), (1, 1), (37, 50), (256, 64), (200, 3), (17, 64), (16, 1)]:
+        phi0 = inputs.random_field((ny, nx), seed=37 + nx + ny, amp=0.9).astype(NP[dtype])
+        for n in (1, 2, 33):
+            assert api.plan2d(nx, ny, n, dtype)["tb_depth"] == 0
+            got = _run2d(api, phi0, h, dt, eps, n, dtype)
+            ref = oracle.step2d(phi0.astype(np.float64), h, dt, eps, n)
+            assert D.rel_linf(got, ref) <= TOL[dtype], (ny, nx, n)
+            tiled = _run2d(api, phi0, h, dt, eps, n, dtype, tune=dict(tb_depth=3, tile_x=-1))
+            assert np.array_equal(got, tiled), (ny, nx, n)
+
+
 def test_2d_plan_kernels(api):
     from paper_2105_09671_amd import _lib as L
     # large grids default to the register kernel
@@ -126,6 +145,13 @@ def test_2d_plan_kernels(api):
         p = api.plan2d(2048, 2048, 100, dt_)
         assert p["kernel"] == 4 and p["tile_x"] == 64 and p["tile_y"] % 16 == 0, p
         assert p["threads"] == 64 * p["tile_y"] // 16
+    # grids up to 64 x 256: one register tile, all steps in one launch; wider
+    # small grids: one LDS-resident workgroup
+    assert api.plan2d(64, 256, 10, torch.float32)["tb_depth"] == 0
+    assert api.plan2d(64, 257, 10, torch.float32)["kernel"] != 4 or \
+        api.plan2d(64, 257, 10, torch.float32)["tb_depth"] > 0
+    assert api.plan2d(100, 60, 10, torch.float32)["kernel"] == 0
+    assert api.plan2d(50, 50, 10, torch.float32, dict(tb_depth=3))["kernel"] == 0
     # 64-wide tiles whose height is not whole 16-row waves fall back to LDS
     assert api.plan2d(2048, 2048, 100, torch.float32, dict(tb_depth=4, tile_y=40))["kernel"] == 3
     with pytest.raises(L.AcError):
