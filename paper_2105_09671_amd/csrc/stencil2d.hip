@@ -1,6 +1,8 @@
-// 2D Allen-Cahn stencil with temporal blocking in LDS (gfx950, wave64).
+// 2D Allen-Cahn stencil with temporal blocking (gfx950, wave64): the register
+// tile kernel (reg2d.h; the default plan) and the LDS tile kernels described
+// here (two LDS buffers, or one updated in place; tile2d.h).
 //
-// One workgroup owns an output tile of (LX - 2*halo) x (LY - 2*halo) cells.
+// LDS tiles.  One workgroup owns an output tile of (LX - 2*halo) x (LY - 2*halo) cells.
 // It loads the tile plus a `halo`-wide ring from HBM once, then advances the
 // loaded region `ksteps` time steps inside LDS, ping-ponging between two LDS
 // buffers, and finally stores the output tile.  After sub-step s only the

@@ -21,6 +21,12 @@
 //
 // LDS holds two sets (even/odd iteration) of K planes of LX*LY values so one
 // barrier per iteration separates producers from consumers.
+//
+// This file holds two kernels of that scheme: stream3d_kernel (stream3d.h),
+// whose planes live in LDS, and reg3d_kernel (reg3d.h), whose planes live in
+// registers with 64-wide tiles (x neighbours by cross-lane shifts, y edge
+// rows through LDS).  The plan takes the register kernel for grids that give
+// it enough workgroups and the LDS kernel for smaller ones.
 #include "reg3d.h"
 #include "stream3d.h"
 
