@@ -29,6 +29,8 @@
 // the result is bitwise that of the LDS 3D kernel.
 #pragma once
 
+#include <type_traits>
+
 #include "reg2d.h"
 
 namespace ac {
@@ -95,7 +97,10 @@ __device__ __forceinline__ void reg3d_stream(const T *__restrict__ src, T *__res
         for (int q = 0; q < RCH; ++q) pf[d][q] = src[zo + gxy[q]];
     }
     const int row = NW * 64;                            // one exchanged row of all waves
-    for (int t = t0; t <= t1; ++t) {
+    // one pass over plane t; ZC: some level of this iteration may sit on a z
+    // edge (then each level tests its plane), else no level does
+    auto iteration = [&](int t, auto zc) {
+        constexpr bool ZC = decltype(zc)::value;
         T *b = xb + (size_t)(t & 1) * K * 2 * row;
         // publish the wave's edge rows of every level (level s: plane t-1-s)
 #pragma unroll
@@ -122,14 +127,19 @@ __device__ __forceinline__ void reg3d_stream(const T *__restrict__ src, T *__res
             const T hu = w > 0 ? b[(2 * (s - 1) + 1) * row + (w - 1) * 64 + tx] : cur[s - 1][0];
             const T hd = w + 1 < NW ? b[(2 * (s - 1)) * row + (w + 1) * 64 + tx]
                                     : cur[s - 1][RCH - 1];
-            const bool zlo = p == 0, zhi = p == nz - 1;
             T res[RCH];
-            if (zlo || zhi)
-                reg3d_level<T, RCH, EX, EY, true>(cur[s - 1], prv[s - 1], nw, hu, hd, res, x, nx, y0,
-                                                  ny, zlo, zhi, alpha, r);
-            else
+            if constexpr (ZC) {
+                const bool zlo = p == 0, zhi = p == nz - 1;
+                if (zlo || zhi)
+                    reg3d_level<T, RCH, EX, EY, true>(cur[s - 1], prv[s - 1], nw, hu, hd, res, x,
+                                                      nx, y0, ny, zlo, zhi, alpha, r);
+                else
+                    reg3d_level<T, RCH, EX, EY, false>(cur[s - 1], prv[s - 1], nw, hu, hd, res, x,
+                                                       nx, y0, ny, false, false, alpha, r);
+            } else {
                 reg3d_level<T, RCH, EX, EY, false>(cur[s - 1], prv[s - 1], nw, hu, hd, res, x, nx,
                                                    y0, ny, false, false, alpha, r);
+            }
 #pragma unroll
             for (int q = 0; q < RCH; ++q) {
                 prv[s - 1][q] = cur[s - 1][q];
@@ -145,7 +155,23 @@ __device__ __forceinline__ void reg3d_stream(const T *__restrict__ src, T *__res
                 if (y >= oy0 && y < oy1) dst[(size_t)pout * pstride + (size_t)y * nx + x] = nw[q];
             }
         }
+    };
+    // iterations t in [K+1, nz-1] advance only planes 1 .. nz-2: no z edge, so
+    // the middle loop carries no branch; the few iterations before and after
+    // it test each level's plane
+    const int fa = max(t0, K + 1), fb = min(t1, nz - 1);
+    const int e1 = min(t1, fa - 1);
+    for (int t = t0; t <= e1; ++t) iteration(t, std::true_type{});
+    int t = fa;
+    // three iterations per trip: the (prv, cur, incoming) rotation of every
+    // level then returns to the same registers, so it costs no moves
+    for (; t + 2 <= fb; t += 3) {
+        iteration(t, std::false_type{});
+        iteration(t + 1, std::false_type{});
+        iteration(t + 2, std::false_type{});
     }
+    for (; t <= fb; ++t) iteration(t, std::false_type{});
+    for (int t = max(fb + 1, fa); t <= t1; ++t) iteration(t, std::true_type{});
 }
 
 template <typename T, int K, int RCH, bool EY>
