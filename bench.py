@@ -365,24 +365,31 @@ def main():
             # the true HBM fraction: counter bytes per launch / launch time
             "frac_meas": (round(traffic / avg_launch / 1e9 / HBM_PEAK_GBS, 4)
                           if traffic is not None else None),
-            "kernel": {4: "tile2d_reg_kernel<float>", 3: "tile2d_inplace_kernel<float>"}.get(
+            "kernel": {4: "tile2d_reg_kernel<float>", 6: "tile2d_regw_kernel<float>",
+                       3: "tile2d_inplace_kernel<float>"}.get(
                 plan["kernel"], "tile2d_kernel<float,%d>" % plan["tile_x"]),
             "algorithmic_bytes_per_launch": int(alg_bytes),
             "avg_launch_us": round(avg_launch * 1e6, 3), "launches_timed": launches}
 
     # the same launches against the instruction-issue bound of the register
-    # kernel: 9 VALU instructions per computed cell (halo recomputation
-    # included), 256 CUs x 64 lanes x 2.4 GHz with packed FP32 off
+    # kernels: 9 VALU instructions per computed cell in 64-wide tiles (two
+    # cross-lane shifts, one folded into an add), 8 in 128-wide tiles (one
+    # shift, folded), halo recomputation included; 256 CUs x 64 lanes x 2.4 GHz
+    # with packed FP32 off.  Register tiles sit flush against the domain edges.
     roof_alu = None
-    if plan["kernel"] == 4:
+    vpc = {4: 9, 6: 8}.get(plan["kernel"])
+    if vpc:
         K, LX, LY = plan["tb_depth"], plan["tile_x"], plan["tile_y"]
-        tiles = -(-g.nx // (LX - 2 * K)) * -(-g.ny // (LY - 2 * K))
+
+        def flush_tiles(n, L):
+            return 1 if n <= L else 1 + -(-(n - L) // (L - 2 * K))
+        tiles = flush_tiles(g.nx, LX) * flush_tiles(g.ny, LY)
         computed = tiles * LX * LY * NSTEPS / plan["launches"]
-        peak = 256 * 64 * 2.4e9 / 9 / 1e9
+        peak = 256 * 64 * 2.4e9 / vpc / 1e9
         ach = computed / avg_launch / 1e9
         roof_alu = {"bound": "alu", "achieved": round(ach, 1), "peak": round(peak, 1),
                     "unit": "G computed cell-updates/s", "frac": round(ach / peak, 4),
-                    "valu_per_cell": 9, "useful_fraction": round(cells / (tiles * LX * LY), 4)}
+                    "valu_per_cell": vpc, "useful_fraction": round(cells / (tiles * LX * LY), 4)}
 
     # correctness check of the timed workload: one fresh solve, radius vs the law
     phi.copy_(phi_init)

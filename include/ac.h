@@ -110,8 +110,11 @@ enum {
     AC_KERNEL_2D_INPLACE = 3,  /* 64-wide LDS tiles updated in place, tb_depth steps per launch */
     AC_KERNEL_2D_REG = 4,      /* 64-wide tiles held in registers (16 rows per wave), x
                                 * neighbours by cross-lane shifts, tb_depth steps per launch */
-    AC_KERNEL_3D_REG = 5       /* z-streamed 64-wide tiles held in registers (4 rows per
+    AC_KERNEL_3D_REG = 5,      /* z-streamed 64-wide tiles held in registers (4 rows per
                                 * wave), tb_depth 1..4 levels per launch */
+    AC_KERNEL_2D_REGW = 6      /* 128-wide tiles held in registers, two adjacent columns
+                                * per lane (8 rows per wave), tb_depth steps per launch;
+                                * needs nx >= 128 */
 };
 
 /* What a stepping call with the same arguments launches (filled by ac_plan_*). */

@@ -62,7 +62,8 @@ class AcBatchInfo(ctypes.Structure):
 AC_TUNE_2D, AC_TUNE_3D, AC_TUNE_BATCHED = 2, 3, 4
 
 KERNEL_NAMES = {0: "tile2d_kernel (resident)", 1: "tile2d_kernel", 2: "stream3d_kernel",
-                3: "tile2d_inplace_kernel", 4: "tile2d_reg_kernel", 5: "reg3d_kernel"}
+                3: "tile2d_inplace_kernel", 4: "tile2d_reg_kernel", 5: "reg3d_kernel",
+                6: "tile2d_regw_kernel"}
 
 
 class AcError(RuntimeError):

@@ -83,25 +83,42 @@ Chunks plan_chunks(int64_t nsteps, int64_t k) {
 // A plan fixes the kernel, its launch shape and the launch sequence of one
 // call.  Built on the host from the device limits; executing it makes no other
 // decision, so ac_plan_* reports exactly what ac_step_* will launch.
-// Steady-state throughput of the tiled 2D kernels on MI355X (GLUPS on a
-// 16384^2 grid in FP32, 16384 x 8192 in FP64, where every CU runs many tiles
-// back to back), by depth and tile height.  Register tiles of 6 or 10 waves
-// (heights 96, 160) measured 10-25 % slower than 4, 8 or 12 and are left out.
-struct TileRate { int K, LY; double glups; };
-static const TileRate kRegF32[] = {{4, 64, 1535}, {4, 128, 1495}, {4, 192, 1529},
-                                   {5, 64, 2129}, {5, 128, 1911}, {5, 192, 2103},
-                                   {6, 64, 2441}, {6, 128, 2259}, {6, 192, 2602},
-                                   {7, 64, 2537}, {7, 128, 2705}, {7, 192, 2783},
-                                   {8, 64, 2509}, {8, 128, 2703}, {8, 192, 2774}};
-static const TileRate kRegF64[] = {{4, 64, 974}, {4, 128, 921}, {4, 192, 918},
-                                   {5, 64, 1208}, {5, 128, 1226}, {5, 192, 1189},
-                                   {6, 64, 1390}, {6, 128, 1370}, {6, 192, 1417},
-                                   {7, 64, 1394}, {7, 128, 1527}, {7, 192, 1587},
-                                   {8, 64, 1391}, {8, 128, 1563}, {8, 192, 1613}};
-static const TileRate kInplaceF32[] = {{6, 64, 1603}, {7, 64, 1617}, {8, 64, 1645},
-                                       {6, 128, 1682}, {7, 128, 1707}, {8, 128, 1732}};
-static const TileRate kInplaceF64[] = {{3, 32, 666}, {4, 32, 749}, {5, 32, 758}, {6, 32, 730},
-                                       {3, 64, 661}, {4, 64, 719}, {5, 64, 731}, {6, 64, 725}};
+// Throughput of the tiled 2D kernels on MI355X by depth and tile height, at
+// two loads per CU.  `steady`: GLUPS on a 16384^2 grid in FP32, 16384 x 8192
+// in FP64, where every CU streams many tiles back to back.  `round`: GLUPS on
+// 2048^2, where about one round of tiles is resident at once, so the tiles'
+// loads, steps and stores overlap little and the launch lasts about one
+// tile's whole life.  Register tiles of 6 or 10 waves (64 x 96, 64 x 160)
+// measured 10-25 % slower than 4, 8 or 12 and are left out.
+struct TileRate { int K, LY; double round, steady; };
+static const TileRate kRegF32[] = {
+    {5, 64, 1786, 2133}, {5, 128, 1824, 1932}, {5, 192, 1777, 2127},
+    {6, 64, 1673, 2480}, {6, 128, 1995, 2283}, {6, 192, 1956, 2555},
+    {7, 64, 1828, 2681}, {7, 128, 2075, 2679}, {7, 192, 2051, 2963},
+    {8, 64, 1696, 2506}, {8, 128, 1807, 2902}, {8, 192, 1670, 3051}};
+static const TileRate kRegF64[] = {
+    {5, 64, 1048, 1209}, {5, 128, 1052, 1232}, {5, 192, 982, 1191},
+    {6, 64, 1136, 1444}, {6, 128, 1152, 1363}, {6, 192, 1063, 1410},
+    {7, 64, 1190, 1442}, {7, 128, 1212, 1568}, {7, 192, 1119, 1625},
+    {8, 64, 1152, 1437}, {8, 128, 1067, 1629}, {8, 192, 955, 1665}};
+// 128-wide register tiles (two columns per lane)
+static const TileRate kRegWF32[] = {
+    {5, 32, 1566, 2254}, {5, 64, 1770, 2360}, {5, 128, 1430, 2419},
+    {6, 32, 1589, 2414}, {6, 64, 1947, 2970}, {6, 128, 1620, 3103},
+    {7, 32, 1687, 2326}, {7, 64, 1995, 2910}, {7, 128, 1669, 3230},
+    {8, 32, 1474, 2073}, {8, 64, 1789, 3054}, {8, 128, 1801, 3455}};
+static const TileRate kRegWF64[] = {
+    {5, 32, 954, 1251}, {5, 64, 1000, 1344}, {5, 128, 708, 1059},
+    {6, 32, 1109, 1337}, {6, 64, 1157, 1623}, {6, 128, 841, 1226},
+    {7, 32, 1141, 1276}, {7, 64, 1269, 1642}, {7, 128, 824, 1191},
+    {8, 32, 1088, 1241}, {8, 64, 1229, 1698}, {8, 128, 985, 1469}};
+// in place in LDS (steady state only)
+static const TileRate kInplaceF32[] = {{6, 64, 1603, 1603}, {7, 64, 1617, 1617},
+                                       {8, 64, 1645, 1645}, {6, 128, 1682, 1682},
+                                       {7, 128, 1707, 1707}, {8, 128, 1732, 1732}};
+static const TileRate kInplaceF64[] = {{3, 32, 666, 666}, {4, 32, 749, 749}, {5, 32, 758, 758},
+                                       {6, 32, 730, 730}, {3, 64, 661, 661}, {4, 64, 719, 719},
+                                       {5, 64, 731, 731}, {6, 64, 725, 725}};
 
 // 3D: the register kernel is the default from half a round of resident
 // workgroups on (measured on MI355X with flush tiles: 256^3 FP32, 0.57 rounds,
@@ -109,33 +126,50 @@ static const TileRate kInplaceF64[] = {{3, 32, 666}, {4, 32, 749}, {5, 32, 758},
 // 509; 512^3 FP32 1254 against 817, 1024^3 1288 against 970)
 static const int64_t kReg3dMinRoundsNum = 1, kReg3dMinRoundsDen = 2;
 
-// Predicted time of a launch ~ the tiles of the busiest CU (ceil(tiles / CUs);
-// the dispatcher spreads workgroups evenly) x the time of one tile at the
-// steady per-CU rate measured for that pair.  A grid whose tile count just
+// Predicted time of a launch ~ a start-up + the tiles of the busiest CU
+// (ceil(tiles / CUs); the dispatcher spreads workgroups evenly) x one tile's
+// time at the streaming rate measured for that pair.  The start-up (tile
+// loads and stores that no other tile's steps overlap) is what the 2048^2
+// rate lacks against the streaming one, at 2048^2's busiest-CU load.  A grid whose tile count just
 // exceeds a multiple of the CU count gives some CUs one tile more, so the
 // depth and tile height are chosen per grid.  (Charging a partial round as a
 // full round of resident slots, as an earlier model did, preferred tall tiles
 // on 2048^2 that measure 5 % slower.)
-void choose_tile2d(int nx, int ny, size_t elem, bool reg, const ac::DevInfo &dev, int *K, int *LY) {
+double choose_tile2d(int nx, int ny, size_t elem, int kernel, const ac::DevInfo &dev, int *K,
+                     int *LY) {
     const bool f64 = elem == 8;
-    const TileRate *tab = reg ? (f64 ? kRegF64 : kRegF32) : (f64 ? kInplaceF64 : kInplaceF32);
-    const int n = reg ? (f64 ? (int)(sizeof kRegF64 / sizeof *kRegF64)
-                             : (int)(sizeof kRegF32 / sizeof *kRegF32))
-                      : (f64 ? (int)(sizeof kInplaceF64 / sizeof *kInplaceF64)
-                             : (int)(sizeof kInplaceF32 / sizeof *kInplaceF32));
+    const bool reg = kernel == AC_KERNEL_2D_REG, wide = kernel == AC_KERNEL_2D_REGW;
+    const int LX = wide ? 128 : 64;
+    struct Tab {
+        const TileRate *p;
+        int n;
+    };
+    const auto of = [](const auto &t) { return Tab{t, (int)(sizeof t / sizeof *t)}; };
+    const Tab tb = wide ? (f64 ? of(kRegWF64) : of(kRegWF32))
+                   : reg ? (f64 ? of(kRegF64) : of(kRegF32))
+                         : (f64 ? of(kInplaceF64) : of(kInplaceF32));
+    const TileRate *tab = tb.p;
+    const int n = tb.n;
     const int64_t cus = std::max(dev.cus, 1);
     double best = -1.0;
     *K = tab[0].K;
     *LY = tab[0].LY;
     for (int i = 0; i < n; ++i) {
         const int k = tab[i].K, ly = tab[i].LY;
-        const int OX = 64 - 2 * k, OY = ly - 2 * k;
-        // register tiles sit flush against the domain edges (reg2d.h)
-        const int64_t tiles = reg ? (int64_t)ac::reg2d_tiles_1d(nx, 64, k) * ac::reg2d_tiles_1d(ny, ly, k)
-                                  : (int64_t)((nx + OX - 1) / OX) * ((ny + OY - 1) / OY);
+        const int OX = LX - 2 * k, OY = ly - 2 * k;
         if ((ny + OY - 1) / OY > 65535) continue;
-        const int64_t busiest = (tiles + cus - 1) / cus;
-        const double t = (double)busiest * OX * OY * k / (tab[i].glups / (double)cus);
+        const auto busiest_of = [&](int gx, int gy) {
+            // register tiles sit flush against the domain edges (reg2d.h)
+            const int64_t tiles = reg || wide ? (int64_t)ac::reg2d_tiles_1d(gx, LX, k) * ac::reg2d_tiles_1d(gy, ly, k)
+                                              : (int64_t)((gx + OX - 1) / OX) * ((gy + OY - 1) / OY);
+            return (tiles + cus - 1) / cus;
+        };
+        // a launch = a start-up the tiles cannot hide + the busiest CU's tiles
+        // at the streaming rate; the start-up is what makes 2048^2 slower
+        const int64_t busiest = busiest_of(nx, ny), n1 = busiest_of(2048, 2048);
+        const double tile = (double)OX * OY * k * cus;          // / rate = one tile's time
+        const double startup = std::max(0.0, (double)n1 * (tile / tab[i].round - tile / tab[i].steady));
+        const double t = startup + (double)busiest * tile / tab[i].steady;
         const double rate = (double)nx * ny * k / t;
         if (rate > best) {
             best = rate;
@@ -143,6 +177,7 @@ void choose_tile2d(int nx, int ny, size_t elem, bool reg, const ac::DevInfo &dev
             *LY = ly;
         }
     }
+    return best;
 }
 
 ac_status make_plan2d(int nx, int ny, int64_t nsteps, size_t elem, const ac_tune *tune,
@@ -177,7 +212,7 @@ ac_status make_plan2d(int nx, int ny, int64_t nsteps, size_t elem, const ac_tune
         p->lds_bytes = (int64_t)ac::tile2d_lds_bytes(nx, ny, elem);
         return AC_OK;
     }
-    int K = 0, LX = 64, LY = 0, kern = 0;
+    int K = 0, LX = 0, LY = 0, kern = 0;
     if (tune) {
         K = tune->tb_depth;
         if (tune->tile_x > 0) LX = tune->tile_x;
@@ -185,13 +220,29 @@ ac_status make_plan2d(int nx, int ny, int64_t nsteps, size_t elem, const ac_tune
         kern = tune->kernel;
     }
     if (kern != 0 && kern != AC_KERNEL_2D_TILED && kern != AC_KERNEL_2D_INPLACE &&
-        kern != AC_KERNEL_2D_REG)
+        kern != AC_KERNEL_2D_REG && kern != AC_KERNEL_2D_REGW)
         return fail(AC_ERR_UNSUPPORTED, "kernel %d is not a tiled 2D kernel", kern);
+    if (kern == AC_KERNEL_2D_REGW && LX == 0) LX = 128;
+    if (LX == 0) {
+        // default: the register tile, 128 wide where the grid is and the
+        // predicted time is shorter (every shape free), else 64 wide
+        LX = 64;
+        int k1, l1, k2, l2;
+        if (kern == 0 && !K && !LY && nx >= 128 &&
+            choose_tile2d(nx, ny, elem, AC_KERNEL_2D_REGW, dev, &k2, &l2) >
+                choose_tile2d(nx, ny, elem, AC_KERNEL_2D_REG, dev, &k1, &l1)) {
+            LX = 128;
+            kern = AC_KERNEL_2D_REGW;
+        }
+    }
     if (!K || !LY) {
         // default: the (depth, tile height) with the best predicted time on
         // this grid, for the register kernel unless another one is asked for
         int dK = 0, dLY = 0;
-        choose_tile2d(nx, ny, elem, kern == 0 || kern == AC_KERNEL_2D_REG, dev, &dK, &dLY);
+        const int kind = kern == AC_KERNEL_2D_REGW             ? AC_KERNEL_2D_REGW
+                         : kern == 0 || kern == AC_KERNEL_2D_REG ? AC_KERNEL_2D_REG
+                                                                 : AC_KERNEL_2D_INPLACE;
+        choose_tile2d(nx, ny, elem, kind, dev, &dK, &dLY);
         if (!K) K = dK;
         if (!LY) LY = dLY;
     }
@@ -200,18 +251,25 @@ ac_status make_plan2d(int nx, int ny, int64_t nsteps, size_t elem, const ac_tune
         return fail(AC_ERR_UNSUPPORTED, "tile %dx%d too small/large for depth %d", LX, LY, K);
     const int rch = ac::rows_per_chunk(elem);
     // 64-wide tiles of whole 16-row wave blocks (at most 16 waves) run from
-    // registers; other 64-wide tiles of at most 16 row chunks in place in LDS
+    // registers; other 64-wide tiles of at most 16 row chunks in place in LDS;
+    // 128-wide tiles of whole 8-row wave blocks from registers, two columns
+    // per lane, on grids at least 128 wide
     const bool reg_ok = LX == 64 && LY % ac::kRegRows == 0 && LY / ac::kRegRows <= 16;
+    const bool regw_ok = LX == 128 && nx >= 128 && LY % ac::kRegWRows == 0 &&
+                         LY / ac::kRegWRows <= 16;
     const bool inplace_ok = LX == 64 && (LY + rch - 1) / rch <= 16;
     int kernel = AC_KERNEL_2D_TILED;
-    if (kern == AC_KERNEL_2D_REG || kern == AC_KERNEL_2D_INPLACE) {
-        if (!(kern == AC_KERNEL_2D_REG ? reg_ok : inplace_ok))
-            return fail(AC_ERR_UNSUPPORTED, "tile %dx%d does not fit kernel %d", LX, LY, kern);
+    if (kern == AC_KERNEL_2D_REG || kern == AC_KERNEL_2D_INPLACE || kern == AC_KERNEL_2D_REGW) {
+        const bool ok = kern == AC_KERNEL_2D_REG ? reg_ok : kern == AC_KERNEL_2D_REGW ? regw_ok : inplace_ok;
+        if (!ok)
+            return fail(AC_ERR_UNSUPPORTED, "tile %dx%d does not fit kernel %d on a %dx%d grid", LX,
+                        LY, kern, nx, ny);
         kernel = kern;
     } else if (kern == 0) {
         kernel = reg_ok ? AC_KERNEL_2D_REG : inplace_ok ? AC_KERNEL_2D_INPLACE : AC_KERNEL_2D_TILED;
     }
-    const size_t lds = kernel == AC_KERNEL_2D_REG ? ac::tile2d_reg_lds_bytes(LY, elem)
+    const size_t lds = kernel == AC_KERNEL_2D_REG      ? ac::tile2d_reg_lds_bytes(LY, elem)
+                       : kernel == AC_KERNEL_2D_REGW    ? ac::tile2d_regw_lds_bytes(LY, elem)
                        : kernel == AC_KERNEL_2D_INPLACE ? ac::tile2d_inplace_lds_bytes(LY, elem)
                                                         : ac::tile2d_lds_bytes(LX, LY, elem);
     if (lds > dev.lds_per_block)
@@ -224,9 +282,11 @@ ac_status make_plan2d(int nx, int ny, int64_t nsteps, size_t elem, const ac_tune
     p->tb_depth = K;
     p->tile_x = LX;
     p->tile_y = LY;
-    // register kernel: one wave per 16 rows; in place: one wave per row chunk
+    // register kernels: one wave per 16 (64 wide) or 8 (128 wide) rows; in
+    // place: one wave per row chunk
     // of the tile; two buffers: per row chunk of the widest sub-step, at most 16
     p->threads = kernel == AC_KERNEL_2D_REG       ? 64 * (LY / ac::kRegRows)
+                 : kernel == AC_KERNEL_2D_REGW    ? 64 * (LY / ac::kRegWRows)
                  : kernel == AC_KERNEL_2D_INPLACE ? ac::tile2d_inplace_threads(LY, elem)
                                                   : 64 * std::max(1, std::min(16, (LY - 2 + rch - 1) / rch));
     p->launches = nsteps > 0 ? c.n : 0;
@@ -361,6 +421,8 @@ ac_status run2d(T *phi, T *work, int nx, int ny, double alpha_d, double r_d, int
     for (int64_t i = 0; i < c.n; ++i) {
         const int k = (int)(c.base + (i < c.rem ? 1 : 0));
         e = p.kernel == AC_KERNEL_2D_REG ? ac::launch_tile2d_reg<T>(src, dst, nx, ny, alpha, r, t, k, stream)
+            : p.kernel == AC_KERNEL_2D_REGW
+                ? ac::launch_tile2d_regw<T>(src, dst, nx, ny, alpha, r, t, k, stream)
             : p.kernel == AC_KERNEL_2D_INPLACE
                 ? ac::launch_tile2d_inplace<T>(src, dst, nx, ny, alpha, r, t, k, stream)
                 : ac::launch_tile2d<T>(src, dst, nx, ny, alpha, r, t, k, stream);

@@ -77,6 +77,16 @@ inline size_t tile2d_reg_lds_bytes(int LY, size_t elem) {
     return (size_t)4 * (LY / kRegRows) * 64 * elem;
 }
 
+// register tiles two columns wide per lane (LX = 128, kRegWRows rows per wave,
+// LY / kRegWRows waves of at most 16; nx >= 128)
+constexpr int kRegWRows = 8;
+template <typename T>
+hipError_t launch_tile2d_regw(const T *src, T *dst, int nx, int ny, T alpha, T r, const Tile2D &t,
+                              int ksteps, hipStream_t stream);
+inline size_t tile2d_regw_lds_bytes(int LY, size_t elem) {
+    return (size_t)8 * (LY / kRegWRows) * 64 * elem;
+}
+
 // 3D z-streaming kernel with K time levels pipelined along z.
 struct Tile3D {
     int LX, LY, LZ, K, threads;

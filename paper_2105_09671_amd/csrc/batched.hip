@@ -480,6 +480,8 @@ ac_status build_plan(Plan &p, const ac_instance2d *inst, int32_t n, int64_t nste
     ac_plan tp;
     ac_status s = make_plan2d(4096, 4096, nsteps, elem, &t, dev, &tp);
     if (s != AC_OK) return s;
+    if (tp.kernel == AC_KERNEL_2D_REGW)
+        return fail(AC_ERR_UNSUPPORTED, "batches run 64-wide tiles (kernel %d is 128 wide)", tp.kernel);
     const int LX = tp.tile_x, LY = tp.tile_y, K = tp.tb_depth;
     const int OX = LX - 2 * K, OY = LY - 2 * K;
     std::vector<BatchInst> hi(n);

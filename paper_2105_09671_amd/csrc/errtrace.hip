@@ -89,8 +89,15 @@ __device__ __forceinline__ void err_steps(float (&v32)[ERR_ROWS], double (&v64)[
         const float hd32 = w + 1 < NW ? x32[pb][0][w + 1][tx] : v32[RCH - 1];
         const double hu64 = w > 0 ? x64[pb][1][w - 1][tx] : v64[0];
         const double hd64 = w + 1 < NW ? x64[pb][0][w + 1][tx] : v64[RCH - 1];
-        reg2d_substep<float, RCH, EX, EY>(v32, hu32, hd32, x, nx, y0, ny, alpha32, r32);
-        reg2d_substep<double, RCH, EX, EY>(v64, hu64, hd64, x, nx, y0, ny, alpha64, r64);
+        float n32[RCH];
+        double n64[RCH];
+        reg2d_substep<float, RCH, EX, EY>(v32, n32, hu32, hd32, x, nx, y0, ny, alpha32, r32);
+        reg2d_substep<double, RCH, EX, EY>(v64, n64, hu64, hd64, x, nx, y0, ny, alpha64, r64);
+#pragma unroll
+        for (int q = 0; q < RCH; ++q) {
+            v32[q] = n32[q];
+            v64[q] = n64[q];
+        }
         double acc = 0.0;
         if (xout) {
 #pragma unroll

@@ -97,49 +97,77 @@ __host__ __device__ inline void reg2d_tile_span(int i, int nt, int n, int L, int
 // x = nx-1, or the domain is narrower than the tile (selects).
 enum { REG_X_IN = 0, REG_X_LEFT = 1, REG_X_RIGHT = 2, REG_X_SEL = 3 };
 
-// One step of a wave's RCH rows, in place.  hu / hd: the rows just above and
+// Row q of one step of a wave's RCH rows, from `in` to `out` (distinct
+// registers, so rows can go in any order).  hu / hd: the rows just above and
 // below the wave's rows (old values).  x: this lane's column; y0: the wave's
 // first row.  EY: the domain ends inside the wave's rows at y = ny-1.
 template <typename T, int RCH, int EX, bool EY>
-__device__ __forceinline__ void reg2d_substep(T v[RCH], T hu, T hd, int x, int nx, int y0, int ny,
-                                              T alpha, T r)
+__device__ __forceinline__ void reg2d_row(int q, const T (&in)[RCH], T (&out)[RCH], T hu, T hd,
+                                          int x, int nx, int y0, int ny, T alpha, T r)
 {
-    const bool atL = EX == REG_X_SEL && x == 0, atR = EX == REG_X_SEL && x == nx - 1;
-    T prev = hu;
-#pragma unroll
-    for (int q = 0; q < RCH; ++q) {
-        const T c = v[q];
-        T up = prev, dn = q + 1 < RCH ? v[q + 1] : hd;
-        T l = EX == REG_X_LEFT ? wave_shift_keep<kDppWaveShr1>(c) : wave_shift<kDppWaveShr1>(c);
-        T rr = EX == REG_X_RIGHT ? wave_shift_keep<kDppWaveShl1>(c) : wave_shift<kDppWaveShl1>(c);
-        if (EX == REG_X_SEL) {
-            l = atL ? c : l;
-            rr = atR ? c : rr;
-        }
-        if (EY) dn = y0 + q == ny - 1 ? c : dn;
-        prev = c;
-        v[q] = update2d<T>(c, l, rr, up, dn, alpha, r);
+    const T c = in[q];
+    const T up = q > 0 ? in[q - 1] : hu;
+    T dn = q + 1 < RCH ? in[q + 1] : hd;
+    T l = EX == REG_X_LEFT ? wave_shift_keep<kDppWaveShr1>(c) : wave_shift<kDppWaveShr1>(c);
+    T rr = EX == REG_X_RIGHT ? wave_shift_keep<kDppWaveShl1>(c) : wave_shift<kDppWaveShl1>(c);
+    if (EX == REG_X_SEL) {
+        l = x == 0 ? c : l;
+        rr = x == nx - 1 ? c : rr;
     }
+    if (EY) dn = y0 + q == ny - 1 ? c : dn;
+    out[q] = update2d<T>(c, l, rr, up, dn, alpha, r);
 }
 
-// The fused steps of one tile for one x/y edge variant (chosen once per tile,
-// so the step loop carries no dispatch).  xb: the LDS row exchange, [2
-// parities][2 rows][NW waves][64 lanes].
+// One step of all RCH rows of a wave, top to bottom.
 template <typename T, int RCH, int EX, bool EY>
-__device__ __forceinline__ void reg2d_steps(T (&v)[RCH], int x, int nx, int y0, int ny, T alpha, T r,
-                                            int ksteps, T *xb)
+__device__ __forceinline__ void reg2d_substep(const T (&in)[RCH], T (&out)[RCH], T hu, T hd, int x,
+                                              int nx, int y0, int ny, T alpha, T r)
+{
+#pragma unroll
+    for (int q = 0; q < RCH; ++q) reg2d_row<T, RCH, EX, EY>(q, in, out, hu, hd, x, nx, y0, ny, alpha, r);
+}
+
+// One fused step of a tile: publish the wave's first and last row to the LDS
+// row exchange xb ([2 parities][2 rows][NW waves][64 lanes], parity s & 1),
+// meet at the barrier, read the neighbours' rows, step `in` into `out`.
+template <typename T, int RCH, int EX, bool EY>
+__device__ __forceinline__ void reg2d_step(const T (&in)[RCH], T (&out)[RCH], int s, int x, int nx,
+                                           int y0, int ny, T alpha, T r, T *xb)
 {
     const int tx = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int NW = blockDim.x >> 6;
-    for (int s = 0; s < ksteps; ++s) {
-        T *b = xb + (s & 1) * 2 * NW * 64;
-        b[w * 64 + tx] = v[0];
-        b[(NW + w) * 64 + tx] = v[RCH - 1];
-        __syncthreads();
-        const T hu = w > 0 ? b[(NW + w - 1) * 64 + tx] : v[0];
-        const T hd = w + 1 < NW ? b[(w + 1) * 64 + tx] : v[RCH - 1];
-        reg2d_substep<T, RCH, EX, EY>(v, hu, hd, x, nx, y0, ny, alpha, r);
+    T *b = xb + (s & 1) * 2 * NW * 64;
+    b[w * 64 + tx] = in[0];
+    b[(NW + w) * 64 + tx] = in[RCH - 1];
+    __syncthreads();
+    const T hu = w > 0 ? b[(NW + w - 1) * 64 + tx] : in[0];
+    const T hd = w + 1 < NW ? b[(w + 1) * 64 + tx] : in[RCH - 1];
+    reg2d_substep<T, RCH, EX, EY>(in, out, hu, hd, x, nx, y0, ny, alpha, r);
+}
+
+// The fused steps of one tile for one x/y edge variant (chosen once per tile,
+// so the step loop carries no dispatch).  FP32 takes two steps per trip, v ->
+// u -> v: the two register sets alternate and no value is moved.  FP64 steps
+// through one spare set and copies back, since a second full set of 16 double
+// rows would not fit the 128 VGPRs a 1024-thread workgroup allows.  xb: the
+// LDS row exchange (reg2d_step).
+template <typename T, int RCH, int EX, bool EY>
+__device__ __forceinline__ void reg2d_steps(T (&v)[RCH], int x, int nx, int y0, int ny, T alpha, T r,
+                                            int ksteps, T *xb)
+{
+    T u[RCH];
+    int s = 0;
+    if constexpr (sizeof(T) == 4) {
+        for (; s + 1 < ksteps; s += 2) {
+            reg2d_step<T, RCH, EX, EY>(v, u, s, x, nx, y0, ny, alpha, r, xb);
+            reg2d_step<T, RCH, EX, EY>(u, v, s + 1, x, nx, y0, ny, alpha, r, xb);
+        }
+    }
+    for (; s < ksteps; ++s) {
+        reg2d_step<T, RCH, EX, EY>(v, u, s, x, nx, y0, ny, alpha, r, xb);
+#pragma unroll
+        for (int q = 0; q < RCH; ++q) v[q] = u[q];
     }
 }
 

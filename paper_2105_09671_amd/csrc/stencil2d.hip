@@ -1,6 +1,7 @@
 // 2D Allen-Cahn stencil with temporal blocking (gfx950, wave64): the register
-// tile kernel (reg2d.h; the default plan) and the LDS tile kernels described
-// here (two LDS buffers, or one updated in place; tile2d.h).
+// tile kernels, 64 wide with one column per lane (reg2d.h) and 128 wide with
+// two (reg2w.h), one of which the default plan takes, and the LDS tile
+// kernels described here (two LDS buffers, or one updated in place; tile2d.h).
 //
 // LDS tiles.  One workgroup owns an output tile of (LX - 2*halo) x (LY - 2*halo) cells.
 // It loads the tile plus a `halo`-wide ring from HBM once, then advances the
@@ -26,6 +27,7 @@
 #include <climits>
 
 #include "reg2d.h"
+#include "reg2w.h"
 #include "tile2d.h"
 
 namespace ac {
@@ -116,6 +118,43 @@ template hipError_t launch_tile2d_reg<float>(const float *, float *, int, int, f
                                              const Tile2D &, int, hipStream_t);
 template hipError_t launch_tile2d_reg<double>(const double *, double *, int, int, double, double,
                                               const Tile2D &, int, hipStream_t);
+
+// Register tiles two columns wide per lane (reg2w.h), grid as above.
+template <typename T>
+__global__ void __launch_bounds__(1024)
+tile2d_regw_kernel(const T *src, T *dst, int nx, int ny, T alpha, T r, int halo, int ksteps,
+                   int tiles_x, int tiles)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int per = (tiles + 7) >> 3;
+    const int t = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+    if (t >= tiles) return;                         // whole workgroup
+    reg2w_body<T, kRegWRows>(src, dst, nx, ny, alpha, r, halo, ksteps, t % tiles_x, t / tiles_x,
+                             reinterpret_cast<T *>(smem_raw));
+}
+
+template <typename T>
+hipError_t launch_tile2d_regw(const T *src, T *dst, int nx, int ny, T alpha, T r, const Tile2D &t,
+                              int ksteps, hipStream_t stream)
+{
+    const int nw = t.LY / kRegWRows;
+    if (nx < 128 || t.LX != 128 || t.LY % kRegWRows || nw < 1 || nw > 16 || ksteps > t.halo ||
+        t.LY < 2 * t.halo + 1)
+        return hipErrorInvalidValue;
+    const int64_t tx = reg2d_tiles_1d(nx, 128, t.halo),
+                  tiles = tx * reg2d_tiles_1d(ny, t.LY, t.halo);
+    if (tiles > INT_MAX - 8) return hipErrorInvalidValue;
+    dim3 grid((unsigned)((tiles + 7) / 8 * 8));
+    hipLaunchKernelGGL(tile2d_regw_kernel<T>, grid, dim3(64 * nw),
+                       tile2d_regw_lds_bytes(t.LY, sizeof(T)), stream, src, dst, nx, ny, alpha, r,
+                       t.halo, ksteps, (int)tx, (int)tiles);
+    return hipGetLastError();
+}
+
+template hipError_t launch_tile2d_regw<float>(const float *, float *, int, int, float, float,
+                                              const Tile2D &, int, hipStream_t);
+template hipError_t launch_tile2d_regw<double>(const double *, double *, int, int, double, double,
+                                               const Tile2D &, int, hipStream_t);
 
 size_t tile2d_lds_bytes(int LX, int LY, size_t elem) {
     return 2 * (size_t)lds_pitch(LX) * lds_rows(LY, elem) * elem;

@@ -89,6 +89,16 @@ def test_batch_order_and_replay(api):
         assert D.rel_linf(v.cpu().numpy(), ref) <= 1e-5
 
 
+def test_wide_register_tiles_are_refused_for_batches(api):
+    """Batches run 64-wide tiles (instances may be narrower than 128); asking
+    for the 128-wide register kernel is an error, not a silent substitute."""
+    from paper_2105_09671_amd import _lib as L
+    fields, prm = _small_batch(44)
+    b = api.Batch([f.astype(np.float32) for f in fields], prm)
+    with pytest.raises(L.AcError):
+        b.step(10, tune=dict(tb_depth=2, tile_x=128, tile_y=32, kernel=6))
+
+
 def test_barrier_timeout_is_reported_and_recovers(api):
     from paper_2105_09671_amd import _lib as L
     fields, prm = _small_batch(42)

@@ -77,10 +77,12 @@ def test_2d_tile_shapes_bitwise(api, dtype):
     h, dt, eps = _par(128, 5)
     phi0 = inputs.random_field((150, 170), seed=22).astype(NP[dtype])
     base = _run2d(api, phi0, h, dt, eps, 20, dtype, tune=dict(tb_depth=1, tile_x=-1))
-    # kernel 0: the plan's choice; 4: registers, 3: in place in LDS, 1: two LDS buffers
+    # kernel 0: the plan's choice; 4: registers, 6: registers two columns per
+    # lane, 3: in place in LDS, 1: two LDS buffers
     for tx, ty, k, kern in [(64, 64, 4, 0), (128, 32, 3, 0), (256, 16, 2, 0), (96, 40, 8, 0),
                             (64, 17, 8, 0), (64, 16, 7, 4), (64, 48, 5, 4), (64, 256, 8, 4),
-                            (64, 128, 1, 4), (64, 64, 4, 3), (64, 64, 4, 1)]:
+                            (64, 128, 1, 4), (128, 64, 7, 6), (128, 8, 1, 6), (128, 24, 3, 6),
+                            (128, 128, 8, 6), (64, 64, 4, 3), (64, 64, 4, 1)]:
         tune = dict(tb_depth=k, tile_x=tx, tile_y=ty, kernel=kern)
         if kern:
             assert api.plan2d(170, 150, 20, dtype, tune)["kernel"] == kern
@@ -123,6 +125,34 @@ def test_2d_register_tiling_sizes(api, dtype):
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_2d_wide_register_tiling_sizes(api, dtype):
+    """128-wide register tiles (two adjacent columns per lane) sit flush against
+    the domain edges like the 64-wide ones.  Widths around every change of the
+    tile count (depth 7: 114 output columns per middle tile), odd widths (rows
+    then move one value at a time instead of pairs), heights below one tile
+    and the single-tile width 128; 19 steps so the last launch is shorter:
+    bitwise the 64-wide register kernel, and the oracle."""
+    h, dt, eps = _par(64, 4)
+    for ny, nx in [(32, 128), (33, 129), (31, 241), (50, 242), (51, 243), (64, 300), (17, 301),
+                   (8, 356), (100, 357), (200, 130)]:
+        phi0 = inputs.random_field((ny, nx), seed=41 + nx + ny, amp=0.9).astype(NP[dtype])
+        ref = oracle.step2d(phi0.astype(np.float64), h, dt, eps, 19)
+        wide = _run2d(api, phi0, h, dt, eps, 19, dtype,
+                      tune=dict(tb_depth=7, tile_x=128, tile_y=32, kernel=6))
+        narrow = _run2d(api, phi0, h, dt, eps, 19, dtype,
+                        tune=dict(tb_depth=7, tile_x=64, tile_y=32, kernel=4))
+        assert np.array_equal(wide, narrow), (ny, nx)
+        assert D.rel_linf(wide, ref) <= TOL[dtype], (ny, nx)
+    # one wave per tile up to sixteen, depth 1 to 8
+    phi0 = inputs.random_field((90, 250), seed=43, amp=0.9).astype(NP[dtype])
+    narrow = _run2d(api, phi0, h, dt, eps, 17, dtype, tune=dict(tb_depth=1, tile_x=-1))
+    for k, ly in [(1, 8), (3, 16), (5, 40), (8, 128)]:
+        wide = _run2d(api, phi0, h, dt, eps, 17, dtype,
+                      tune=dict(tb_depth=k, tile_x=128, tile_y=ly, kernel=6))
+        assert np.array_equal(wide, narrow), (k, ly)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_2d_whole_grid_register_tile(api, dtype):
     """Grids up to 64 wide and 256 tall run as one register tile with every
     step in one launch: the oracle, and bitwise the forced tiled plan."""
@@ -140,11 +170,17 @@ def test_2d_whole_grid_register_tile(api, dtype):
 
 def test_2d_plan_kernels(api):
     from paper_2105_09671_amd import _lib as L
-    # large grids default to the register kernel
+    # large grids default to a register kernel: 64 wide (16 rows per wave) or
+    # 128 wide (two columns per lane, 8 rows per wave), whichever the measured
+    # rates predict faster; the streaming regime of 16384^2 FP32 takes 128
     for dt_ in (torch.float32, torch.float64):
         p = api.plan2d(2048, 2048, 100, dt_)
-        assert p["kernel"] == 4 and p["tile_x"] == 64 and p["tile_y"] % 16 == 0, p
-        assert p["threads"] == 64 * p["tile_y"] // 16
+        assert p["kernel"] in (4, 6), p
+        rows = 16 if p["kernel"] == 4 else 8
+        assert p["tile_x"] == (64 if p["kernel"] == 4 else 128) and p["tile_y"] % rows == 0, p
+        assert p["threads"] == 64 * p["tile_y"] // rows
+    assert api.plan2d(16384, 16384, 100, torch.float32)["kernel"] == 6
+    assert api.plan2d(127, 2048, 100, torch.float32)["kernel"] == 4
     # grids up to 64 x 256: one register tile, all steps in one launch; wider
     # small grids: one LDS-resident workgroup
     assert api.plan2d(64, 256, 10, torch.float32)["tb_depth"] == 0
@@ -160,6 +196,15 @@ def test_2d_plan_kernels(api):
         api.plan2d(2048, 2048, 100, torch.float32, dict(tb_depth=4, tile_x=128, kernel=4))
     with pytest.raises(L.AcError):
         api.plan2d(2048, 2048, 100, torch.float32, dict(kernel=2))
+    # 128-wide register tiles: whole 8-row waves, grids at least 128 wide
+    p = api.plan2d(300, 200, 100, torch.float32, dict(kernel=6, tb_depth=5, tile_y=40))
+    assert p["kernel"] == 6 and p["tile_x"] == 128 and p["threads"] == 64 * 5, p
+    for bad in (dict(kernel=6, tb_depth=4, tile_y=36), dict(kernel=6, tb_depth=4, tile_y=136),
+                dict(kernel=6, tb_depth=4, tile_x=64)):
+        with pytest.raises(L.AcError):
+            api.plan2d(300, 200, 100, torch.float32, bad)
+    with pytest.raises(L.AcError):
+        api.plan2d(127, 200, 100, torch.float32, dict(kernel=6))
 
 
 def test_2d_split_equals_single_call(api):
@@ -175,17 +220,17 @@ def test_2d_split_equals_single_call(api):
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_2d_invariants(api, dtype):
     h, dt, eps = _par(160, 3)            # m = 3: the largest alpha accepted
-    tune = dict(tb_depth=5, tile_x=-1)
-    for v in (1.0, -1.0, 0.0):
-        c = np.full((170, 140), v, dtype=NP[dtype])
-        assert np.array_equal(_run2d(api, c, h, dt, eps, 30, dtype, tune), c)
-    phi0 = inputs.random_field((170, 140), seed=25, amp=1.0).astype(NP[dtype])
-    out = _run2d(api, phi0, h, dt, eps, 60, dtype, tune)
-    assert np.max(np.abs(out)) <= 1.0 + 4 * np.finfo(NP[dtype]).eps
-    assert np.array_equal(_run2d(api, -phi0, h, dt, eps, 60, dtype, tune), -out)
-    assert np.array_equal(_run2d(api, phi0[:, ::-1], h, dt, eps, 60, dtype, tune), out[:, ::-1])
-    assert np.array_equal(_run2d(api, phi0[::-1], h, dt, eps, 60, dtype, tune), out[::-1])
-    assert np.array_equal(_run2d(api, phi0.T, h, dt, eps, 60, dtype, tune), out.T)
+    for tune in (dict(tb_depth=5, tile_x=-1), dict(tb_depth=5, tile_x=128, tile_y=64, kernel=6)):
+        for v in (1.0, -1.0, 0.0):
+            c = np.full((170, 140), v, dtype=NP[dtype])
+            assert np.array_equal(_run2d(api, c, h, dt, eps, 30, dtype, tune), c)
+        phi0 = inputs.random_field((170, 140), seed=25, amp=1.0).astype(NP[dtype])
+        out = _run2d(api, phi0, h, dt, eps, 60, dtype, tune)
+        assert np.max(np.abs(out)) <= 1.0 + 4 * np.finfo(NP[dtype]).eps
+        assert np.array_equal(_run2d(api, -phi0, h, dt, eps, 60, dtype, tune), -out)
+        assert np.array_equal(_run2d(api, phi0[:, ::-1], h, dt, eps, 60, dtype, tune), out[:, ::-1])
+        assert np.array_equal(_run2d(api, phi0[::-1], h, dt, eps, 60, dtype, tune), out[::-1])
+        assert np.array_equal(_run2d(api, phi0.T, h, dt, eps, 60, dtype, tune), out.T)
 
 
 def test_2d_energy_decreases(api):
