@@ -279,6 +279,15 @@ def only(name: str) -> dict:
         api.step3d(p3, g3.h, g3.dt, g3.eps, 200)
         t = timed(lambda: api.step3d(p3, g3.h, g3.dt, g3.eps, 2000), 1)
         return {"workload": name, "GLUPS": round(256 ** 3 * 2000 / t / 1e9, 2), "ms": round(t * 1e3, 2)}
+    if name == "hbm16k":
+        from paper_2105_09671_amd import inputs
+        g = workloads.hbm16k()
+        t = inputs.random_field_torch((g.ny, g.nx), g.seed, g.stream, dtype=torch.float32, device="cuda")
+        n = workloads.HBM_STEPS
+        api.step2d(t, g.h, g.dt, g.eps, n)
+        sec = timed(lambda: api.step2d(t, g.h, g.dt, g.eps, n), 1)
+        return {"workload": name, "GLUPS": round(g.nx * g.ny * n / sec / 1e9, 2),
+                "ms": round(sec * 1e3, 2), "plan": api.plan2d(g.nx, g.ny, n, torch.float32)}
     if name == "sur256":
         import numpy as np
         from paper_2105_09671_amd import sur_train
@@ -301,7 +310,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=10.0, help="seconds of oracle work")
     ap.add_argument("--copy-ref", action="store_true",
                     help="also run a 256 MiB device copy (counter scale reference)")
-    ap.add_argument("--only", default="", choices=["", "batch512", "sep256c", "sur256"],
+    ap.add_argument("--only", default="", choices=["", "batch512", "sep256c", "hbm16k", "sur256"],
                     help="run one secondary workload alone (to profile its kernels)")
     args = ap.parse_args()
 
