@@ -60,9 +60,11 @@ typedef enum { AC_F32 = 0, AC_F64 = 1 } ac_dtype;
  *   tb_depth  time steps fused per launch (temporal blocking), 1..8
  *   tile_x/y  loaded tile extent in cells, including the tb_depth halo
  *   tile_z    2D: unused; 3D: z-extent of one streamed column segment
- *   kernel    0 = choose; 2D: AC_KERNEL_2D_TILED / _INPLACE / _REG (_REG needs
- *             tile_x = 64 and tile_y a multiple of 16 up to 256, _INPLACE
- *             tile_x = 64); 3D: AC_KERNEL_3D_STREAM / _REG (_REG needs tile_x =
+ *   kernel    0 = choose; 2D: AC_KERNEL_2D_TILED / _INPLACE / _REG / _REGW
+ *             (_REG needs tile_x = 64 and tile_y a multiple of 16 up to 256,
+ *             _REGW tile_x = 128 (its default), tile_y a multiple of 8 up to
+ *             128 and nx >= 128, _INPLACE tile_x = 64; batches take 64-wide
+ *             tiles only); 3D: AC_KERNEL_3D_STREAM / _REG (_REG needs tile_x =
  *             64, tile_y a multiple of 4 up to 32 and tb_depth <= 4)
  * Any valid choice gives bitwise the same result: every cell is always
  * updated by the same expression from the same neighbour values. */
@@ -71,7 +73,7 @@ typedef struct {
     int32_t tile_x;
     int32_t tile_y;
     int32_t tile_z;
-    int32_t kernel;   /* 2D tiled: 0 = choose, or AC_KERNEL_2D_TILED / _INPLACE / _REG */
+    int32_t kernel;   /* 2D tiled: 0 = choose, or AC_KERNEL_2D_TILED / _INPLACE / _REG / _REGW */
 } ac_tune;
 
 /* 2D step, 5-point stencil (section 2.1, Eq. pytorchACeq).  phi, work: nx*ny
