@@ -473,8 +473,8 @@ ac_status build_plan(Plan &p, const ac_instance2d *inst, int32_t n, int64_t nste
     ac_tune t = tune;
     if (t.tile_x == 0) t.tile_x = 64;
     // default: depth 8 on 64 x 128 register tiles (8 waves), fastest measured
-    // on the 512-grid batch in both precisions (FP32 2494 GLUPS, FP64 1501;
-    // depth 6 on 64 x 64: 2439 / 1405)
+    // on the 512-grid batch in both precisions (FP32 2692 GLUPS, FP64 1539;
+    // depth 7 on 64 x 128: 2602 / 1489; depth 8 on 64 x 192: 2625 / 1482)
     if (t.tile_y == 0) t.tile_y = 128;
     if (t.tb_depth == 0) t.tb_depth = 8;
     ac_plan tp;
