@@ -488,6 +488,22 @@ hipError_t device_info(DevInfo *out) {
 
 using namespace ac;
 
+// The plan of a 2D call: an explicit tune, else the tuning table's entry for
+// the grid's size class, else the built-in choice.  A table entry is shared by
+// every grid of the class, so it can fail to fit one of them (a 128-wide tile
+// on a grid narrower than 128); that grid then takes the built-in choice.
+static ac_status plan2d_with_table(int nx, int ny, int64_t nsteps, int32_t dtype,
+                                   const ac_tune *tune, const ac::DevInfo &dev, ac_plan *p) {
+    ac_tune tabled;
+    const bool from_table = !tune && tuned_lookup(AC_TUNE_2D, dtype, nx, ny, 1, &tabled);
+    ac_status s = make_plan2d(nx, ny, nsteps, elem_size(dtype), from_table ? &tabled : tune, dev, p);
+    if (s != AC_OK && from_table) {
+        s = make_plan2d(nx, ny, nsteps, elem_size(dtype), nullptr, dev, p);
+        if (s == AC_OK) g_err.clear();
+    }
+    return s;
+}
+
 extern "C" {
 
 ac_status ac_step_2d_tuned(void *phi, void *work, int32_t nx, int32_t ny, double h, double dt,
@@ -501,10 +517,8 @@ ac_status ac_step_2d_tuned(void *phi, void *work, int32_t nx, int32_t ny, double
     ac::DevInfo dev;
     hipError_t e = ac::device_info(&dev);
     if (e != hipSuccess) return hip_fail(e, "device query");
-    ac_tune tabled;
-    if (!tune && tuned_lookup(AC_TUNE_2D, dtype, nx, ny, 1, &tabled)) tune = &tabled;
     ac_plan p;
-    if ((s = make_plan2d(nx, ny, nsteps, elem_size(dtype), tune, dev, &p)) != AC_OK) return s;
+    if ((s = plan2d_with_table(nx, ny, nsteps, dtype, tune, dev, &p)) != AC_OK) return s;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     if (dtype == AC_F64)
         return run2d<double>((double *)phi, (double *)work, nx, ny, alpha, r, nsteps, p, st);
@@ -552,9 +566,7 @@ ac_status ac_plan_2d(int32_t nx, int32_t ny, int64_t nsteps, int32_t dtype, cons
     ac::DevInfo dev;
     hipError_t e = ac::device_info(&dev);
     if (e != hipSuccess) return hip_fail(e, "device query");
-    ac_tune tabled;
-    if (!tune && tuned_lookup(AC_TUNE_2D, dtype, nx, ny, 1, &tabled)) tune = &tabled;
-    return make_plan2d(nx, ny, nsteps, elem_size(dtype), tune, dev, out);
+    return plan2d_with_table(nx, ny, nsteps, dtype, tune, dev, out);
 }
 
 ac_status ac_plan_3d(int32_t nx, int32_t ny, int32_t nz, int64_t nsteps, int32_t dtype,

@@ -83,10 +83,14 @@ static ac_status sweep(const std::vector<ac_tune> &cands, hipStream_t st, F fn, 
 static std::vector<ac_tune> cands2d() {
     std::vector<ac_tune> v;
     // 64-wide tiles from registers (one wave per 16 rows) and in place in LDS
-    // (one wave per 16 FP32 or 8 FP64 rows), and a two-buffer LDS tile
-    const int tiles[][3] = {{64, 64, AC_KERNEL_2D_REG}, {64, 128, AC_KERNEL_2D_REG},
-                            {64, 192, AC_KERNEL_2D_REG}, {64, 64, AC_KERNEL_2D_INPLACE},
-                            {64, 128, AC_KERNEL_2D_INPLACE}, {128, 64, AC_KERNEL_2D_TILED}};
+    // (one wave per 16 FP32 or 8 FP64 rows), 128-wide register tiles (two
+    // columns per lane, one wave per 8 rows; grids at least 128 wide), and a
+    // two-buffer LDS tile
+    const int tiles[][3] = {{64, 64, AC_KERNEL_2D_REG},     {64, 128, AC_KERNEL_2D_REG},
+                            {64, 192, AC_KERNEL_2D_REG},    {128, 32, AC_KERNEL_2D_REGW},
+                            {128, 64, AC_KERNEL_2D_REGW},   {128, 128, AC_KERNEL_2D_REGW},
+                            {64, 64, AC_KERNEL_2D_INPLACE}, {64, 128, AC_KERNEL_2D_INPLACE},
+                            {128, 64, AC_KERNEL_2D_TILED}};
     for (int k : {3, 4, 5, 6, 7, 8})
         for (auto &t : tiles) v.push_back(ac_tune{k, t[0], t[1], 0, t[2]});
     return v;

@@ -148,6 +148,33 @@ def test_autotune_batched_and_2d(api, tmp_path):
     api.tune_clear()
 
 
+def test_table_entry_that_does_not_fit_falls_back(api, tmp_path):
+    """A tuning-table entry serves every grid of its size class.  A 128-wide
+    register tile entry fits 256 x 256 but not 64 x 1024 (same class, 2^16
+    cells): the narrow grid takes the built-in plan instead of failing, and
+    both grids give the bits of the forced single-step tiled plan."""
+    src = tmp_path / "tab.json"
+    src.write_text('{"arch": "gfx950", "entries": [\n'
+                   ' {"kind": 2, "dtype": 0, "cls": 16, "tb_depth": 6, "tile_x": 128, '
+                   '"tile_y": 64, "tile_z": 0, "kernel": 6}\n]}\n')
+    api.tune_clear()
+    api.tune_load(str(src))
+    try:
+        assert api.plan2d(256, 256, 30, torch.float32)["kernel"] == 6
+        assert api.plan2d(64, 1024, 30, torch.float32)["kernel"] != 6
+        for ny, nx in ((256, 256), (1024, 64)):
+            h, dt, eps = 1 / 256, params.dt_of(1 / 256), params.eps_m(1 / 256, 4)
+            f = inputs.random_field((ny, nx), 45, amp=0.8).astype(np.float32)
+            x = torch.from_numpy(f).cuda()
+            api.step2d(x, h, dt, eps, 30)           # table entry, or its fallback
+            api.check()
+            y = torch.from_numpy(f).cuda()
+            api.step2d(y, h, dt, eps, 30, tune=dict(tb_depth=1, tile_x=-1))
+            assert torch.equal(x, y), (ny, nx)
+    finally:
+        api.tune_clear()
+
+
 # FP32 on a random start: phase separation amplifies perturbations, so the bar
 # for such an instance is max(1e-5, SENS_FACTOR * sens), where sens is how far
 # the FP64 oracle itself moves when phi0 is moved by one FP32 ulp.  An FP32 run
