@@ -504,6 +504,20 @@ static ac_status plan2d_with_table(int nx, int ny, int64_t nsteps, int32_t dtype
     return s;
 }
 
+// The same for 3D (an entry can fail a grid of its class by, e.g., giving it
+// more than 65535 z segments).
+static ac_status plan3d_with_table(int nx, int ny, int nz, int64_t nsteps, int32_t dtype,
+                                   const ac_tune *tune, const ac::DevInfo &dev, ac_plan *p) {
+    ac_tune tabled;
+    const bool from_table = !tune && tuned_lookup(AC_TUNE_3D, dtype, nx, ny, nz, &tabled);
+    ac_status s = make_plan3d(nx, ny, nz, nsteps, elem_size(dtype), from_table ? &tabled : tune, dev, p);
+    if (s != AC_OK && from_table) {
+        s = make_plan3d(nx, ny, nz, nsteps, elem_size(dtype), nullptr, dev, p);
+        if (s == AC_OK) g_err.clear();
+    }
+    return s;
+}
+
 extern "C" {
 
 ac_status ac_step_2d_tuned(void *phi, void *work, int32_t nx, int32_t ny, double h, double dt,
@@ -542,10 +556,8 @@ ac_status ac_step_3d_tuned(void *phi, void *work, int32_t nx, int32_t ny, int32_
     ac::DevInfo dev;
     hipError_t e = ac::device_info(&dev);
     if (e != hipSuccess) return hip_fail(e, "device query");
-    ac_tune tabled;
-    if (!tune && tuned_lookup(AC_TUNE_3D, dtype, nx, ny, nz, &tabled)) tune = &tabled;
     ac_plan p;
-    if ((s = make_plan3d(nx, ny, nz, nsteps, elem_size(dtype), tune, dev, &p)) != AC_OK) return s;
+    if ((s = plan3d_with_table(nx, ny, nz, nsteps, dtype, tune, dev, &p)) != AC_OK) return s;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     if (dtype == AC_F64)
         return run3d<double>((double *)phi, (double *)work, nx, ny, nz, alpha, r, nsteps, p, st);
@@ -578,9 +590,7 @@ ac_status ac_plan_3d(int32_t nx, int32_t ny, int32_t nz, int64_t nsteps, int32_t
     ac::DevInfo dev;
     hipError_t e = ac::device_info(&dev);
     if (e != hipSuccess) return hip_fail(e, "device query");
-    ac_tune tabled;
-    if (!tune && tuned_lookup(AC_TUNE_3D, dtype, nx, ny, nz, &tabled)) tune = &tabled;
-    return make_plan3d(nx, ny, nz, nsteps, elem_size(dtype), tune, dev, out);
+    return plan3d_with_table(nx, ny, nz, nsteps, dtype, tune, dev, out);
 }
 
 ac_status ac_check(void *stream) {
