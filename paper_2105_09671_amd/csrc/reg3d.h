@@ -124,9 +124,24 @@ __device__ __forceinline__ void reg3d_stream(const T *__restrict__ src, T *__res
 #pragma unroll
         for (int s = 1; s <= K; ++s) {
             const int p = t - s;                        // plane advanced to level s
-            const T hu = w > 0 ? b[(2 * (s - 1) + 1) * row + (w - 1) * 64 + tx] : cur[s - 1][0];
-            const T hd = w + 1 < NW ? b[(2 * (s - 1)) * row + (w + 1) * 64 + tx]
-                                    : cur[s - 1][RCH - 1];
+            // the rows beyond the wave; the tile's first (last) wave uses its
+            // own first (last) row there, the Neumann mirror at a domain edge.
+            // FP64 reads it back from the exchange at a selected address, so
+            // no branch splits the iteration and the cross-lane shifts can
+            // fold into adds (measured +4-5 %); FP32 takes the value under a
+            // branch (the selected address measured +5 % at 256^3 but -5 % at
+            // 1024^3 there)
+            T hu, hd;
+            if constexpr (sizeof(T) == 8) {
+                const int iu = w > 0 ? (2 * (s - 1) + 1) * row + (w - 1) * 64 : (2 * (s - 1)) * row + w * 64;
+                const int id = w + 1 < NW ? (2 * (s - 1)) * row + (w + 1) * 64
+                                          : (2 * (s - 1) + 1) * row + w * 64;
+                hu = b[iu + tx];
+                hd = b[id + tx];
+            } else {
+                hu = w > 0 ? b[(2 * (s - 1) + 1) * row + (w - 1) * 64 + tx] : cur[s - 1][0];
+                hd = w + 1 < NW ? b[(2 * (s - 1)) * row + (w + 1) * 64 + tx] : cur[s - 1][RCH - 1];
+            }
             T res[RCH];
             if constexpr (ZC) {
                 const bool zlo = p == 0, zhi = p == nz - 1;
