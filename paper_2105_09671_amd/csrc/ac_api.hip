@@ -316,7 +316,8 @@ ac_status make_plan3d(int nx, int ny, int nz, int64_t nsteps, size_t elem, const
         if (rk <= ac::kReg3dMaxDepth) {
             const int64_t wgs = (int64_t)ac::reg2d_tiles_1d(nx, 64, rk) *
                                 ac::reg2d_tiles_1d(ny, 32, rk) * ((nz + 31) / 32);
-            const int per_cu = ac::reg3d_blocks_per_cu(rk, 32, elem);
+            const int per_cu =
+                ac::reg3d_blocks_per_cu(rk, 32, elem, ac::reg3d_select_reads(nx, ny, nz, elem));
             reg = wgs * kReg3dMinRoundsDen >=
                   kReg3dMinRoundsNum * (int64_t)std::max(per_cu, 1) * std::max(dev.cus, 1);
         }
@@ -357,7 +358,10 @@ ac_status make_plan3d(int nx, int ny, int nz, int64_t nsteps, size_t elem, const
                                : (int64_t)((nx + LX - 2 * K - 1) / (LX - 2 * K)) *
                                      ((ny + LY - 2 * K - 1) / (LY - 2 * K));
         const int64_t want = reg && !f64
-                                 ? (int64_t)std::max(ac::reg3d_blocks_per_cu(K, LY, elem), 1) * dev.cus
+                                 ? (int64_t)std::max(ac::reg3d_blocks_per_cu(
+                                                         K, LY, elem, ac::reg3d_select_reads(nx, ny, nz, elem)),
+                                                     1) *
+                                       dev.cus
                                  : 32LL * dev.cus;
         while (LZ < 128 && xy * ((nz + 2 * LZ - 1) / (2 * LZ)) >= want) LZ *= 2;
     }

@@ -105,7 +105,10 @@ inline size_t reg3d_lds_bytes(int K, int LY, size_t elem) {
 template <typename T>
 hipError_t launch_reg3d(const T *src, T *dst, int nx, int ny, int nz, T alpha, T r,
                         const Tile3D &t, hipStream_t stream);
-int reg3d_blocks_per_cu(int K, int LY, size_t elem);   // 0 if the query fails
+// the register kernel's read mode for a grid (reg3d_stream's SR) and its
+// resident workgroups per CU in that mode
+bool reg3d_select_reads(int nx, int ny, int nz, size_t elem);
+int reg3d_blocks_per_cu(int K, int LY, size_t elem, bool sr);   // 0 if the query fails
 
 // Raise a kernel's dynamic-LDS limit when it asks for more than 64 KiB; a
 // runtime that rejects the attribute leaves the launch to report any problem.

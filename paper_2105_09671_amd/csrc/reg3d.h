@@ -70,8 +70,8 @@ __device__ __forceinline__ void reg3d_level(const T cur[RCH], const T prv[RCH], 
 // The plane loop of one tile for one x/y edge variant (chosen once per tile,
 // so the loop carries no per-level dispatch): K levels pipelined along the z
 // segment [oz0, oz1).  xb: LDS exchange, [2 parities][K levels][2 rows][NW
-// waves][64 lanes].
-template <typename T, int K, int RCH, int EX, bool EY>
+// waves][64 lanes].  SR: how a wave reads the rows beyond its own (below).
+template <typename T, int K, int RCH, int EX, bool EY, bool SR>
 __device__ __forceinline__ void reg3d_stream(const T *__restrict__ src, T *__restrict__ dst, int nx,
                                              int ny, int nz, T alpha, T r, int x, int y0, bool xout,
                                              int oy0, int oy1, int oz0, int oz1,
@@ -126,13 +126,12 @@ __device__ __forceinline__ void reg3d_stream(const T *__restrict__ src, T *__res
             const int p = t - s;                        // plane advanced to level s
             // the rows beyond the wave; the tile's first (last) wave uses its
             // own first (last) row there, the Neumann mirror at a domain edge.
-            // FP64 reads it back from the exchange at a selected address, so
+            // SR: it reads it back from the exchange at a selected address, so
             // no branch splits the iteration and the cross-lane shifts can
-            // fold into adds (measured +4-5 %); FP32 takes the value under a
-            // branch (the selected address measured +5 % at 256^3 but -5 % at
-            // 1024^3 there)
+            // fold into adds; else it takes the value under a branch, which
+            // lets the compiler start the shifts while the reads are in flight
             T hu, hd;
-            if constexpr (sizeof(T) == 8) {
+            if constexpr (SR) {
                 const int iu = w > 0 ? (2 * (s - 1) + 1) * row + (w - 1) * 64 : (2 * (s - 1)) * row + w * 64;
                 const int id = w + 1 < NW ? (2 * (s - 1)) * row + (w + 1) * 64
                                           : (2 * (s - 1) + 1) * row + w * 64;
@@ -189,7 +188,7 @@ __device__ __forceinline__ void reg3d_stream(const T *__restrict__ src, T *__res
     for (int t = max(fb + 1, fa); t <= t1; ++t) iteration(t, std::true_type{});
 }
 
-template <typename T, int K, int RCH, bool EY>
+template <typename T, int K, int RCH, bool EY, bool SR>
 __device__ __forceinline__ void reg3d_stream_x(int ex, const T *__restrict__ src, T *__restrict__ dst,
                                                int nx, int ny, int nz, T alpha, T r, int x, int y0,
                                                bool xout, int oy0, int oy1, int oz0, int oz1,
@@ -197,19 +196,19 @@ __device__ __forceinline__ void reg3d_stream_x(int ex, const T *__restrict__ src
 {
     switch (ex) {
     case REG_X_IN:
-        reg3d_stream<T, K, RCH, REG_X_IN, EY>(src, dst, nx, ny, nz, alpha, r, x, y0, xout, oy0, oy1,
+        reg3d_stream<T, K, RCH, REG_X_IN, EY, SR>(src, dst, nx, ny, nz, alpha, r, x, y0, xout, oy0, oy1,
                                               oz0, oz1, gxy, xb);
         break;
     case REG_X_LEFT:
-        reg3d_stream<T, K, RCH, REG_X_LEFT, EY>(src, dst, nx, ny, nz, alpha, r, x, y0, xout, oy0,
+        reg3d_stream<T, K, RCH, REG_X_LEFT, EY, SR>(src, dst, nx, ny, nz, alpha, r, x, y0, xout, oy0,
                                                 oy1, oz0, oz1, gxy, xb);
         break;
     case REG_X_RIGHT:
-        reg3d_stream<T, K, RCH, REG_X_RIGHT, EY>(src, dst, nx, ny, nz, alpha, r, x, y0, xout, oy0,
+        reg3d_stream<T, K, RCH, REG_X_RIGHT, EY, SR>(src, dst, nx, ny, nz, alpha, r, x, y0, xout, oy0,
                                                  oy1, oz0, oz1, gxy, xb);
         break;
     default:
-        reg3d_stream<T, K, RCH, REG_X_SEL, EY>(src, dst, nx, ny, nz, alpha, r, x, y0, xout, oy0,
+        reg3d_stream<T, K, RCH, REG_X_SEL, EY, SR>(src, dst, nx, ny, nz, alpha, r, x, y0, xout, oy0,
                                                oy1, oz0, oz1, gxy, xb);
         break;
     }
@@ -217,7 +216,7 @@ __device__ __forceinline__ void reg3d_stream_x(int ex, const T *__restrict__ src
 
 // Advance xy tile `tile` (row-major over tiles_x columns) of z segment `zseg`
 // (LZ planes) by K steps.  xb: the LDS row exchange of reg3d_stream.
-template <typename T, int K, int RCH>
+template <typename T, int K, int RCH, bool SR>
 __device__ __forceinline__ void reg3d_body(const T *__restrict__ src, T *__restrict__ dst, int nx,
                                            int ny, int nz, T alpha, T r, int LZ, int tiles_x,
                                            int tile, int zseg, T *xb)
@@ -246,10 +245,10 @@ __device__ __forceinline__ void reg3d_body(const T *__restrict__ src, T *__restr
 #pragma unroll
     for (int q = 0; q < RCH; ++q) gxy[q] = min(y0 + q, ny - 1) * nx + xc;
     if (edgeY)
-        reg3d_stream_x<T, K, RCH, true>(ex, src, dst, nx, ny, nz, alpha, r, x, y0, xout, oy0, oy1,
+        reg3d_stream_x<T, K, RCH, true, SR>(ex, src, dst, nx, ny, nz, alpha, r, x, y0, xout, oy0, oy1,
                                         oz0, oz1, gxy, xb);
     else
-        reg3d_stream_x<T, K, RCH, false>(ex, src, dst, nx, ny, nz, alpha, r, x, y0, xout, oy0, oy1,
+        reg3d_stream_x<T, K, RCH, false, SR>(ex, src, dst, nx, ny, nz, alpha, r, x, y0, xout, oy0, oy1,
                                          oz0, oz1, gxy, xb);
 }
 

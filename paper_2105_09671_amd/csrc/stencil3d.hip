@@ -93,32 +93,47 @@ hipError_t launch_stream3d(const T *src, T *dst, int nx, int ny, int nz, T alpha
 }
 
 // Register-resident variant (reg3d.h): 64-wide tiles, kReg3dRows rows per wave.
-template <typename T, int K>
+// SR: the rows beyond a wave are read at a selected LDS address rather than
+// under a branch (reg3d_stream).
+template <typename T, int K, bool SR>
 __global__ void __launch_bounds__(512)
 reg3d_kernel(const T *__restrict__ src, T *__restrict__ dst, int nx, int ny, int nz, T alpha, T r,
              int LZ, int tiles_x)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    reg3d_body<T, K, kReg3dRows>(src, dst, nx, ny, nz, alpha, r, LZ, tiles_x, blockIdx.x,
-                                 blockIdx.y, reinterpret_cast<T *>(smem_raw));
+    reg3d_body<T, K, kReg3dRows, SR>(src, dst, nx, ny, nz, alpha, r, LZ, tiles_x, blockIdx.x,
+                                     blockIdx.y, reinterpret_cast<T *>(smem_raw));
 }
 
-template <typename T, int K>
-static const void *reg3d_ptr() { return (const void *)reg3d_kernel<T, K>; }
+template <typename T, int K, bool SR>
+static const void *reg3d_ptr() { return (const void *)reg3d_kernel<T, K, SR>; }
 
-template <typename T>
-static const void *reg3d_kernel_of(int K) {
+template <typename T, bool SR>
+static const void *reg3d_kernel_k(int K) {
     switch (K) {
-    case 1: return reg3d_ptr<T, 1>();
-    case 2: return reg3d_ptr<T, 2>();
-    case 3: return reg3d_ptr<T, 3>();
-    case 4: return reg3d_ptr<T, 4>();
+    case 1: return reg3d_ptr<T, 1, SR>();
+    case 2: return reg3d_ptr<T, 2, SR>();
+    case 3: return reg3d_ptr<T, 3, SR>();
+    case 4: return reg3d_ptr<T, 4, SR>();
     default: return nullptr;
     }
 }
 
-int reg3d_blocks_per_cu(int K, int LY, size_t elem) {
-    const void *k = elem == 8 ? reg3d_kernel_of<double>(K) : reg3d_kernel_of<float>(K);
+// The read mode per grid (measured on MI355X, A/B on one box): the selected
+// address lets every level's cross-lane shifts fold into adds and wins in FP64
+// (256^3 +5.5 %, 512^3 +4 %) and in FP32 up to 512^3 (256^3 +5 %, 512^3
+// +2 %, 768^3 even), while FP32 1024^3 runs 5 % faster with the branch.
+bool reg3d_select_reads(int nx, int ny, int nz, size_t elem) {
+    return elem == 8 || (int64_t)nx * ny * nz <= (int64_t)512 * 512 * 512;
+}
+
+static const void *reg3d_kernel_of(int K, size_t elem, bool sr) {
+    if (elem == 8) return reg3d_kernel_k<double, true>(K);
+    return sr ? reg3d_kernel_k<float, true>(K) : reg3d_kernel_k<float, false>(K);
+}
+
+int reg3d_blocks_per_cu(int K, int LY, size_t elem, bool sr) {
+    const void *k = reg3d_kernel_of(K, elem, sr);
     if (!k) return 0;
     const size_t lds = reg3d_lds_bytes(K, LY, elem);
     set_lds_limit(k, lds);
@@ -135,7 +150,7 @@ template <typename T>
 hipError_t launch_reg3d(const T *src, T *dst, int nx, int ny, int nz, T alpha, T r,
                         const Tile3D &t, hipStream_t stream)
 {
-    const void *k = reg3d_kernel_of<T>(t.K);
+    const void *k = reg3d_kernel_of(t.K, sizeof(T), reg3d_select_reads(nx, ny, nz, sizeof(T)));
     if (!k || t.LX != 64 || t.LY % kReg3dRows || t.LY / kReg3dRows > kReg3dMaxWaves)
         return hipErrorInvalidValue;
     // xy tiles flush against the domain edges (reg2d_tile_span)
