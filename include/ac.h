@@ -242,6 +242,17 @@ ac_status ac_autotune_3d(int32_t nx, int32_t ny, int32_t nz, int32_t dtype,
                          int64_t probe_steps, ac_tune *best, void *stream);
 ac_status ac_autotune_batched(const ac_instance2d *inst, int32_t n_inst, int32_t dtype,
                               int64_t probe_steps, ac_tune *best, void *stream);
+/* The autotuner in one call: fill the table for representative grids of
+ * dimension dim (2: 512^2, 2048^2, 4096^2; 3: 128^3, 256^3 -- one size class
+ * each) in dtype, timing every candidate on scratch buffers on the null stream.
+ * cache_json_path may be NULL (no persistence).  If the file exists its entries
+ * are loaded first and every size whose class they already cover is skipped,
+ * so a complete cache times nothing and makes no HIP call; the whole table is
+ * then written back to the file.  Errors: AC_ERR_INVALID_ARG for dim outside
+ * {2, 3} or a bad dtype (before any HIP call) and for an existing file that
+ * does not parse (it is left untouched); otherwise as ac_autotune_2d/3d and
+ * ac_tune_save. */
+ac_status ac_autotune(int32_t dim, int32_t dtype, const char *cache_json_path);
 /* Persist / restore / clear the tuning table (a small JSON file). */
 ac_status ac_tune_save(const char *path);
 ac_status ac_tune_load(const char *path);
@@ -285,8 +296,12 @@ ac_status ac_sur_infer(ac_sur *s, const float *phi_in, float *phi_out, int32_t b
  * stores d loss / d out for the backward pass; loss_dev (may be NULL) receives
  * the loss as a device float */
 ac_status ac_sur_loss(ac_sur *s, const float *target, int32_t batch, float *loss_dev);
-/* gradients of that loss with respect to every parameter */
-ac_status ac_sur_backward(ac_sur *s, int32_t batch);
+/* after ac_sur_forward on the same batch: gradients with respect to every
+ * parameter of a loss whose gradient with respect to phi_out is dloss_dout
+ * (device, batch*H*W floats, [batch][hw][hw]; read before the call returns in
+ * stream order).  dloss_dout = NULL takes the gradient ac_sur_loss stored, and
+ * then requires ac_sur_loss on that batch first. */
+ac_status ac_sur_backward(ac_sur *s, const float *dloss_dout, int32_t batch);
 ac_status ac_sur_get_grads(ac_sur *s, float *host, int64_t n);
 /* one Adam update (bias-corrected, step t >= 1) of the FP32 master weights */
 ac_status ac_sur_adam_step(ac_sur *s, float lr, float b1, float b2, float eps_adam, int64_t t);

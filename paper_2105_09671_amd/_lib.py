@@ -100,6 +100,7 @@ SIGNATURES = {
     "ac_autotune_3d": ([_i32, _i32, _i32, _i32, _i64, ctypes.POINTER(AcTune), _vp], _i32),
     "ac_autotune_batched": ([ctypes.POINTER(AcInstance2D), _i32, _i32, _i64,
                              ctypes.POINTER(AcTune), _vp], _i32),
+    "ac_autotune": ([_i32, _i32, ctypes.c_char_p], _i32),
     "ac_tune_save": ([ctypes.c_char_p], _i32),
     "ac_tune_load": ([ctypes.c_char_p], _i32),
     "ac_tune_clear": ([], None),
@@ -113,7 +114,7 @@ SIGNATURES = {
     "ac_sur_forward": ([_vp, _vp, _vp, _i32], _i32),
     "ac_sur_infer": ([_vp, _vp, _vp, _i32], _i32),
     "ac_sur_loss": ([_vp, _vp, _i32, _vp], _i32),
-    "ac_sur_backward": ([_vp, _i32], _i32),
+    "ac_sur_backward": ([_vp, _vp, _i32], _i32),
     "ac_sur_get_grads": ([_vp, ctypes.POINTER(ctypes.c_float), _i64], _i32),
     "ac_sur_adam_step": ([_vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                           _i64], _i32),

@@ -245,6 +245,14 @@ def autotune3d(nx: int, ny: int, nz: int, dtype=torch.float32, probe_steps: int 
     return {k: getattr(best, k) for k, _ in best._fields_}
 
 
+def autotune(dim: int, dtype=torch.float32, cache_path: str | None = None) -> None:
+    """ac_autotune: tune the representative grids of dimension dim, using and
+    updating the JSON cache at cache_path when given."""
+    code = L.AC_F64 if dtype == torch.float64 else L.AC_F32
+    L.check(L.lib().ac_autotune(int(dim), code, cache_path.encode() if cache_path else None),
+            "ac_autotune")
+
+
 def tune_save(path: str) -> None:
     L.check(L.lib().ac_tune_save(path.encode()), "ac_tune_save")
 

@@ -68,6 +68,7 @@ ac_status validate(const void *phi, const void *work, int64_t ncells, int dim, d
 // then copies work back into phi at the end.
 Chunks plan_chunks(int64_t nsteps, int64_t k) {
     Chunks c{};
+    if (nsteps <= 0 || k <= 0) return c;   // no launch (a plan query may ask for 0 steps)
     c.n = (nsteps + k - 1) / k;
     c.copy_back = false;
     if (c.n & 1) {

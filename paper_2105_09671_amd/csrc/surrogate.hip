@@ -943,14 +943,24 @@ ac_status ac_sur_loss(ac_sur *s, const float *target, int32_t batch, float *loss
     return AC_OK;
 }
 
-ac_status ac_sur_backward(ac_sur *s, int32_t batch) {
+ac_status ac_sur_backward(ac_sur *s, const float *dloss_dout, int32_t batch) {
     g_err.clear();
     if (!s) return fail(AC_ERR_INVALID_ARG, "null handle");
-    if (!s->have_loss || batch != s->last_batch)
+    if (dloss_dout) {
+        if (!s->have_fwd || batch != s->last_batch)
+            return fail(AC_ERR_INVALID_ARG, "ac_sur_backward needs the forward pass of the same batch first");
+    } else if (!s->have_loss || batch != s->last_batch) {
         return fail(AC_ERR_INVALID_ARG, "ac_sur_backward needs forward and loss of the same batch first");
+    }
     const int B = batch, H = s->H, W = s->W, H2 = H / 2, W2 = W / 2, H4 = H / 4, W4 = W / 4;
     const int n1 = B * H * W;
-    hipError_t e = hipMemsetAsync(s->g, 0, s->nparam * 4, s->st);
+    hipError_t e = hipSuccess;
+    if (dloss_dout) {
+        e = hipMemcpyAsync(s->dU, dloss_dout, (size_t)n1 * 4, hipMemcpyDeviceToDevice, s->st);
+        if (e != hipSuccess) return hip_fail(e, "dloss_dout copy");
+        s->have_loss = false;   // dU no longer holds the stored loss gradient
+    }
+    e = hipMemsetAsync(s->g, 0, s->nparam * 4, s->st);
     if (e == hipSuccess) e = hipMemsetAsync(s->g_first, 0, 32 * 72 * 4, s->st);
     if (e != hipSuccess) return hip_fail(e, "grad reset");
     const View none{nullptr, 0, 0};

@@ -237,6 +237,44 @@ ac_status ac_tune_load(const char *path) {
     return AC_OK;
 }
 
+ac_status ac_autotune(int32_t dim, int32_t dtype, const char *cache_json_path) {
+    g_err.clear();
+    if (dim != 2 && dim != 3) return fail(AC_ERR_INVALID_ARG, "dim must be 2 or 3, got %d", dim);
+    if (dtype != AC_F32 && dtype != AC_F64)
+        return fail(AC_ERR_INVALID_ARG, "dtype must be AC_F32 (0) or AC_F64 (1), got %d", dtype);
+    if (cache_json_path) {
+        FILE *f = std::fopen(cache_json_path, "r");
+        if (f) {
+            std::fclose(f);
+            // an existing cache that does not parse is left alone, not overwritten
+            const ac_status s = ac_tune_load(cache_json_path);
+            if (s != AC_OK) return s;
+        }
+    }
+    // representative sizes: square grids of the sizes the stepper is usually
+    // run at; each fills one size class of the table
+    static const int32_t k2d[] = {512, 2048, 4096}, k3d[] = {128, 256};
+    const int32_t *sizes = dim == 2 ? k2d : k3d;
+    const int nsz = dim == 2 ? 3 : 2;
+    for (int i = 0; i < nsz; ++i) {
+        const int64_t n = sizes[i];
+        ac_tune have{}, best{};
+        if (dim == 2) {
+            if (tuned_lookup(AC_TUNE_2D, dtype, n, n, 1, &have)) continue;   // cache hit
+            const ac_status s = ac_autotune_2d((int32_t)n, (int32_t)n, dtype, 112, &best, nullptr);
+            if (s != AC_OK) return s;
+        } else {
+            if (tuned_lookup(AC_TUNE_3D, dtype, n, n, n, &have)) continue;
+            const ac_status s = ac_autotune_3d((int32_t)n, (int32_t)n, (int32_t)n, dtype, 48, &best,
+                                               nullptr);
+            if (s != AC_OK) return s;
+        }
+        const hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) return hip_fail(e, "autotune");
+    }
+    return cache_json_path ? ac_tune_save(cache_json_path) : AC_OK;
+}
+
 void ac_tune_clear(void) {
     std::lock_guard<std::mutex> lock(g_tmu);
     g_table.clear();

@@ -9,10 +9,11 @@ Training: mini-batches of pairs, MSE of phi + U(phi) against phi_{k+1}, Adam;
 forward, backward and update all run in libac's BF16-MFMA kernels.
 
 Inference to T with judge and fallback: each K-block the surrogate advances
-every trusted grid; the plain stepper advances a rotating sample of them (the
-judge compares the two: interface error <= h and RMS <= l2_bar) and every grid
-that has failed once (the fallback), all in one masked batched launch.
-Time-to-T includes the judge and the fallback.
+every trusted grid; the plain stepper advances the same grids from the same
+states (the judge compares the two: interface error <= h and RMS <= l2_bar;
+every block by default, a rotating sample as an option) and every grid that
+has failed once (the fallback), all in one masked batched launch.  Time-to-T
+includes the judge and the fallback.
 
   python -m paper_2105_09671_amd.sur_train --out weights.npz [--trajectories 4096] [--steps 3000]
 """
@@ -160,17 +161,23 @@ def forward_rate(net: Surrogate, n: int, reps: int = 3) -> dict:
             "flop_per_grid": FORWARD_FLOP}
 
 
-def evaluate(net: Surrogate, seeds, T_blocks: int = 20, sample_every: int = 16,
-             l2_bar: float = L2_BAR) -> dict:
+def evaluate(net: Surrogate, seeds, T_blocks: int = 20, sample_every: int = 1,
+             l2_bar: float = L2_BAR, return_state: bool = False) -> dict:
     """Surrogate + judge + fallback to T versus the plain stepper, on held-out seeds.
 
-    Per K-block: the surrogate advances every trusted grid; the plain stepper
-    advances the judge sample -- every grid in the first block, then a rotating
-    1/sample_every of the trusted grids -- and every untrusted grid, in one
-    masked batched launch.  A sampled grid keeps the plain result; if the
-    surrogate's prediction for it fails the judge (interface error > h or
-    RMS > l2_bar) the grid is untrusted from then on.  Unsampled trusted grids
-    take the surrogate's prediction."""
+    Per K-block the surrogate predicts every trusted grid.  The judged grids
+    -- every trusted grid when sample_every == 1 (the default), else every grid
+    in the first block and then a rotating 1/sample_every of the trusted ones --
+    are also advanced by the plain stepper from the same state (the judge), in
+    one masked batched launch together with every untrusted grid (the
+    fallback).  A judged prediction within interface error h and RMS l2_bar of
+    the plain result is kept; otherwise the plain result is kept and the grid
+    is untrusted (stepped plainly) from then on.  With sample_every > 1 the
+    predictions of unjudged blocks are taken unchecked.  Time-to-T includes the
+    surrogate, the judge and the fallback.  The final states are compared with
+    a plain run to T (per grid: interface error and RMS)."""
+    if sample_every < 1:
+        raise ValueError("sample_every must be >= 1")
     gs, fields = grids_for(seeds)
     params = [(g.h, g.dt, g.eps) for g in gs]
     N = len(seeds)
@@ -198,18 +205,20 @@ def evaluate(net: Surrogate, seeds, T_blocks: int = 20, sample_every: int = 16,
     B = net.batch_max
     net.infer(state[:min(N, B)].contiguous(), pred[:min(N, B)])     # warm-up
     torch.cuda.synchronize()
-    # book-keeping on the host: which grids are trusted, sampled, stepped
+    # book-keeping on the host: which grids are trusted, judged, stepped
     trusted = np.ones(N, dtype=bool)
+    sur_blocks = np.zeros(N, dtype=np.int64)           # surrogate predictions kept, per grid
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.int64)).cuda()
-    sur_grid_blocks, judged, judged_fail = 0, 0, 0
+    judged, judged_fail = 0, 0
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for k in range(T_blocks):
         tidx = np.nonzero(trusted)[0]
         nt = len(tidx)
-        # the first block of every trajectory is judged for every grid; then a
-        # rotating 1/sample_every of the trusted grids
-        spos = np.arange(nt) if k == 0 else np.arange(k % sample_every, nt, sample_every)
+        if sample_every == 1 or k == 0:
+            spos = np.arange(nt)
+        else:
+            spos = np.arange(k % sample_every, nt, sample_every)
         kpos = np.setdiff1d(np.arange(nt), spos)
         samp = tidx[spos]
         if nt == N:
@@ -222,16 +231,20 @@ def evaluate(net: Surrogate, seeds, T_blocks: int = 20, sample_every: int = 16,
         act = ~trusted
         act[samp] = True
         active.copy_(torch.from_numpy(act.astype(np.int32)))
-        fb.step_masked(K_STEPS, active)                 # plain: sample + untrusted, in place
+        fb.step_masked(K_STEPS, active)                 # plain: judged + untrusted, in place
         if len(samp):
             iface, l2 = api.judge2d(out.index_select(0, dev(spos)), state.index_select(0, dev(samp)), h)
             ok = ((iface <= h) & (l2 <= l2_bar)).cpu().numpy()
             judged += len(samp)
             judged_fail += int((~ok).sum())
             trusted[samp[~ok]] = False
+            keep = spos[ok]                             # accepted predictions replace the judge's state
+            if len(keep):
+                state.index_copy_(0, dev(tidx[keep]), out.index_select(0, dev(keep)))
+                sur_blocks[tidx[keep]] += 1
         if len(kpos):
             state.index_copy_(0, dev(tidx[kpos]), out.index_select(0, dev(kpos)))
-            sur_grid_blocks += len(kpos)
+            sur_blocks[tidx[kpos]] += 1
     e1.record()
     torch.cuda.synchronize()
     sur_ms = e0.elapsed_time(e1)
@@ -239,18 +252,23 @@ def evaluate(net: Surrogate, seeds, T_blocks: int = 20, sample_every: int = 16,
     iface_T, l2_T = iface_T.cpu().numpy(), l2_T.cpu().numpy()
     kinds = [g.kind for g in gs]
     ok_T = (iface_T <= h) & (l2_T <= l2_bar)
-    trusted_np = trusted
     by_kind = {kd: {"final_ok": float(np.mean(ok_T[[i for i, x in enumerate(kinds) if x == kd]])),
-                    "trusted_at_T": float(np.mean(trusted_np[[i for i, x in enumerate(kinds) if x == kd]]))}
+                    "trusted_at_T": float(np.mean(trusted[[i for i, x in enumerate(kinds) if x == kd]]))}
                for kd in sorted(set(kinds))}
-    return {"grids": N, "T_steps": K_STEPS * T_blocks, "plain_ms": round(plain_ms, 3),
-            "surrogate_ms": round(sur_ms, 3), "speedup": round(plain_ms / sur_ms, 4),
-            "forward": forward_rate(net, N),
-            "surrogate_grid_blocks": sur_grid_blocks, "grid_blocks": N * T_blocks,
-            "judged": judged, "judged_failures": judged_fail, "sample_every": sample_every,
-            "final_ok_fraction": float(np.mean(ok_T)), "by_kind": by_kind,
-            "final_iface_median_over_h": float(np.median(np.minimum(iface_T / h, 1e9))),
-            "final_l2_median": float(np.median(l2_T))}
+    res = {"grids": N, "T_steps": K_STEPS * T_blocks, "plain_ms": round(plain_ms, 3),
+           "surrogate_ms": round(sur_ms, 3), "speedup": round(plain_ms / sur_ms, 4),
+           "forward": forward_rate(net, N),
+           "surrogate_grid_blocks": int(sur_blocks.sum()), "grid_blocks": N * T_blocks,
+           "judged": judged, "judged_failures": judged_fail, "sample_every": sample_every,
+           "final_ok_fraction": float(np.mean(ok_T)), "by_kind": by_kind,
+           "final_iface_max_over_h": float(np.max(np.minimum(iface_T / h, 1e9))),
+           "final_iface_median_over_h": float(np.median(np.minimum(iface_T / h, 1e9))),
+           "final_l2_max": float(np.max(l2_T)), "final_l2_median": float(np.median(l2_T))}
+    if return_state:
+        res["state"], res["ref_T"] = state.clone(), ref_T
+        res["per_grid"] = {"iface": iface_T, "l2": l2_T, "trusted": trusted.copy(),
+                           "surrogate_blocks": sur_blocks, "kinds": kinds}
+    return res
 
 
 def main():

@@ -99,8 +99,15 @@ class Surrogate:
         L.check(L.lib().ac_sur_loss(self._h, target.data_ptr(), b, self._loss.data_ptr()), "ac_sur_loss")
         return self._loss
 
-    def backward(self, batch: int) -> None:
-        L.check(L.lib().ac_sur_backward(self._h, int(batch)), "ac_sur_backward")
+    def backward(self, batch: int, dloss_dout: torch.Tensor | None = None) -> None:
+        """Parameter gradients after forward(): of the loss stored by loss(), or
+        of any loss whose gradient with respect to the output is dloss_dout."""
+        ptr = None
+        if dloss_dout is not None:
+            if self._check(dloss_dout) != int(batch):
+                raise ValueError("dloss_dout must hold %d grids" % int(batch))
+            ptr = dloss_dout.data_ptr()
+        L.check(L.lib().ac_sur_backward(self._h, ptr, int(batch)), "ac_sur_backward")
 
     def adam(self, lr: float, b1: float = 0.9, b2: float = 0.999, eps: float = 1e-8) -> None:
         self.t += 1

@@ -198,3 +198,41 @@ def test_batched3d_rejects_overlap_between_instances(lib):
     arr = (L.AcInstance3D * 2)(_inst3(A, B), _inst3(C, A + 256))
     assert lib.ac_step_batched_3d(arr, 2, 10, 0, None, None, None) == L.AC_ERR_INVALID_ARG
     assert b"overlap" in lib.ac_last_error()
+
+
+def test_autotune_one_call_validation_and_cache_hit(lib, tmp_path):
+    """ac_autotune(dim, dtype, cache): bad dim / dtype fail before any HIP call;
+    an existing cache that does not parse is refused and left as it was; a cache
+    that already covers every representative size class of (dim, dtype) times
+    nothing (no HIP call, so this runs without a GPU) and is written back."""
+    lib.ac_tune_clear()
+    assert lib.ac_autotune(1, 0, None) == L.AC_ERR_INVALID_ARG
+    assert lib.ac_autotune(4, 0, None) == L.AC_ERR_INVALID_ARG
+    assert lib.ac_autotune(2, 7, None) == L.AC_ERR_INVALID_ARG
+    assert b"dtype" in lib.ac_last_error()
+    junk = tmp_path / "junk.json"
+    junk.write_text("not a table\n")
+    assert lib.ac_autotune(2, 0, str(junk).encode()) == L.AC_ERR_INVALID_ARG
+    assert junk.read_text() == "not a table\n"
+    # size classes floor(log2(cells)): 512^2 -> 18, 2048^2 -> 22, 4096^2 -> 24;
+    # 128^3 -> 21, 256^3 -> 24
+    rows = [(2, 0, 18, 5, 64, 64, 0, 4), (2, 0, 22, 7, 64, 128, 0, 4), (2, 0, 24, 8, 128, 128, 0, 6),
+            (3, 1, 21, 3, 64, 32, 32, 5), (3, 1, 24, 4, 64, 32, 64, 5)]
+    cache = tmp_path / "cache.json"
+    cache.write_text('{"arch": "gfx950", "entries": [\n' + ",\n".join(
+        ' {"kind": %d, "dtype": %d, "cls": %d, "tb_depth": %d, "tile_x": %d, "tile_y": %d, '
+        '"tile_z": %d, "kernel": %d}' % r for r in rows) + "\n]}\n")
+    assert lib.ac_autotune(2, 0, str(cache).encode()) == L.AC_OK
+    assert lib.ac_autotune(3, 1, str(cache).encode()) == L.AC_OK
+    assert lib.ac_tune_count() == len(rows)
+    text = cache.read_text()
+    for r in rows:
+        assert '"kind": %d, "dtype": %d, "cls": %d, "tb_depth": %d' % r[:4] in text
+    lib.ac_tune_clear()
+
+
+def test_surrogate_calls_reject_null_handle(lib):
+    assert lib.ac_sur_backward(None, None, 1) == L.AC_ERR_INVALID_ARG
+    assert lib.ac_sur_backward(None, A, 1) == L.AC_ERR_INVALID_ARG
+    assert lib.ac_sur_forward(None, A, B, 1) == L.AC_ERR_INVALID_ARG
+    assert lib.ac_sur_adam_step(None, 1e-3, 0.9, 0.999, 1e-8, 1) == L.AC_ERR_INVALID_ARG

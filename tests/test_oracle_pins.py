@@ -284,3 +284,129 @@ def test_crop_locality(oracle_mod):
     crop3 = oracle_mod.step3d(np.ascontiguousarray(p3[0:15, 5:20, 8:22]), h, 0.1 * h * h,
                               params.eps_m(h, 3), n)
     assert np.array_equal(full3[0:8, 12:13, 15:22], crop3[0:8, 7:8, 7:14])
+
+
+# ----------------------------------------------------------------------------
+# Interface diagnostics (the reading of "interface error": zero crossings on
+# the edges between cell centres, located by linear interpolation; the error
+# is the symmetric Hausdorff distance between the two crossing sets).  Pinned
+# to geometry, not to the code's own formulas.
+
+def _centres(n, h):
+    return (np.arange(n) + 0.5) * h
+
+
+@pytest.mark.parametrize("x0", [0.3141, 0.5, 0.515625, 0.7773])
+def test_crossings_of_linear_field_are_exact(x0):
+    """Linear interpolation is exact on a linear field: phi = x - x0 crosses
+    zero at x = x0 on every row (one crossing per row, on a horizontal edge,
+    none on vertical ones); phi = y - y0 likewise on every column.  A wrong
+    interpolation weight or a half-cell offset on either axis moves these
+    points.  x0 = 0.515625 sits exactly on a cell centre (phi = 0 there): the
+    crossing is that centre."""
+    nx, ny, h = 64, 40, 1 / 64
+    X, Y = np.meshgrid(_centres(nx, h), _centres(ny, h))       # shape (ny, nx)
+    p = D.crossings(X - x0, h)
+    assert p.shape == (ny, 2)
+    assert np.max(np.abs(p[:, 0] - x0)) <= 1e-14
+    assert np.max(np.abs(np.sort(p[:, 1]) - _centres(ny, h))) <= 1e-14
+    y0 = x0 * 40 / 64 + 0.1
+    Xt, Yt = np.meshgrid(_centres(ny, h), _centres(nx, h))     # shape (nx, ny): 64 rows
+    q = D.crossings(Yt - y0, h)
+    assert q.shape == (ny, 2)
+    assert np.max(np.abs(q[:, 1] - y0)) <= 1e-14
+    assert np.max(np.abs(np.sort(q[:, 0]) - _centres(ny, h))) <= 1e-14
+
+
+def test_crossings_of_oblique_linear_field_lie_on_the_line():
+    """phi = (x - x0) + 2 (y - y0): every crossing, on horizontal and vertical
+    edges alike, lies exactly on the line, and there is one per sign-changing
+    edge."""
+    n, h, x0, y0 = 48, 1 / 48, 0.41, 0.57
+    X, Y = np.meshgrid(_centres(n, h), _centres(n, h))
+    phi = (X - x0) + 2 * (Y - y0)
+    p = D.crossings(phi, h)
+    edges = int(np.sum((phi[:, :-1] > 0) != (phi[:, 1:] > 0)) + np.sum((phi[:-1] > 0) != (phi[1:] > 0)))
+    assert len(p) == edges and edges > n
+    assert np.max(np.abs((p[:, 0] - x0) + 2 * (p[:, 1] - y0))) <= 1e-14
+
+
+def test_interface_error_of_parallel_fronts():
+    """Two straight fronts x = x0 and x = x1 on the same rows: every crossing of
+    one has its nearest crossing of the other on its own row, |x1 - x0| away."""
+    n, h = 64, 1 / 64
+    X, _ = np.meshgrid(_centres(n, h), _centres(n, h))
+    for x0, x1 in ((0.3, 0.3 + 0.37 / 64), (0.25, 0.61), (0.5, 0.5)):
+        assert abs(D.interface_error(X - x0, X - x1, h) - abs(x1 - x0)) <= 1e-15
+
+
+@pytest.mark.parametrize("s", [1, 2, 5])
+def test_interface_error_of_front_shifted_by_whole_cells(s):
+    """A tanh front and the same front moved by s whole cells: the sampled
+    values are the same numbers s cells over, so every crossing moves by
+    exactly s h and the distance is s h."""
+    n, h = 96, 1 / 96
+    eps = params.eps_m(h, 4)
+    X, _ = np.meshgrid(_centres(n, h), _centres(n, h))
+    a = np.tanh((X - 0.4) / (math.sqrt(2) * eps))
+    b = np.tanh((X - 0.4 - s * h) / (math.sqrt(2) * eps))
+    assert abs(D.interface_error(a, b, h) - s * h) <= 1e-13
+
+
+@pytest.mark.parametrize("n,R", [(128, 0.25), (256, 0.3)])
+def test_interface_error_of_concentric_circles(n, R):
+    """Crossings of a sampled circle lie on the circle to O(h^2) (the
+    interpolation error of a smooth front: measured below 1.3 h^2 / R for
+    these tanh profiles, bound 2 h^2 / R).  For circles R and R + d the two
+    crossing sets are discrete: a crossing of one circle is at least d - 2h^2/R
+    from every crossing of the other, and within sqrt(d^2 + h^2/2) + 2h^2/R of
+    one (consecutive crossings along a front lie on the boundary of one cell,
+    at most sqrt(2) h apart, so the nearest is at most h/sqrt(2) along the front
+    from the foot of the normal)."""
+    h = 1 / n
+    eps = params.eps_m(h, 4)
+    X, Y = np.meshgrid(_centres(n, h), _centres(n, h))
+    r = np.hypot(X - 0.5, Y - 0.5)
+    f = lambda RR: np.tanh((RR - r) / (math.sqrt(2) * eps))
+    p = D.crossings(f(R), h)
+    slack = 2 * h * h / R
+    assert np.max(np.abs(np.hypot(p[:, 0] - 0.5, p[:, 1] - 0.5) - R)) <= slack
+    for d in (0.37 * h, 1.5 * h, 3.0 * h):
+        e = D.interface_error(f(R), f(R + d), h)
+        assert d - slack <= e <= math.sqrt(d * d + h * h / 2) + slack, (d / h, e / h)
+
+
+def test_hausdorff_against_brute_force():
+    """cKDTree queries against the full distance matrix (max of row minima and
+    of column minima) on random sets, including one set inside the other,
+    where the two directed distances differ."""
+    rng = np.random.RandomState(3)
+    for na, nb in ((7, 11), (30, 5), (1, 1)):
+        A, B = rng.rand(na, 2), rng.rand(nb, 2)
+        M = np.sqrt(((A[:, None, :] - B[None, :, :]) ** 2).sum(-1))
+        assert abs(D.hausdorff(A, B) - max(M.min(1).max(), M.min(0).max())) <= 1e-15
+    A = rng.rand(6, 2)
+    B = np.concatenate([A, [[5.0, 5.0]]])
+    far = np.min(np.hypot(A[:, 0] - 5.0, A[:, 1] - 5.0))
+    assert abs(D.hausdorff(A, B) - far) <= 1e-15 and abs(D.hausdorff(B, A) - far) <= 1e-15
+
+
+def test_interface_error_empty_cases():
+    n, h = 16, 1 / 16
+    pos = np.ones((n, n))
+    X, _ = np.meshgrid(_centres(n, h), _centres(n, h))
+    assert D.interface_error(pos, 0.5 * pos, h) == 0.0
+    assert math.isinf(D.interface_error(pos, X - 0.5, h))
+    assert math.isinf(D.interface_error(X - 0.5, -pos, h))
+
+
+def test_err_metric_closed_forms():
+    """Eq. ERReq's Err is the time average of the per-snapshot RMS difference.
+    A constant difference c_t has RMS |c_t|; a checkerboard of +-a has RMS a.
+    Differences 1 and 3 average to 2 (an RMS over time would give sqrt(5), a
+    sum 4)."""
+    a = [np.zeros((5, 7)), np.zeros((5, 7))]
+    assert D.err_metric(a, [x + 1.0 for x in a[:1]] + [a[1] - 3.0]) == 2.0
+    chk = np.where((np.add.outer(np.arange(6), np.arange(8)) % 2) == 0, 0.25, -0.25)
+    assert D.err_metric([np.zeros((6, 8))], [chk]) == 0.25
+    assert D.err_metric(a, a) == 0.0

@@ -136,3 +136,37 @@ def test_adam_matches_reference_update(sur):
     expect = w - 1e-3 * (m / 0.1) / (np.sqrt(v / 0.001) + 1e-8)
     assert np.max(np.abs(w1 - expect)) <= 1e-6
     net.close()
+
+
+def test_backward_of_external_output_gradient(sur):
+    """ac_sur_backward with a caller's d loss / d out: fed the mean-squared-error
+    gradient 2 (out - target) / n it gives the gradients of the stored-loss
+    path (to FP32 summation order) and of the oracle (BF16 bar); the map is
+    linear in d loss / d out (x3 gives 3x the gradients)."""
+    B, hw = 2, 32
+    w, phi, tgt = _case(71, B, hw)
+    net = sur.Surrogate(B, hw)
+    net.set_weights(w.astype(np.float32))
+    x = torch.from_numpy(phi.astype(np.float32)).cuda()
+    t = torch.from_numpy(tgt.astype(np.float32)).cuda()
+    out = net.forward(x).clone()
+    net.loss(t)
+    net.backward(B)
+    g_loss = net.grads().astype(np.float64)
+    dU = (out - t) * np.float32(2.0 / out.numel())
+    net.forward(x)
+    net.backward(B, dU)
+    g_ext = net.grads().astype(np.float64)
+    assert _rel(g_ext, g_loss) <= 1e-5
+    _, gref = S.loss_grad(w, phi, tgt)
+    assert _rel(g_ext, gref) <= 5e-2
+    net.forward(x)
+    net.backward(B, (3.0 * dU).contiguous())
+    assert _rel(net.grads().astype(np.float64), 3.0 * g_ext) <= 1e-5
+    from paper_2105_09671_amd import _lib as L
+    net.infer(x, torch.empty_like(x))               # no activations kept: refused
+    with pytest.raises(L.AcError):
+        net.backward(B, dU)
+    with pytest.raises(ValueError):
+        net.backward(1, dU)                         # wrong batch for the gradient tensor
+    net.close()
