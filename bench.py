@@ -36,9 +36,13 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 NSTEPS = 20000
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_tile2d_reg_circle2048_fp32.json")
-KERNEL_SRCS = [os.path.join(ROOT, "paper_2105_09671_amd", "csrc", f)
-               for f in ("stencil2d.hip", "reg2d.h", "ac_internal.h")]
+REG3D_MAX_DEPTH = 8     # FP32
+CSRC = os.path.join(ROOT, "paper_2105_09671_amd", "csrc")
+# stored HBM-traffic counters: (summary file, the kernel sources they were taken on)
+TRAFFIC_HEADLINE = (os.path.join(ROOT, "profiles", "traffic_tile2d_reg_circle2048_fp32.json"),
+                    [os.path.join(CSRC, f) for f in ("stencil2d.hip", "reg2d.h", "update.h")])
+TRAFFIC_BATCH = (os.path.join(ROOT, "profiles", "traffic_batched_phase_batch512_fp32.json"),
+                 [os.path.join(CSRC, f) for f in ("batched.hip", "reg2d.h", "update.h")])
 
 
 def log(*a):
@@ -69,14 +73,15 @@ def timed(fn, reps: int):
     return ts[len(ts) // 2]
 
 
-def measured_traffic():
+def measured_traffic(which=TRAFFIC_HEADLINE):
     """HBM bytes per launch from stored rocprofv3 counters, if they were taken on
-    the current kernel source; else None."""
-    if not os.path.exists(TRAFFIC_FILE):
+    the current source of the kernel; else None."""
+    path, srcs = which
+    if not os.path.exists(path):
         return None
-    with open(TRAFFIC_FILE) as f:
+    with open(path) as f:
         t = json.load(f)
-    if t.get("src_sha256") != src_hash(KERNEL_SRCS):
+    if t.get("src_sha256") != src_hash(srcs):
         return None
     return t.get("hbm_bytes_per_launch")
 
@@ -111,7 +116,7 @@ def cpu_baseline(phi0, g, budget_s: float) -> dict:
                       % (steps, NSTEPS, threads, el, s1, cells * s1 / el1 / 1e9)}
 
 
-def extras(api, torch, workloads, params) -> dict:
+def extras(api, torch, workloads, params, cpu_budget) -> dict:
     out = {}
     # FP64 circle, same workload
     g = workloads.circle2048()
@@ -123,26 +128,32 @@ def extras(api, torch, workloads, params) -> dict:
                               "ms": round(t * 1e3, 2), "plan": api.plan2d(g.nx, g.ny, NSTEPS, torch.float64)}
     log("extra circle2048_fp64", out["circle2048_fp64"])
     del phi
-    # 3D 256^3 FP32, 2000 steps, every temporal-blocking depth
+    # 3D 256^3 FP32, 2000 steps, every temporal-blocking depth: on the z-streamed
+    # register kernel (the default for this grid) and on the LDS kernel
     g3 = workloads.sep256c()
     p3 = torch.from_numpy(g3.initial()).float().cuda()
     n3 = g3.nx * g3.ny * g3.nz
-    depth = {}
-    for k in range(1, 9):
-        tune = {"tb_depth": k, "tile_x": 32 if k <= 4 else 64, "tile_y": 32, "tile_z": 32}
-        try:
-            t = timed(lambda: api.step3d(p3, g3.h, g3.dt, g3.eps, 2000, tune=tune), 1)
-        except Exception as ex:   # an infeasible tile for this depth
-            depth[k] = {"error": str(ex)}
-            continue
-        gl = n3 * 2000 / t / 1e9
-        depth[k] = {"GLUPS": round(gl, 2), "f_eff": round(gl * 8 / HBM_PEAK_GBS, 3),
-                    "tune": tune}
+    by_kernel = {}
+    for kname, kern, maxk in (("reg3d", 5, REG3D_MAX_DEPTH), ("stream3d_lds", 2, 8)):
+        depth = {}
+        for k in range(1, maxk + 1):
+            tune = ({"kernel": 5, "tb_depth": k, "tile_x": 64, "tile_y": 32} if kern == 5 else
+                    {"kernel": 2, "tb_depth": k, "tile_x": 32 if k <= 4 else 64, "tile_y": 32,
+                     "tile_z": 32})
+            try:
+                t = timed(lambda: api.step3d(p3, g3.h, g3.dt, g3.eps, 2000, tune=tune), 1)
+            except Exception as ex:   # an infeasible tile for this depth
+                depth[k] = {"error": str(ex)}
+                continue
+            gl = n3 * 2000 / t / 1e9
+            depth[k] = {"GLUPS": round(gl, 2), "f_eff": round(gl * 8 / HBM_PEAK_GBS, 3),
+                        "plan": api.plan3d(256, 256, 256, 2000, tune=tune)}
+        by_kernel[kname] = depth
     t = timed(lambda: api.step3d(p3, g3.h, g3.dt, g3.eps, 2000), 1)
     gl = n3 * 2000 / t / 1e9
     out["sep256c_fp32"] = {"GLUPS": round(gl, 2), "f_eff": round(gl * 8 / HBM_PEAK_GBS, 3),
                            "ms": round(t * 1e3, 2), "plan": api.plan3d(256, 256, 256, 2000),
-                           "by_depth": depth}
+                           "by_depth": by_kernel}
     log("extra sep256c_fp32", {k: v for k, v in out["sep256c_fp32"].items() if k != "by_depth"})
     del p3
     # sphere: R^2 = R0^2 - 4t
@@ -155,18 +166,7 @@ def extras(api, torch, workloads, params) -> dict:
     out["sphere256_fp32"] = {"R_T": round(R, 6), "R_law": round(law, 6),
                              "err_over_h": round(abs(R - law) / gs.h, 3)}
     del ps
-    # 512 uneven grids, 5000 steps, one persistent launch replayed from a hipGraph
-    insts = workloads.batch_instances(512)
-    b = api.Batch([gi.initial().astype("float32") for gi in insts],
-                  [(gi.h, gi.dt, gi.eps) for gi in insts])
-    info = b.step(5000)                       # builds and caches the plan + graph
-    torch.cuda.synchronize()
-    t = timed(lambda: b.step(5000), 1)
-    gl = b.cells * 5000 / t / 1e9
-    out["batch512_fp32"] = {"GLUPS": round(gl, 2), "f_eff": round(gl * 8 / HBM_PEAK_GBS, 3),
-                            "ms": round(t * 1e3, 2), "cells": b.cells, "launch": info}
-    log("extra batch512_fp32", out["batch512_fp32"])
-    del b
+    out["batch512_fp32"] = batch512(api, torch, workloads, cpu_budget)
     # learned K=100-step surrogate vs the plain stepper: 256 held-out 256^2
     # grids to T = 2000 steps, judge + fallback included (stored weights)
     import numpy as np
@@ -222,6 +222,92 @@ def extras(api, torch, workloads, params) -> dict:
     log("extra err_trace_2048", out["err_trace_2048"])
     del p32, p64
     return out
+
+
+def batch512(api, torch, workloads, cpu_budget: float) -> dict:
+    """512 uneven 2D grids (sides 96..1024, m 3..8, mixed starts), FP32, 5000
+    steps per call, replayed from the cached hipGraph: the default graph of one
+    launch per temporal block (the line's figure), the single persistent launch
+    with a phase barrier per block, and the plan the autotuner picks for this
+    batch.  Its own roofline (the batched tile kernel: algorithmic 8 B per
+    update, tb_depth updates per cell and launch, over the mean launch time of
+    the graph), and the FP64 oracle on a bounded number of steps of all 512
+    grids on every host core."""
+    n = 5000
+    insts = workloads.batch_instances(512)
+    fields = [gi.initial().astype("float32") for gi in insts]
+    prm = [(gi.h, gi.dt, gi.eps) for gi in insts]
+    b = api.Batch(fields, prm)
+    cells = b.cells
+    modes = {}
+    try:
+        for name, persistent in (("graph", False), ("persistent", True)):
+            api.batched_persistent(persistent)
+            info = b.step(n)                      # builds and caches the plan + graph
+            torch.cuda.synchronize()
+            t = timed(lambda: b.step(n), 1)
+            api.check()
+            modes[name] = {"GLUPS": round(cells * n / t / 1e9, 2), "ms": round(t * 1e3, 2),
+                           "launch": info}
+            log("extra batch512_fp32 %s" % name, modes[name])
+    finally:
+        api.batched_persistent(False)
+    api.tune_clear()
+    best = b.autotune(probe_steps=200)
+    info = b.step(n)
+    torch.cuda.synchronize()
+    t = timed(lambda: b.step(n), 1)
+    modes["autotuned_graph"] = {"GLUPS": round(cells * n / t / 1e9, 2), "ms": round(t * 1e3, 2),
+                                "tune": best, "launch": info}
+    log("extra batch512_fp32 autotuned_graph", modes["autotuned_graph"])
+    api.tune_clear()
+    g = modes["graph"]
+    launches = g["launch"]["blocks"]
+    sec = g["ms"] / 1e3
+    alg = 8.0 * cells * n / launches
+    traffic = measured_traffic(TRAFFIC_BATCH)
+    res = {"GLUPS": g["GLUPS"], "f_eff": round(g["GLUPS"] * 8 / HBM_PEAK_GBS, 3), "ms": g["ms"],
+           "cells": cells, "mode": "graph of one launch per temporal block (built-in tile)",
+           "modes": modes,
+           "roofline": {"bound": "hbm", "kernel": "batched_phase_kernel<float>",
+                        "achieved": round(alg / (sec / launches) / 1e9, 1), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(alg / (sec / launches) / 1e9 / HBM_PEAK_GBS, 4),
+                        "traffic": traffic,
+                        "frac_meas": (round(traffic / (sec / launches) / 1e9 / HBM_PEAK_GBS, 4)
+                                      if traffic is not None else None),
+                        "algorithmic_bytes_per_launch": int(alg),
+                        "avg_launch_us": round(sec / launches * 1e6, 3), "launches_timed": launches}}
+    del b
+    if cpu_budget > 0:
+        res["cpu_baseline"] = cpu_baseline_batch(fields, prm, cells, n, cpu_budget)
+        log("extra batch512_fp32 cpu_baseline", res["cpu_baseline"])
+    return res
+
+
+def cpu_baseline_batch(fields, prm, cells: int, nsteps: int, budget_s: float) -> dict:
+    """The FP64 oracle on all 512 grids, every host core, as many steps as fit
+    about budget_s."""
+    import numpy as np
+    import oracle
+    threads = oracle.cpus_available()
+    f64 = [f.astype(np.float64) for f in fields]
+    hs, dts, es = ([p[i] for p in prm] for i in range(3))
+    probe = 2
+    while True:
+        t0 = time.perf_counter()
+        oracle.step_batched2d(f64, hs, dts, es, probe, threads)
+        el = time.perf_counter() - t0
+        if el > 0.05 * budget_s or probe >= nsteps // 4:
+            break
+        probe *= 4
+    steps = int(max(2, min(nsteps, budget_s / max(el / probe, 1e-9))))
+    t0 = time.perf_counter()
+    oracle.step_batched2d(f64, hs, dts, es, steps, threads)
+    el = time.perf_counter() - t0
+    return {"value": round(cells * steps / el / 1e9, 4), "unit": "GLUPS", "cores": threads,
+            "kind": "oracle",
+            "sample": "all 512 grids (%d cells), FP64 plain loops, first %d of the %d steps on %d "
+                      "threads (%.1f s)" % (cells, steps, nsteps, threads, el)}
 
 
 def hbm_resident(api, torch, workloads) -> dict:
@@ -325,6 +411,15 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_ref:
+        # a device-to-device copy of 256 MiB: the scale reference of the counters
+        a = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     if args.only:
         print(json.dumps(only(args.only)))
         return
@@ -336,14 +431,6 @@ def main():
     plan = api.plan2d(g.nx, g.ny, NSTEPS, torch.float32)
     log("plan", plan)
 
-    if args.copy_ref:
-        a = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
-        b = torch.empty_like(a)
-        a.fill_(1.0)
-        torch.cuda.synchronize()
-        b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
 
     for i in range(args.warmup):
         api.step2d(phi, g.h, g.dt, g.eps, NSTEPS)
@@ -409,7 +496,8 @@ def main():
     check = {"R_T": round(R, 6), "R_law": round(law, 6), "err_over_h": round(abs(R - law) / g.h, 3)}
     log("radius check", check)
 
-    extra = {} if args.no_extra else extras(api, torch, workloads, params)
+    extra = {} if args.no_extra else extras(api, torch, workloads, params,
+                                              0 if args.no_cpu else args.cpu_budget)
     cpu = None
     if not args.no_cpu:
         log("cpu baseline ...")

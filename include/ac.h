@@ -65,7 +65,8 @@ typedef enum { AC_F32 = 0, AC_F64 = 1 } ac_dtype;
  *             _REGW tile_x = 128 (its default), tile_y a multiple of 8 up to
  *             128 and nx >= 128, _INPLACE tile_x = 64; batches take 64-wide
  *             tiles only); 3D: AC_KERNEL_3D_STREAM / _REG (_REG needs tile_x =
- *             64, tile_y a multiple of 4 up to 32 and tb_depth <= 4)
+ *             64, tile_y a multiple of 4 up to 32 and tb_depth <= 8 in
+ *             FP32, <= 6 in FP64)
  * Any valid choice gives bitwise the same result: every cell is always
  * updated by the same expression from the same neighbour values. */
 typedef struct {
@@ -113,7 +114,7 @@ enum {
     AC_KERNEL_2D_REG = 4,      /* 64-wide tiles held in registers (16 rows per wave), x
                                 * neighbours by cross-lane shifts, tb_depth steps per launch */
     AC_KERNEL_3D_REG = 5,      /* z-streamed 64-wide tiles held in registers (4 rows per
-                                * wave), tb_depth 1..4 levels per launch */
+                                * wave), tb_depth 1..8 (FP64 1..6) levels per launch */
     AC_KERNEL_2D_REGW = 6      /* 128-wide tiles held in registers, two adjacent columns
                                 * per lane (8 rows per wave), tb_depth steps per launch;
                                 * needs nx >= 128 */
@@ -338,6 +339,7 @@ ac_status ac_judge_2d(const float *a, const float *b, int32_t batch, int32_t nx,
                       double h, int32_t window, float *iface_err, float *l2_err,
                       void *workspace, void *stream);
 int64_t ac_judge_workspace_bytes(int32_t batch);
+
 
 /* Synchronise `stream` and report any pending HIP error, or a batched grid
  * barrier timeout, as AC_ERR_HIP. */

@@ -314,7 +314,7 @@ ac_status make_plan3d(int nx, int ny, int nz, int64_t nsteps, size_t elem, const
         return fail(AC_ERR_UNSUPPORTED, "3D register tiles need nx * ny < 2^31 (%d x %d)", nx, ny);
     if (kern == 0 && !shape_given && plane32) {
         const int rk = tune && tune->tb_depth ? tune->tb_depth : (f64 ? 3 : 4);
-        if (rk <= ac::kReg3dMaxDepth) {
+        if (rk <= ac::reg3d_max_depth(elem)) {
             const int64_t wgs = (int64_t)ac::reg2d_tiles_1d(nx, 64, rk) *
                                 ac::reg2d_tiles_1d(ny, 32, rk) * ((nz + 31) / 32);
             const int per_cu =
@@ -338,12 +338,12 @@ ac_status make_plan3d(int nx, int ny, int nz, int64_t nsteps, size_t elem, const
         return fail(AC_ERR_UNSUPPORTED, "tile %dx%dx%d too small for depth %d", LX, LY, LZ, K);
     if (reg) {
         if (LX != 64 || LY % ac::kReg3dRows || LY / ac::kReg3dRows > ac::kReg3dMaxWaves ||
-            K > ac::kReg3dMaxDepth)
+            K > ac::reg3d_max_depth(elem))
             return fail(AC_ERR_UNSUPPORTED,
                         "3D register tiles need tile_x 64, tile_y a multiple of %d up to %d and "
                         "depth <= %d (got %dx%d, depth %d)",
-                        ac::kReg3dRows, ac::kReg3dRows * ac::kReg3dMaxWaves, ac::kReg3dMaxDepth, LX,
-                        LY, K);
+                        ac::kReg3dRows, ac::kReg3dRows * ac::kReg3dMaxWaves, ac::reg3d_max_depth(elem),
+                        LX, LY, K);
         threads = 64 * (LY / ac::kReg3dRows);
     }
     if (!tune || tune->tile_z <= 0) {

@@ -7,42 +7,9 @@
 #include <string>
 
 #include "ac.h"
+#include "update.h"
 
 namespace ac {
-
-// ---------------------------------------------------------------------------
-// The explicit Allen-Cahn update of one cell (section 2.1, Eq. pytorchACeq):
-//   phi' = phi + alpha*(phi - phi^3) + r*(S - 2d*phi),
-//   alpha = dt/eps^2, r = dt/h^2, S = sum of the axis neighbours.
-// The neighbour sum is paired per axis, (x- + x+) + (y- + y+) [+ (z- + z+)],
-// and the remaining products are fused multiply-adds written out explicitly,
-// so every kernel (any tile shape, any temporal-blocking depth) rounds
-// identically.  phi = +-1 and phi = 0 are bitwise fixed points:
-//   c = +-1: c*c = 1, fma(-1, c, c) = 0, and S = 2d*c exactly.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-__device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
-
-template <typename T>
-__device__ __forceinline__ T react_and_diffuse(T c, T s, T two_d, T alpha, T r) {
-    const T lap = fma_(-two_d, c, s);      // S - 2d*c, rounded once
-    const T c2 = c * c;
-    const T re = fma_(-c2, c, c);          // c - c^3
-    const T t = fma_(alpha, re, c);        // c + alpha*(c - c^3)
-    return fma_(r, lap, t);                // + r*(S - 2d*c)
-}
-
-template <typename T>
-__device__ __forceinline__ T update2d(T c, T xm, T xp, T ym, T yp, T alpha, T r) {
-    const T s = (xm + xp) + (ym + yp);
-    return react_and_diffuse<T>(c, s, T(4), alpha, r);
-}
-
-template <typename T>
-__device__ __forceinline__ T update3d(T c, T xm, T xp, T ym, T yp, T zm, T zp, T alpha, T r) {
-    const T s = ((xm + xp) + (ym + yp)) + (zm + zp);
-    return react_and_diffuse<T>(c, s, T(6), alpha, r);
-}
 
 // ----------------------------------------------------------- launchers ----
 // 2D tiled kernel: each workgroup loads a (LX x LY) tile including a `halo`
@@ -97,8 +64,10 @@ hipError_t launch_stream3d(const T *src, T *dst, int nx, int ny, int nz, T alpha
 size_t stream3d_lds_bytes(const Tile3D &t, size_t elem);
 int stream3d_cells_per_thread(const Tile3D &t);
 // register-resident 3D variant: LX = 64, kReg3dRows rows per wave, at most
-// kReg3dMaxWaves waves, depth 1..4; LDS row exchange [2][K][2 rows][waves][64]
-constexpr int kReg3dRows = 4, kReg3dMaxWaves = 8, kReg3dMaxDepth = 4;
+// kReg3dMaxWaves waves, depth 1..reg3d_max_depth; LDS row exchange
+// [2][K][2 rows][waves][64]
+constexpr int kReg3dRows = 4, kReg3dMaxWaves = 8;
+inline int reg3d_max_depth(size_t elem) { return elem == 8 ? 6 : 8; }
 inline size_t reg3d_lds_bytes(int K, int LY, size_t elem) {
     return (size_t)4 * K * (LY / kReg3dRows) * 64 * elem;
 }

@@ -1,0 +1,218 @@
+// 3x3 convolution (replicate padding) of NHWC bf16 activations as an implicit
+// GEMM whose A operand is read from an input patch staged in LDS.
+//
+// A workgroup of 4 waves computes an output tile of TY = 4 RW rows x 64
+// columns of one image and CN output channels (blockIdx.y picks the channel
+// slice).  Wave w owns tile rows RW w .. RW w + RW - 1, i.e. 64 RW pixels = 4 RW
+// A fragments of 16 pixels, times CN / 16 B fragments.
+//
+// K runs over 32-channel chunks of the input and, per chunk, over the 9 taps.
+// For a chunk the workgroup copies the (TY + 2) x 66 pixel patch around its
+// tile (rows and columns clamped to the image: the replicate padding) into
+// LDS, 32 channels per pixel at a pitch of 40 bf16 (80 bytes: sixteen
+// consecutive pixels of one 16-byte channel group then fall on sixteen
+// disjoint 4-bank groups, so a fragment read has no bank conflict).  The A
+// fragment of tap (dy, dx) for the 16 pixels starting at tile column c of row
+// r is at ((r + dy) * 66 + c + dx) * 40 + 8 * (lane / 16) + ...: a per-lane
+// base plus a compile-time offset, so the K loop does no address arithmetic.
+// B fragments (weights) are read from global memory in fragment order
+// ([chunk][tap][16-channel tile][lane][8]; 1 KiB per wave and fragment,
+// L2-resident), one K step ahead of their use.
+//
+// Channels may come from two sources: the first LOWC channels from a tensor
+// at half resolution, read at (y / 2, x / 2) (the nearest 2x upsampling of a
+// decoder input, fused into the load), the rest from a full-resolution view.
+//
+// Epilogue: bias, relu, rounding to bf16, then the tile is staged in LDS
+// (pitch CN + 8) and written with 16-byte stores; optionally also the 2 x 2
+// average of the tile (the pooled input of the next level), or -- for the
+// last layer, CN = 32 -- the 1x1 head and the residual, out = phi + hb +
+// sum_c a_c wh_c in FP32, in channel order.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "sur_kernels.h"
+
+namespace ac {
+namespace sur {
+
+constexpr int PC = 32;          // channels per patch chunk
+constexpr int PP = PC + 8;      // LDS pitch of a patch pixel (bf16 units)
+constexpr int PW = 66;          // patch width: 64 columns + the two pad columns
+
+template <int RW>
+constexpr int patch_lds_bytes() { return (4 * RW + 2) * PW * PP * 2; }
+template <int RW, int CN>
+constexpr int stage_lds_bytes() { return 4 * RW * 64 * (CN + 8) * 2; }
+template <int RW, int CN>
+constexpr int conv3p_lds_bytes() {
+    return patch_lds_bytes<RW>() > stage_lds_bytes<RW, CN>() ? patch_lds_bytes<RW>()
+                                                             : stage_lds_bytes<RW, CN>();
+}
+
+// Row-major tile grid over B images of H x W: (image, tile row, tile column);
+// consecutive workgroups take horizontally, then vertically adjacent tiles of
+// one image, and with the XCD-aware numbering (xcd_tile) each XCD takes a
+// contiguous band, so the halo rows two tiles share are read through one L2.
+template <int CIN, int CN, int RW, int LOWC, bool POOL, bool HEAD>
+__global__ void __launch_bounds__(256)
+conv3_patch_kernel(View X, View Xlo, int B, int H, int W, const bf16_t *__restrict__ Wf,
+                   const float *__restrict__ bias, int Cout, View Y, View P,
+                   const float *__restrict__ wh, const float *__restrict__ hb,
+                   const float *__restrict__ phi, float *__restrict__ out)
+{
+    static_assert(CIN % PC == 0 && LOWC % PC == 0 && LOWC <= CIN, "32-channel chunks");
+    static_assert(CN == 32 || CN == 64, "channel slice of 32 or 64");
+    static_assert(!HEAD || CN == 32, "the head needs all 32 channels of a pixel");
+    constexpr int TY = 4 * RW, NI = 4 * RW, NJ = CN / 16, NCH = CIN / PC;
+    extern __shared__ __align__(16) bf16_t lds[];
+    const int tiles_x = (W + 63) >> 6, tiles_y = (H + TY - 1) / TY;
+    const int ntiles = B * tiles_y * tiles_x;
+    const int tile = xcd_tile(ntiles);
+    if (tile >= ntiles) return;                      // padding workgroup (whole group)
+    const int n = tile / (tiles_y * tiles_x), rem = tile - n * tiles_y * tiles_x;
+    const int y0 = (rem / tiles_x) * TY, x0 = (rem % tiles_x) * 64;
+    const int n0 = blockIdx.y * CN;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int lr = lane & 15, lq = lane >> 4;
+
+    // per-lane A base of fragment i = (row r, 16-pixel group g), bf16 units
+    int abase[NI];
+#pragma unroll
+    for (int i = 0; i < NI; ++i)
+        abase[i] = ((RW * w + i / 4) * PW + 16 * (i % 4) + lr) * PP + 8 * lq;
+    // B fragment (chunk, tap, j): Wf + (((chunk * 9 + tap) * (Cout / 16) + n0 / 16 + j) * 64 + lane) * 8
+    const int ntile16 = Cout >> 4;
+    const bf16_t *wlane = Wf + ((size_t)(n0 >> 4) * 64 + lane) * 8;
+
+    floatx4 acc[NI][NJ] = {};
+    bf16x8 bcur[NJ], bnext[NJ];
+    auto loadB = [&](int chunk, int tap, bf16x8 (&dst)[NJ]) {
+#pragma unroll
+        for (int j = 0; j < NJ; ++j)
+            dst[j] = *reinterpret_cast<const bf16x8 *>(
+                wlane + ((size_t)(chunk * 9 + tap) * ntile16 + j) * 512);
+    };
+    loadB(0, 0, bcur);
+
+    for (int ch = 0; ch < NCH; ++ch) {
+        // ---- stage the patch of this 32-channel chunk (clamped = replicate pad)
+        const bool low = ch * PC < LOWC;
+        const View S = low ? Xlo : X;
+        const int cofs = low ? ch * PC : ch * PC - LOWC;
+        const int Hs = low ? (H >> 1) : H, Ws = low ? (W >> 1) : W;
+        if (ch > 0) __syncthreads();                 // every wave is done with the previous chunk
+        constexpr int NV = (TY + 2) * PW * 4;        // 16-byte vectors in the patch
+#pragma unroll 4
+        for (int v = t; v < NV; v += 256) {
+            const int q = v & 3, pix = v >> 2, pr = pix / PW, pc = pix - pr * PW;
+            int gy = min(max(y0 - 1 + pr, 0), H - 1), gx = min(max(x0 - 1 + pc, 0), W - 1);
+            if (low) { gy >>= 1; gx >>= 1; }
+            const uint4 val = *reinterpret_cast<const uint4 *>(
+                S.p + ((size_t)(n * Hs + gy) * Ws + gx) * S.Cs + S.Co + cofs + 8 * q);
+            *reinterpret_cast<uint4 *>(lds + pix * PP + 8 * q) = val;
+        }
+        __syncthreads();
+        // ---- 9 taps of this chunk: A from the patch, B one step ahead
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) {
+            const int dy = tap / 3, dx = tap % 3;
+            if (tap < 8) loadB(ch, tap + 1, bnext);
+            else if (ch + 1 < NCH) loadB(ch + 1, 0, bnext);
+            bf16x8 a[NI];
+#pragma unroll
+            for (int i = 0; i < NI; ++i)
+                a[i] = *reinterpret_cast<const bf16x8 *>(lds + abase[i] + (dy * PW + dx) * PP);
+#pragma unroll
+            for (int i = 0; i < NI; ++i)
+#pragma unroll
+                for (int j = 0; j < NJ; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bcur[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) bcur[j] = bnext[j];
+        }
+    }
+
+    // ---- epilogue: bias + relu -> bf16, staged in LDS as [pixel][CN]
+    __syncthreads();                                 // the patch is dead
+    constexpr int SP = CN + 8;
+#pragma unroll
+    for (int i = 0; i < NI; ++i)
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            const int col = 16 * j + lr;
+            const float bv = bias[n0 + col];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int pix = (RW * w + i / 4) * 64 + 16 * (i % 4) + 4 * lq + q;
+                float v = acc[i][j][q] + bv;
+                v = v > 0.f ? v : 0.f;
+                lds[pix * SP + col] = f2bf(v);
+            }
+        }
+    __syncthreads();
+    if constexpr (HEAD) {
+        // one thread per pixel: out = phi + (hb + sum_c a_c wh_c), c in order
+        for (int pix = t; pix < TY * 64; pix += 256) {
+            const int y = y0 + (pix >> 6), x = x0 + (pix & 63);
+            if (y >= H || x >= W) continue;
+            const bf16_t *a = lds + pix * SP;
+            float s = hb[0];
+#pragma unroll
+            for (int c = 0; c < 32; ++c) s += bf2f(a[c]) * wh[c];
+            const size_t g = (size_t)(n * H + y) * W + x;
+            out[g] = phi[g] + s;
+        }
+        return;
+    }
+    constexpr int CQ = CN / 8;                       // 16-byte groups per pixel
+    for (int v = t; v < TY * 64 * CQ; v += 256) {
+        const int q = v % CQ, pix = v / CQ;
+        const int y = y0 + pix / 64, x = x0 + (pix & 63);
+        if (y >= H || x >= W) continue;
+        *reinterpret_cast<uint4 *>(Y.p + ((size_t)(n * H + y) * W + x) * Y.Cs + Y.Co + n0 + 8 * q) =
+            *reinterpret_cast<const uint4 *>(lds + pix * SP + 8 * q);
+    }
+    if constexpr (POOL) {
+        // 2 x 2 averages of the tile (TY and the tile origin are even), summed
+        // in the order (y, x), (y, x+1), (y+1, x), (y+1, x+1) like pool_kernel
+        const int Ho = H >> 1, Wo = W >> 1;
+        for (int v = t; v < (TY / 2) * 32 * CQ; v += 256) {
+            const int q = v % CQ, pp = v / CQ, py = pp / 32, px = pp % 32;
+            const int oy = (y0 >> 1) + py, ox = (x0 >> 1) + px;
+            if (oy >= Ho || ox >= Wo) continue;
+            float s[8] = {};
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+                const int pix = (2 * py + (d >> 1)) * 64 + 2 * px + (d & 1);
+                const uint4 u = *reinterpret_cast<const uint4 *>(lds + pix * SP + 8 * q);
+                const bf16_t *e = reinterpret_cast<const bf16_t *>(&u);
+#pragma unroll
+                for (int k = 0; k < 8; ++k) s[k] += bf2f(e[k]);
+            }
+            uint4 o;
+            bf16_t *oe = reinterpret_cast<bf16_t *>(&o);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) oe[k] = f2bf(0.25f * s[k]);
+            *reinterpret_cast<uint4 *>(P.p + ((size_t)(n * Ho + oy) * Wo + ox) * P.Cs + P.Co + n0 + 8 * q) = o;
+        }
+    }
+}
+
+// FP32 canonical weights [Cout][3][3][Cin] -> bf16 fragment order
+// [Cin/32][9][Cout/16][64 lanes][8]: lane l of tile (chunk, tap, jt) holds
+// output channel 16 jt + l % 16, input channels 32 chunk + 8 (l / 16) .. + 7.
+__global__ void pack_frag_weights_kernel(const float *w, int Cout, int Cin, bf16_t *out)
+{
+    const int total = Cout * 9 * Cin;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+        const int e = i & 7, lane = (i >> 3) & 63, rest = i >> 9;
+        const int jt = rest % (Cout >> 4), r2 = rest / (Cout >> 4), tap = r2 % 9, chunk = r2 / 9;
+        const int co = 16 * jt + (lane & 15), ci = 32 * chunk + 8 * (lane >> 4) + e;
+        out[i] = f2bf(w[((size_t)co * 9 + tap) * Cin + ci]);
+    }
+}
+
+}  // namespace sur
+}  // namespace ac

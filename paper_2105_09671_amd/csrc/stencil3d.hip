@@ -108,6 +108,8 @@ reg3d_kernel(const T *__restrict__ src, T *__restrict__ dst, int nx, int ny, int
 template <typename T, int K, bool SR>
 static const void *reg3d_ptr() { return (const void *)reg3d_kernel<T, K, SR>; }
 
+// Depths up to reg3d_max_depth: FP32 8 (169 VGPRs at depth 8), FP64 6 (211
+// VGPRs; depth 8 would spill).
 template <typename T, bool SR>
 static const void *reg3d_kernel_k(int K) {
     switch (K) {
@@ -115,8 +117,15 @@ static const void *reg3d_kernel_k(int K) {
     case 2: return reg3d_ptr<T, 2, SR>();
     case 3: return reg3d_ptr<T, 3, SR>();
     case 4: return reg3d_ptr<T, 4, SR>();
-    default: return nullptr;
+    case 5: return reg3d_ptr<T, 5, SR>();
+    case 6: return reg3d_ptr<T, 6, SR>();
+    default: break;
     }
+    if constexpr (sizeof(T) == 4) {
+        if (K == 7) return reg3d_ptr<T, 7, SR>();
+        if (K == 8) return reg3d_ptr<T, 8, SR>();
+    }
+    return nullptr;
 }
 
 // The read mode per grid (measured on MI355X, A/B on one box): the selected

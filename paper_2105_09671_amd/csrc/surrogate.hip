@@ -27,6 +27,7 @@
 #include <vector>
 
 #include "ac_internal.h"
+#include "conv_patch.h"
 #include "sur_kernels.h"
 
 namespace ac {
@@ -620,7 +621,8 @@ struct ac_sur {
     int64_t woff[NL], boff[NL];     // canonical flat offsets (weights, bias)
     int64_t kwoff[NL];              // offsets into the bf16 kernel-layout weights
     float *w32 = nullptr, *m = nullptr, *v = nullptr, *g = nullptr, *g_first = nullptr;
-    bf16_t *wb = nullptr, *wt = nullptr;
+    bf16_t *wb = nullptr, *wt = nullptr, *wf = nullptr;   // wf: fragment order (3x3, Cin >= 32)
+    bf16_t *u2lo = nullptr, *u1lo = nullptr;             // decoder 1x1 outputs at low resolution (inference)
     float *out = nullptr, *dU = nullptr, *loss = nullptr;
     bf16_t *x0, *e1a, *cat1, *p1, *e2a, *cat2, *p2, *bt, *d2, *d1;
     bf16_t *dd1, *dcat1, *du1, *dd2, *dcat2, *du2, *dbt, *dp2, *de2a, *dp1, *de1a;
@@ -660,6 +662,23 @@ void launch_fwd(ac_sur *s, int l, View X, int lgcin, int B, int H, int W, View Y
                        H, W, wk_of(s, l), bias_of(s, l), L.cout, Y, (int)relu,
                        (const float *)nullptr, (const float *)nullptr, (const float *)nullptr,
                        (float *)nullptr);
+}
+
+// 3x3 layer (relu) from an LDS patch: Y (and the pooled P, or the head
+// output `out`) from X, with the first LOWC input channels from Xlo at half
+// resolution.
+template <int CIN, int CN, int RW, int LOWC, bool POOL, bool HEAD>
+void launch_c3p(ac_sur *s, int l, View X, View Xlo, int B, int H, int W, View Y, View P,
+                const float *phi = nullptr, float *out = nullptr) {
+    const LayerDef &L = kLayers[l];
+    constexpr int lds = conv3p_lds_bytes<RW, CN>();
+    const void *kern = reinterpret_cast<const void *>(&conv3_patch_kernel<CIN, CN, RW, LOWC, POOL, HEAD>);
+    set_lds_limit(kern, lds);
+    const int ntiles = B * ((H + 4 * RW - 1) / (4 * RW)) * ((W + 63) / 64);
+    dim3 grid(xcd_grid(ntiles), L.cout / CN);
+    hipLaunchKernelGGL((conv3_patch_kernel<CIN, CN, RW, LOWC, POOL, HEAD>), grid, dim3(256), lds, s->st,
+                       X, Xlo, B, H, W, s->wf + s->kwoff[l], bias_of(s, l), L.cout, Y, P,
+                       s->w32 + s->woff[L_HEAD], s->w32 + s->boff[L_HEAD], phi, out);
 }
 
 void conv_fwd(ac_sur *s, int l, View X, int B, int H, int W, View Y, bool relu, bool up) {
@@ -745,6 +764,9 @@ void refresh_weights(ac_sur *s) {
                            L.cout, taps, L.cin, cin_pad, s->wb + s->kwoff[l]);
         hipLaunchKernelGGL(transpose_w_kernel, grid1(n), dim3(256), 0, s->st, s->wb + s->kwoff[l],
                            L.cout, taps, cin_pad, s->wt + s->kwoff[l]);
+        if (L.k == 3 && L.cin >= 32)
+            hipLaunchKernelGGL(pack_frag_weights_kernel, grid1(n), dim3(256), 0, s->st,
+                               s->w32 + s->woff[l], L.cout, L.cin, s->wf + s->kwoff[l]);
     }
 }
 
@@ -792,7 +814,8 @@ ac_status ac_sur_create(ac_sur **out, int32_t batch_max, int32_t hw, void *strea
     auto A = [&](void **p, size_t bytes) { if (st == AC_OK) st = sur_alloc(s, p, bytes); };
     A((void **)&s->w32, o * 4); A((void **)&s->m, o * 4); A((void **)&s->v, o * 4);
     A((void **)&s->g, o * 4); A((void **)&s->g_first, 32 * 72 * 4);
-    A((void **)&s->wb, ko * B2); A((void **)&s->wt, ko * B2);
+    A((void **)&s->wb, ko * B2); A((void **)&s->wt, ko * B2); A((void **)&s->wf, ko * B2);
+    A((void **)&s->u2lo, n3 * 64 * B2); A((void **)&s->u1lo, n2 * 32 * B2);
     A((void **)&s->out, n1 * 4); A((void **)&s->dU, n1 * 4); A((void **)&s->loss, 16);
     A((void **)&s->x0, n1 * 8 * B2); A((void **)&s->e1a, n1 * 32 * B2); A((void **)&s->cat1, n1 * 64 * B2);
     A((void **)&s->p1, n2 * 32 * B2); A((void **)&s->e2a, n2 * 64 * B2); A((void **)&s->cat2, n2 * 128 * B2);
@@ -860,19 +883,18 @@ ac_status ac_sur_forward(ac_sur *s, const float *phi_in, float *phi_out, int32_t
     const int B = batch, H = s->H, W = s->W, H2 = H / 2, W2 = W / 2, H4 = H / 4, W4 = W / 4;
     const int n1 = B * H * W;
     hipLaunchKernelGGL(pack_input_kernel, grid1(n1), dim3(256), 0, s->st, phi_in, s->x0, n1);
+    const View none{nullptr, 0, 0};
     conv_fwd(s, L_E1A, V(s->x0, 8), B, H, W, V(s->e1a, 32), true, false);
-    conv_fwd(s, L_E1B, V(s->e1a, 32), B, H, W, V(s->cat1, 64, 32), true, false);
-    hipLaunchKernelGGL(pool_kernel, grid1((long long)n1 / 4 * 4), dim3(256), 0, s->st, V(s->cat1, 64, 32),
-                       32, B, H, W, V(s->p1, 32));
-    conv_fwd(s, L_E2A, V(s->p1, 32), B, H2, W2, V(s->e2a, 64), true, false);
-    conv_fwd(s, L_E2B, V(s->e2a, 64), B, H2, W2, V(s->cat2, 128, 64), true, false);
-    hipLaunchKernelGGL(pool_kernel, grid1((long long)n1 / 16 * 8), dim3(256), 0, s->st, V(s->cat2, 128, 64),
-                       64, B, H2, W2, V(s->p2, 64));
-    conv_fwd(s, L_BT, V(s->p2, 64), B, H4, W4, V(s->bt, 128), true, false);
+    launch_c3p<32, 32, 2, 0, true, false>(s, L_E1B, V(s->e1a, 32), none, B, H, W, V(s->cat1, 64, 32),
+                                          V(s->p1, 32));
+    launch_c3p<32, 64, 2, 0, false, false>(s, L_E2A, V(s->p1, 32), none, B, H2, W2, V(s->e2a, 64), none);
+    launch_c3p<64, 64, 2, 0, true, false>(s, L_E2B, V(s->e2a, 64), none, B, H2, W2, V(s->cat2, 128, 64),
+                                          V(s->p2, 64));
+    launch_c3p<64, 64, 2, 0, false, false>(s, L_BT, V(s->p2, 64), none, B, H4, W4, V(s->bt, 128), none);
     conv_fwd(s, L_U2, V(s->bt, 128), B, H4, W4, V(s->cat2, 128, 0), false, true);
-    conv_fwd(s, L_D2, V(s->cat2, 128), B, H2, W2, V(s->d2, 64), true, false);
+    launch_c3p<128, 64, 2, 0, false, false>(s, L_D2, V(s->cat2, 128), none, B, H2, W2, V(s->d2, 64), none);
     conv_fwd(s, L_U1, V(s->d2, 64), B, H2, W2, V(s->cat1, 64, 0), false, true);
-    conv_fwd(s, L_D1, V(s->cat1, 64), B, H, W, V(s->d1, 32), true, false);
+    launch_c3p<64, 32, 2, 0, false, false>(s, L_D1, V(s->cat1, 64), none, B, H, W, V(s->d1, 32), none);
     float *o = phi_out ? phi_out : s->out;
     hipLaunchKernelGGL(head_fwd_kernel, grid1(n1), dim3(256), 0, s->st, V(s->d1, 32),
                        s->w32 + s->woff[L_HEAD], s->w32 + s->boff[L_HEAD], phi_in, o, n1);
@@ -896,26 +918,23 @@ ac_status ac_sur_infer(ac_sur *s, const float *phi_in, float *phi_out, int32_t b
     const int B = batch, H = s->H, W = s->W, H2 = H / 2, W2 = W / 2, H4 = H / 4, W4 = W / 4;
     const int n1 = B * H * W;
     hipLaunchKernelGGL(pack_input_kernel, grid1(n1), dim3(256), 0, s->st, phi_in, s->x0, n1);
+    const View none{nullptr, 0, 0};
     conv_fwd(s, L_E1A, V(s->x0, 8), B, H, W, V(s->e1a, 32), true, false);
-    conv_fwd(s, L_E1B, V(s->e1a, 32), B, H, W, V(s->cat1, 64, 32), true, false);
-    hipLaunchKernelGGL(pool_kernel, grid1((long long)n1 / 4 * 4), dim3(256), 0, s->st, V(s->cat1, 64, 32),
-                       32, B, H, W, V(s->p1, 32));
-    conv_fwd(s, L_E2A, V(s->p1, 32), B, H2, W2, V(s->e2a, 64), true, false);
-    conv_fwd(s, L_E2B, V(s->e2a, 64), B, H2, W2, V(s->cat2, 128, 64), true, false);
-    hipLaunchKernelGGL(pool_kernel, grid1((long long)n1 / 16 * 8), dim3(256), 0, s->st, V(s->cat2, 128, 64),
-                       64, B, H2, W2, V(s->p2, 64));
-    conv_fwd(s, L_BT, V(s->p2, 64), B, H4, W4, V(s->bt, 128), true, false);
-    conv_fwd(s, L_U2, V(s->bt, 128), B, H4, W4, V(s->cat2, 128, 0), false, true);
-    conv_fwd(s, L_D2, V(s->cat2, 128), B, H2, W2, V(s->d2, 64), true, false);
-    conv_fwd(s, L_U1, V(s->d2, 64), B, H2, W2, V(s->cat1, 64, 0), false, true);
+    launch_c3p<32, 32, 2, 0, true, false>(s, L_E1B, V(s->e1a, 32), none, B, H, W, V(s->cat1, 64, 32),
+                                          V(s->p1, 32));
+    launch_c3p<32, 64, 2, 0, false, false>(s, L_E2A, V(s->p1, 32), none, B, H2, W2, V(s->e2a, 64), none);
+    launch_c3p<64, 64, 2, 0, true, false>(s, L_E2B, V(s->e2a, 64), none, B, H2, W2, V(s->cat2, 128, 64),
+                                          V(s->p2, 64));
+    launch_c3p<64, 64, 2, 0, false, false>(s, L_BT, V(s->p2, 64), none, B, H4, W4, V(s->bt, 128), none);
+    // decoder 1x1 layers at low resolution; the next 3x3 layer reads them
+    // through the nearest upsampling
+    conv_fwd(s, L_U2, V(s->bt, 128), B, H4, W4, V(s->u2lo, 64), false, false);
+    launch_c3p<128, 64, 2, 64, false, false>(s, L_D2, V(s->cat2, 128, 64), V(s->u2lo, 64), B, H2, W2,
+                                             V(s->d2, 64), none);
+    conv_fwd(s, L_U1, V(s->d2, 64), B, H2, W2, V(s->u1lo, 32), false, false);
     // last 3x3 layer with the head and the residual in its epilogue
-    const LayerDef &L = kLayers[L_D1];
-    const int M = n1;
-    dim3 grid(xcd_grid((M + 127) / 128), (L.cout + 31) / 32);
-    hipLaunchKernelGGL((conv_fwd_kernel<3, false, 4, 1, 2, 2, true>), grid, dim3(256), 0, s->st,
-                       V(s->cat1, 64), lg2(L.cin), B, H, W, wk_of(s, L_D1), bias_of(s, L_D1), L.cout,
-                       V(s->d1, 32), 1, s->w32 + s->woff[L_HEAD], s->w32 + s->boff[L_HEAD], phi_in,
-                       phi_out);
+    launch_c3p<64, 32, 2, 32, false, true>(s, L_D1, V(s->cat1, 64, 32), V(s->u1lo, 32), B, H, W, none,
+                                           none, phi_in, phi_out);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "surrogate inference");
     s->have_fwd = false;             // activations are not those of a forward for backward

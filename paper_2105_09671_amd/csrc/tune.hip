@@ -139,9 +139,13 @@ ac_status ac_autotune_3d(int32_t nx, int32_t ny, int32_t nz, int32_t dtype, int6
     if ((e = hipMemsetAsync(a.p, 0, bytes, st)) != hipSuccess) return hip_fail(e, "scratch fill");
     const double h = 1.0 / std::max(std::max(nx, ny), nz), dt = 0.1 * h * h, eps = 4.0 * h;
     std::vector<ac_tune> cands;
+    // LDS tiles (z segments of 32 or 64 planes) and register tiles (64 wide,
+    // 16..32 rows; z segment chosen by the plan)
     const int tiles[][3] = {{32, 16, 32}, {32, 32, 32}, {64, 16, 32}, {64, 32, 32}, {32, 32, 64}};
     for (int k : {1, 2, 3, 4})
-        for (auto &t : tiles) cands.push_back(ac_tune{k, t[0], t[1], t[2]});
+        for (auto &t : tiles) cands.push_back(ac_tune{k, t[0], t[1], t[2], AC_KERNEL_3D_STREAM});
+    for (int k = 2; k <= reg3d_max_depth(elem_size(dtype)); ++k)
+        for (int ly : {16, 24, 32}) cands.push_back(ac_tune{k, 64, ly, 0, AC_KERNEL_3D_REG});
     auto run = [&](const ac_tune &t, bool warm) {
         return ac_step_3d_tuned(a.p, b.p, nx, ny, nz, h, dt, eps, warm ? t.tb_depth : probe_steps,
                                 dtype, &t, stream);

@@ -15,21 +15,24 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in r.stderr
 
 
-def test_traffic_record_is_complete():
+def test_traffic_records_are_complete():
     sys.path.insert(0, ROOT)
     import bench
-    with open(bench.TRAFFIC_FILE) as f:
-        t = json.load(f)
-    for key in ("kernel", "counters", "hbm_bytes_per_launch", "algorithmic_bytes_per_launch",
-                "src", "src_sha256", "command"):
-        assert key in t, key
-    assert set(t["counters"]) == {"FETCH_SIZE", "WRITE_SIZE"}
-    for c in t["counters"].values():
-        assert c["dispatches"] > 0 and c["scale"] > 0 and c["bytes_per_dispatch"] > 0
-    assert abs(t["hbm_bytes_per_launch"] - sum(c["bytes_per_dispatch"]
-                                               for c in t["counters"].values())) < 1.0
-    # the record covers exactly the sources bench hashes, and its command runs
-    # committed files only
-    names = [os.path.basename(p) for p in bench.KERNEL_SRCS]
-    assert [os.path.basename(s) for s in t["src"].split(",")] == names
-    assert "_work" not in t["command"] and "bench.py" in t["command"]
+    for path, srcs in (bench.TRAFFIC_HEADLINE, bench.TRAFFIC_BATCH):
+        if path == bench.TRAFFIC_BATCH[0] and not os.path.exists(path):
+            continue
+        with open(path) as f:
+            t = json.load(f)
+        for key in ("kernel", "counters", "hbm_bytes_per_launch", "algorithmic_bytes_per_launch",
+                    "src", "src_sha256", "command"):
+            assert key in t, key
+        assert set(t["counters"]) == {"FETCH_SIZE", "WRITE_SIZE"}
+        for c in t["counters"].values():
+            assert c["dispatches"] > 0 and c["scale"] > 0 and c["bytes_per_dispatch"] > 0
+        assert abs(t["hbm_bytes_per_launch"] - sum(c["bytes_per_dispatch"]
+                                                   for c in t["counters"].values())) < 1.0
+        # the record covers exactly the sources bench hashes, and its command runs
+        # committed files only
+        names = [os.path.basename(p) for p in srcs]
+        assert [os.path.basename(s) for s in t["src"].split(",")] == names
+        assert "_work" not in t["command"] and "bench.py" in t["command"]

@@ -267,15 +267,19 @@ def test_3d_all_depths(api, dtype):
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_3d_register_kernel(api, dtype):
     """The register-resident 3D kernel (64-wide tiles, 4 rows per wave) at depths
-    1..4 and 1..8 waves, on a grid ragged against every tile and z segment:
-    bitwise the LDS kernel, and the oracle to the usual bar."""
+    1..8 (FP64 1..6) and 1..8 waves, on a grid ragged against every tile and z
+    segment: bitwise the LDS kernel, and the oracle to the usual bar."""
     h, dt, eps = _par(64, 4)
     phi0 = inputs.random_field((37, 45, 70), seed=34).astype(NP[dtype])
     ref = oracle.step3d(phi0.astype(np.float64), h, dt, eps, 13)
     base = _run3d(api, phi0, h, dt, eps, 13, dtype,
                   tune=dict(tb_depth=2, tile_x=24, tile_y=24, tile_z=8, kernel=2))
     assert D.rel_linf(base, ref) <= TOL[dtype]
-    for k, ly, lz in [(1, 4, 5), (2, 16, 8), (3, 8, 16), (4, 32, 8), (4, 12, 64), (3, 32, 37)]:
+    cases = [(1, 4, 5), (2, 16, 8), (3, 8, 16), (4, 32, 8), (4, 12, 64), (3, 32, 37), (5, 32, 8),
+             (6, 16, 12)]
+    if dtype == torch.float32:
+        cases += [(7, 32, 20), (8, 20, 9), (8, 32, 64)]
+    for k, ly, lz in cases:
         tune = dict(tb_depth=k, tile_x=64, tile_y=ly, tile_z=lz, kernel=5)
         p = api.plan3d(70, 45, 37, 13, dtype, tune)
         assert p["kernel"] == 5 and p["threads"] == 64 * ly // 4, p
@@ -310,10 +314,15 @@ def test_3d_plan_kernels(api):
         assert api.plan3d(96, 96, 96, 100, dt_)["kernel"] == 2
         assert api.plan3d(96, 96, 96, 100, dt_, dict(kernel=5))["kernel"] == 5
         assert api.plan3d(1024, 1024, 1024, 100, dt_, dict(kernel=2))["kernel"] == 2
-    for bad in (dict(kernel=5, tb_depth=5), dict(kernel=5, tile_x=32), dict(kernel=5, tile_y=36),
+    for bad in (dict(kernel=5, tb_depth=9), dict(kernel=5, tile_x=32), dict(kernel=5, tile_y=36),
                 dict(kernel=5, tile_y=30), dict(kernel=4)):
         with pytest.raises(L.AcError):
             api.plan3d(256, 256, 256, 100, torch.float32, bad)
+    # register depth limits: FP32 8, FP64 6
+    assert api.plan3d(256, 256, 256, 100, torch.float32, dict(kernel=5, tb_depth=8))["tb_depth"] == 8
+    assert api.plan3d(256, 256, 256, 100, torch.float64, dict(kernel=5, tb_depth=6))["tb_depth"] == 6
+    with pytest.raises(L.AcError):
+        api.plan3d(256, 256, 256, 100, torch.float64, dict(kernel=5, tb_depth=7))
 
 
 @pytest.mark.parametrize("shape", [(1, 1, 1), (1, 1, 9), (9, 1, 1), (1, 7, 1), (2, 3, 4),

@@ -57,12 +57,15 @@ def test_forward_matches_oracle(sur, B, hw):
     net.close()
 
 
-@pytest.mark.parametrize("B,hw", [(3, 20), (2, 32), (1, 64)])
+@pytest.mark.parametrize("B,hw", [(3, 20), (2, 32), (1, 64), (1, 136)])
 def test_infer_matches_forward_and_oracle(sur, B, hw):
-    """The fused inference path (head and residual in the last layer's
-    epilogue) against the unfused forward: the same BF16 activations, so only
-    the FP32 order of the 32-term head sum differs; and against the oracle to
-    the forward's own bar.  B*hw*hw = 1200 leaves a ragged last 128-row tile."""
+    """The fused inference path (decoder 1x1 outputs kept at low resolution and
+    upsampled inside the next 3x3 layer's patch load; head and residual in the
+    last layer's epilogue) against the unfused forward, which stores the
+    upsampled maps and runs the head as its own kernel: the same products in
+    the same order, so bit for bit equal; and against the oracle to the
+    forward's own bar.  Sizes cover grids narrower than a 64-wide tile, odd
+    sizes at the coarse levels (20 -> 10 -> 5) and ragged tiles (136)."""
     w, phi, _ = _case(62, B, hw)
     net = sur.Surrogate(B, hw)
     net.set_weights(w.astype(np.float32))
@@ -70,9 +73,8 @@ def test_infer_matches_forward_and_oracle(sur, B, hw):
     a = net.forward(x).cpu().numpy().astype(np.float64)
     y = torch.full_like(x, float("nan"))
     b = net.infer(x, y).cpu().numpy().astype(np.float64)
-    scale = max(1.0, float(np.max(np.abs(a - phi))))
     assert np.all(np.isfinite(b))
-    assert np.max(np.abs(a - b)) <= 1e-5 * scale
+    assert np.array_equal(a, b)
     ref = S.forward(w, phi)
     U, Ur = b - phi, ref - phi
     assert _rel(U, Ur) <= 1e-2
@@ -142,7 +144,8 @@ def test_backward_of_external_output_gradient(sur):
     """ac_sur_backward with a caller's d loss / d out: fed the mean-squared-error
     gradient 2 (out - target) / n it gives the gradients of the stored-loss
     path (to FP32 summation order) and of the oracle (BF16 bar); the map is
-    linear in d loss / d out (x3 gives 3x the gradients)."""
+    linear in d loss / d out (x2, exact in BF16 and FP32, gives 2x the
+    gradients up to the order of the FP32 atomic sums)."""
     B, hw = 2, 32
     w, phi, tgt = _case(71, B, hw)
     net = sur.Surrogate(B, hw)
@@ -161,8 +164,8 @@ def test_backward_of_external_output_gradient(sur):
     _, gref = S.loss_grad(w, phi, tgt)
     assert _rel(g_ext, gref) <= 5e-2
     net.forward(x)
-    net.backward(B, (3.0 * dU).contiguous())
-    assert _rel(net.grads().astype(np.float64), 3.0 * g_ext) <= 1e-5
+    net.backward(B, (2.0 * dU).contiguous())
+    assert _rel(net.grads().astype(np.float64), 2.0 * g_ext) <= 1e-5
     from paper_2105_09671_amd import _lib as L
     net.infer(x, torch.empty_like(x))               # no activations kept: refused
     with pytest.raises(L.AcError):
