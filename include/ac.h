@@ -340,6 +340,18 @@ ac_status ac_judge_2d(const float *a, const float *b, int32_t batch, int32_t nx,
                       void *workspace, void *stream);
 int64_t ac_judge_workspace_bytes(int32_t batch);
 
+/* ac_judge_2d without a workspace and without allocating, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Same arguments, results and
+ * kernels as ac_judge_2d; the per-grid scratch lives in a fixed device array
+ * of the library (196,608 bytes, kept on each device it runs on until the
+ * process ends), cleared by a kernel at the start of every call.  batch is
+ * limited to 16384: larger batches return AC_ERR_INVALID_ARG before any HIP
+ * call.  Every call on one device shares that array, so calls that overlap on
+ * one GPU (concurrent streams, or host threads) race and must be ordered by
+ * the caller. */
+ac_status ac_judge_2d_noalloc(const float *a, const float *b, int32_t batch, int32_t nx, int32_t ny,
+                              double h, int32_t window, float *iface_err, float *l2_err, void *stream);
 
 /* Synchronise `stream` and report any pending HIP error, or a batched grid
  * barrier timeout, as AC_ERR_HIP. */

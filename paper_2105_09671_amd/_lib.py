@@ -123,6 +123,7 @@ SIGNATURES = {
     "ac_err_3d": ([_vp, _vp, _vp, _vp, _i32, _i32, _i32, _dbl, _dbl, _dbl, _i64, _vp, _vp, _vp],
                   _i32),
     "ac_judge_workspace_bytes": ([_i32], _i64),
+    "ac_judge_2d_noalloc": ([_vp, _vp, _i32, _i32, _i32, _dbl, _i32, _vp, _vp, _vp], _i32),
     "ac_check": ([_vp], _i32),
     "ac_status_string": ([_i32], ctypes.c_char_p),
     "ac_last_error": ([], ctypes.c_char_p),

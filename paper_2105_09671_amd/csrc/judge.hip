@@ -15,12 +15,47 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 
 #include "ac_internal.h"
+
+// Scratch of the allocation-free judge (ac_judge_2d_noalloc): the same three
+// words per grid as the caller's workspace of ac_judge_2d (distance bits,
+// squared-error sum, crossing flags), for at most kJudgeNoallocMaxBatch grids:
+// 192 KiB held on every device the library runs on until the process ends.
+// Host code never passes `scratch` itself to a kernel (on the host it is only
+// a stand-in for the symbol); it takes the device address that
+// hipGetSymbolAddress reports for the current device.
+constexpr int kJudgeNoallocMaxBatch = 16384;
+static __device__ __align__(256) unsigned scratch[3 * kJudgeNoallocMaxBatch];
 
 namespace ac {
 
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per device.
+ac_status scratch_ptr(void **out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(AC_ERR_UNSUPPORTED, "device %d beyond the %d devices the static scratch serves", dev,
+                    kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!p) return fail(AC_ERR_HIP, "hipGetSymbolAddress(scratch) returned null");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return AC_OK;
+}
 
 // Crossing on the edge from cell (i, j) to (i + di, j + dj); returns false if
 // the sign does not change.  Coordinates in cell units (cell (i, j) centre at
@@ -107,19 +142,21 @@ __global__ void judge_zero_kernel(unsigned *dist_bits, float *sq, int *count, in
 
 using namespace ac;
 
-extern "C" {
+namespace {
 
-ac_status ac_judge_2d(const float *a, const float *b, int32_t batch, int32_t nx, int32_t ny,
-                      double h, int32_t window, float *iface_err, float *l2_err, void *workspace,
-                      void *stream)
-{
-    g_err.clear();
-    if (!a || !b || !iface_err || !l2_err || !workspace)
-        return fail(AC_ERR_INVALID_ARG, "null pointer argument");
+ac_status judge_args(const float *a, const float *b, int32_t batch, int32_t nx, int32_t ny, double h,
+                     int32_t window, const float *iface_err, const float *l2_err) {
+    if (!a || !b || !iface_err || !l2_err) return fail(AC_ERR_INVALID_ARG, "null pointer argument");
     if (batch < 1 || nx < 1 || ny < 1 || window < 1 || window > 16 || !(h > 0) || !std::isfinite(h))
         return fail(AC_ERR_INVALID_ARG, "bad judge sizes (batch %d, %d x %d, window %d)", batch, nx, ny, window);
     if (batch > 65535) return fail(AC_ERR_UNSUPPORTED, "batch above 65535");
-    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    return AC_OK;
+}
+
+// The three launches of a judgement; workspace holds 3 * batch words.
+ac_status judge_launch(const float *a, const float *b, int32_t batch, int32_t nx, int32_t ny, double h,
+                       int32_t window, float *iface_err, float *l2_err, void *workspace,
+                       hipStream_t st) {
     unsigned *dist = static_cast<unsigned *>(workspace);
     float *sq = reinterpret_cast<float *>(dist + batch);
     int *cnt = reinterpret_cast<int *>(sq + batch);
@@ -131,6 +168,38 @@ ac_status ac_judge_2d(const float *a, const float *b, int32_t batch, int32_t nx,
                        batch, (size_t)cells, (float)h, iface_err, l2_err);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? AC_OK : hip_fail(e, "judge launch");
+}
+
+}  // namespace
+
+extern "C" {
+
+ac_status ac_judge_2d(const float *a, const float *b, int32_t batch, int32_t nx, int32_t ny,
+                      double h, int32_t window, float *iface_err, float *l2_err, void *workspace,
+                      void *stream)
+{
+    g_err.clear();
+    ac_status s = judge_args(a, b, batch, nx, ny, h, window, iface_err, l2_err);
+    if (s != AC_OK) return s;
+    if (!workspace) return fail(AC_ERR_INVALID_ARG, "null workspace");
+    return judge_launch(a, b, batch, nx, ny, h, window, iface_err, l2_err, workspace,
+                        reinterpret_cast<hipStream_t>(stream));
+}
+
+ac_status ac_judge_2d_noalloc(const float *a, const float *b, int32_t batch, int32_t nx, int32_t ny,
+                              double h, int32_t window, float *iface_err, float *l2_err, void *stream)
+{
+    g_err.clear();
+    ac_status s = judge_args(a, b, batch, nx, ny, h, window, iface_err, l2_err);
+    if (s != AC_OK) return s;
+    if (batch > kJudgeNoallocMaxBatch)
+        return fail(AC_ERR_INVALID_ARG, "batch %d exceeds the %d grids of the static judge scratch",
+                    batch, kJudgeNoallocMaxBatch);
+    void *ws = nullptr;
+    s = scratch_ptr(&ws);
+    if (s != AC_OK) return s;
+    return judge_launch(a, b, batch, nx, ny, h, window, iface_err, l2_err, ws,
+                        reinterpret_cast<hipStream_t>(stream));
 }
 
 int64_t ac_judge_workspace_bytes(int32_t batch) { return (int64_t)batch * 12; }

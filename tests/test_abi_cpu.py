@@ -236,3 +236,15 @@ def test_surrogate_calls_reject_null_handle(lib):
     assert lib.ac_sur_backward(None, A, 1) == L.AC_ERR_INVALID_ARG
     assert lib.ac_sur_forward(None, A, B, 1) == L.AC_ERR_INVALID_ARG
     assert lib.ac_sur_adam_step(None, 1e-3, 0.9, 0.999, 1e-8, 1) == L.AC_ERR_INVALID_ARG
+
+
+def test_noalloc_judge_validation_before_hip(lib):
+    """Size and pointer errors of the allocation-free judge come before any HIP
+    call (batch above the static scratch's 16384 grids included)."""
+    f = lib.ac_judge_2d_noalloc
+    assert f(A, B, 16385, 64, 64, H, 3, C, D, None) == L.AC_ERR_INVALID_ARG
+    assert b"16384" in lib.ac_last_error()
+    assert f(A, B, 0, 64, 64, H, 3, C, D, None) == L.AC_ERR_INVALID_ARG
+    assert f(A, B, 4, 64, 64, H, 17, C, D, None) == L.AC_ERR_INVALID_ARG
+    assert f(0, B, 4, 64, 64, H, 3, C, D, None) == L.AC_ERR_INVALID_ARG
+    assert f(A, B, 4, 64, 64, -1.0, 3, C, D, None) == L.AC_ERR_INVALID_ARG
