@@ -365,6 +365,13 @@ def only(name: str) -> dict:
         api.step3d(p3, g3.h, g3.dt, g3.eps, 200)
         t = timed(lambda: api.step3d(p3, g3.h, g3.dt, g3.eps, 2000), 1)
         return {"workload": name, "GLUPS": round(256 ** 3 * 2000 / t / 1e9, 2), "ms": round(t * 1e3, 2)}
+    if name == "batch3d64":
+        insts = workloads.batch3d_instances(64)
+        b3 = api.Batch3D([g.initial().astype("float32") for g in insts], [(g.h, g.dt, g.eps) for g in insts])
+        info = b3.step(1000)
+        t = timed(lambda: b3.step(1000), 3)
+        return {"workload": name, "GLUPS": round(b3.cells * 1000 / t / 1e9, 2), "ms": round(t * 1e3, 2),
+                "launch": info}
     if name == "hbm16k":
         from paper_2105_09671_amd import inputs
         g = workloads.hbm16k()
@@ -374,6 +381,15 @@ def only(name: str) -> dict:
         sec = timed(lambda: api.step2d(t, g.h, g.dt, g.eps, n), 1)
         return {"workload": name, "GLUPS": round(g.nx * g.ny * n / sec / 1e9, 2),
                 "ms": round(sec * 1e3, 2), "plan": api.plan2d(g.nx, g.ny, n, torch.float32)}
+    if name == "sur_forward":
+        import numpy as np
+        from paper_2105_09671_amd import sur_train
+        from paper_2105_09671_amd.surrogate import Surrogate
+        net = Surrogate(256, 256)
+        net.set_weights(np.load(os.path.join(ROOT, "paper_2105_09671_amd", "weights", "sur256.npz"))["weights"])
+        res = sur_train.forward_rate(net, 256, reps=2)
+        net.close()
+        return {"workload": name, **res}
     if name == "sur256":
         import numpy as np
         from paper_2105_09671_amd import sur_train
@@ -396,7 +412,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=10.0, help="seconds of oracle work")
     ap.add_argument("--copy-ref", action="store_true",
                     help="also run a 256 MiB device copy (counter scale reference)")
-    ap.add_argument("--only", default="", choices=["", "batch512", "sep256c", "hbm16k", "sur256"],
+    ap.add_argument("--only", default="", choices=["", "batch512", "batch3d64", "sep256c", "hbm16k", "sur256", "sur_forward"],
                     help="run one secondary workload alone (to profile its kernels)")
     args = ap.parse_args()
 

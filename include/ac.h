@@ -205,7 +205,10 @@ typedef struct {
  * segment)), captured in a hipGraph and cached like the 2D batch.  Validation
  * as in ac_step_3d per instance, no two buffers may overlap.  The launch shape
  * comes from `tune` (tb_depth 1..4, tile_x, tile_y, tile_z), else the 3D
- * defaults; nsteps not divisible by tb_depth adds one shorter phase.  Result
+ * defaults; nsteps not divisible by tb_depth adds one shorter phase.  Every
+ * instance runs the LDS tile body, except with tune->kernel =
+ * AC_KERNEL_3D_REG in FP32, where instances at least 64 cells wide run the
+ * register tile body on flush 64 x 32 tiles and 32-plane segments.  Result
  * in each phi.  Each instance is stepped exactly as ac_step_3d steps it, bit
  * for bit (the update of a cell does not depend on tile shape or depth). */
 ac_status ac_step_batched_3d(const ac_instance3d *inst, int32_t n_inst, int64_t nsteps,

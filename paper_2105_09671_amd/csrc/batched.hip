@@ -36,6 +36,7 @@
 #include <vector>
 
 #include "reg2d.h"
+#include "reg3d.h"
 #include "stream3d.h"
 #include "tile2d.h"
 
@@ -45,7 +46,8 @@ struct BatchInst {
     void *phi, *work;
     int nx, ny;
     double alpha, r;
-    int nz, tiles_x;   // 3D batches: depth and xy tiles along x
+    int nz, tiles_x;   // 3D batches: depth and xy tiles along x (LDS tiles)
+    int rtiles_x, pad; // 3D batches: xy tiles along x of the register tiles
 };
 
 // sync[0]: items finished (over all phases); sync[1 + x]: tickets taken from
@@ -255,15 +257,62 @@ __device__ void copy_tile3d(const T *src, T *dst, int nx, int ny, int nz, int OX
     }
 }
 
-// 3D batch: items (instance, xy tile, z segment, -); every phase advances each
-// item by K steps with the z-streaming body of ac_step_3d.  Phases are
+// Copy the output region of one register-tile 3D item (flush xy tiles of 64 x
+// 32 cells, z segment of LZ planes) from src to dst.
+template <typename T>
+__device__ void copy_tile3d_reg(const T *src, T *dst, int nx, int ny, int nz, int K, int LZ,
+                                int tiles_x, int tile, int zseg) {
+    int lx0, ox0, ox1, ly0, oy0, oy1;
+    reg2d_tile_span(tile % tiles_x, tiles_x, nx, 64, K, &lx0, &ox0, &ox1);
+    reg2d_tile_span(tile / tiles_x, reg2d_tiles_1d(ny, 32, K), ny, 32, K, &ly0, &oy0, &oy1);
+    const int z0 = zseg * LZ, w = ox1 - ox0, hh = oy1 - oy0, d = min(z0 + LZ, nz) - z0;
+    const long long n = (long long)w * hh * d;
+    for (long long i = threadIdx.x; i < n; i += blockDim.x) {
+        const int x = ox0 + (int)(i % w), y = oy0 + (int)((i / w) % hh), z = z0 + (int)(i / ((long long)w * hh));
+        const size_t c = ((size_t)z * ny + y) * nx + x;
+        dst[c] = src[c];
+    }
+}
+
+// One 3D item for one phase: it.w = 0 runs the LDS z-streaming body on an LX x
+// LY tile and LZ-plane segment, it.w = 1 (FP32, 512 threads) the register
+// body on a flush 64 x 32 tile and LZR-plane segment.  Both give the bits of
+// ac_step_3d.  copy: the final copy phase of the item's output region.
+template <typename T, int K, int CPT>
+__device__ __forceinline__ void batch3d_item(const BatchInst &I, int4 it, int phase, bool copy, int LX,
+                                             int LY, int LZ, int LZR, unsigned char *smem_raw)
+{
+    if (!copy) {
+        const T *src = static_cast<const T *>((phase & 1) ? I.work : I.phi);
+        T *dst = static_cast<T *>((phase & 1) ? I.phi : I.work);
+        if constexpr (sizeof(T) == 4) {
+            if (it.w) {
+                reg3d_body<T, K, kReg3dRows, true>(src, dst, I.nx, I.ny, I.nz, (T)I.alpha, (T)I.r, LZR,
+                                                   I.rtiles_x, it.y, it.z,
+                                                   reinterpret_cast<T *>(smem_raw));
+                return;
+            }
+        }
+        stream3d_body<T, K, CPT>(src, dst, I.nx, I.ny, I.nz, (T)I.alpha, (T)I.r, LX, LY, LZ,
+                                 I.tiles_x, it.y, it.z, smem_raw);
+    } else if (it.w) {
+        copy_tile3d_reg<T>(static_cast<const T *>(I.work), static_cast<T *>(I.phi), I.nx, I.ny, I.nz, K,
+                           LZR, I.rtiles_x, it.y, it.z);
+    } else {
+        copy_tile3d<T>(static_cast<const T *>(I.work), static_cast<T *>(I.phi), I.nx, I.ny, I.nz,
+                       LX - 2 * K, LY - 2 * K, LZ, I.tiles_x, it.y, it.z);
+    }
+}
+
+// 3D batch: items (instance, xy tile, z segment, body); every phase advances each
+// item by K steps with a z-streaming body of ac_step_3d (batch3d_item).  Phases are
 // numbered from phase0 for the phi/work ping-pong, so a second launch can run
 // a shorter remainder phase.  Scheduling as in batched_kernel.
 template <typename T, int K, int CPT>
 __global__ void __launch_bounds__(512)
 batched3d_kernel(const BatchInst *__restrict__ inst, const int4 *__restrict__ items, int n_items,
-                 int LX, int LY, int LZ, int nphase, int phase0, int copy_back, unsigned *sync,
-                 int *err, long long spin_limit, long long wall_limit)
+                 int LX, int LY, int LZ, int LZR, int nphase, int phase0, int copy_back,
+                 unsigned *sync, int *err, long long spin_limit, long long wall_limit)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ unsigned s_ticket;
@@ -284,16 +333,7 @@ batched3d_kernel(const BatchInst *__restrict__ inst, const int4 *__restrict__ it
             unsigned next = 0;
             if (threadIdx.x == 0) next = atomicAdd(tickets, 1u);
             const BatchInst I = inst[it.x];
-            if (b < nphase) {
-                const int g = phase0 + b;
-                const T *src = static_cast<const T *>((g & 1) ? I.work : I.phi);
-                T *dst = static_cast<T *>((g & 1) ? I.phi : I.work);
-                stream3d_body<T, K, CPT>(src, dst, I.nx, I.ny, I.nz, (T)I.alpha, (T)I.r, LX, LY,
-                                         LZ, I.tiles_x, it.y, it.z, smem_raw);
-            } else {
-                copy_tile3d<T>(static_cast<const T *>(I.work), static_cast<T *>(I.phi), I.nx, I.ny,
-                               I.nz, LX - 2 * K, LY - 2 * K, LZ, I.tiles_x, it.y, it.z);
-            }
+            batch3d_item<T, K, CPT>(I, it, phase0 + b, b >= nphase, LX, LY, LZ, LZR, smem_raw);
             if (threadIdx.x == 0) s_ticket = next;
             __syncthreads();
             t = s_ticket;
@@ -310,7 +350,7 @@ batched3d_kernel(const BatchInst *__restrict__ inst, const int4 *__restrict__ it
 template <typename T, int K, int CPT>
 __global__ void __launch_bounds__(512)
 batched3d_phase_kernel(const BatchInst *__restrict__ inst, const int4 *__restrict__ items,
-                       int n_items, int LX, int LY, int LZ, int phase, int copy)
+                       int n_items, int LX, int LY, int LZ, int LZR, int phase, int copy)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int per = (n_items + 7) / 8;
@@ -318,15 +358,7 @@ batched3d_phase_kernel(const BatchInst *__restrict__ inst, const int4 *__restric
     if ((int)(blockIdx.x >> 3) >= per || i >= n_items) return;     // whole workgroup
     const int4 it = items[i];
     const BatchInst I = inst[it.x];
-    if (!copy) {
-        const T *src = static_cast<const T *>((phase & 1) ? I.work : I.phi);
-        T *dst = static_cast<T *>((phase & 1) ? I.phi : I.work);
-        stream3d_body<T, K, CPT>(src, dst, I.nx, I.ny, I.nz, (T)I.alpha, (T)I.r, LX, LY, LZ,
-                                 I.tiles_x, it.y, it.z, smem_raw);
-    } else {
-        copy_tile3d<T>(static_cast<const T *>(I.work), static_cast<T *>(I.phi), I.nx, I.ny, I.nz,
-                       LX - 2 * K, LY - 2 * K, LZ, I.tiles_x, it.y, it.z);
-    }
+    batch3d_item<T, K, CPT>(I, it, phase, copy != 0, LX, LY, LZ, LZR, smem_raw);
 }
 
 // ---------------------------------------------------------------- host ----
@@ -336,6 +368,7 @@ namespace {
 long long g_spin_limit = 20000000;   // ~2 s of polling per barrier
 bool g_persistent = false;           // false: a graph of one launch per phase
 constexpr int64_t kMaxGraphBlocks = 2048;   // temporal blocks per captured graph
+constexpr int kRegBatchLZ = 32;             // z segment of a register-tile 3D batch item
 
 struct Plan {
     // key
@@ -685,9 +718,15 @@ ac_status build_plan3d(Plan &p, const ac_instance3d *inst, int32_t n, int64_t ns
                        int32_t dtype, const ac_tune &tune, const std::vector<double> &alpha,
                        const std::vector<double> &r, const DevInfo &dev) {
     const size_t elem = elem_size(dtype);
-    // the batched 3D kernels use the LDS tile body
+    // kernel 0 or AC_KERNEL_3D_STREAM: the LDS body for every instance.
+    // AC_KERNEL_3D_REG: FP32 instances at least 64 cells wide take the
+    // register body on flush 64 x 32 tiles (z segments of kRegBatchLZ planes),
+    // the others the LDS body.  On the 64-grid workload (sides 24..128) the
+    // register items measured slower (591 against 697 GLUPS): at those widths
+    // the flush 64-wide tiles recompute up to a third of their columns.
     ac_tune tl = tune;
-    if (tl.kernel == 0) tl.kernel = AC_KERNEL_3D_STREAM;
+    const bool mixed = tl.kernel == AC_KERNEL_3D_REG && dtype == AC_F32;
+    tl.kernel = AC_KERNEL_3D_STREAM;
     // FP32 default: depth 3 on 32 x 32 tiles, 16-plane segments, fastest
     // measured on the 64-grid batch of sides 24..128 (692 GLUPS; the
     // single-grid default, depth 4 with 32-plane segments: 652)
@@ -696,8 +735,8 @@ ac_status build_plan3d(Plan &p, const ac_instance3d *inst, int32_t n, int64_t ns
         tl.tile_x = tl.tile_y = 32;
         tl.tile_z = 16;
     }
-    if (tl.kernel != AC_KERNEL_3D_STREAM)
-        return fail(AC_ERR_UNSUPPORTED, "batched 3D runs the LDS z-streaming kernel only");
+    if (tune.kernel != 0 && tune.kernel != AC_KERNEL_3D_STREAM && tune.kernel != AC_KERNEL_3D_REG)
+        return fail(AC_ERR_UNSUPPORTED, "kernel %d is not a 3D kernel", tune.kernel);
     ac_plan tp;
     ac_status s = make_plan3d(256, 256, 256, nsteps, elem, &tl, dev, &tp);
     if (s != AC_OK) return s;
@@ -706,16 +745,29 @@ ac_status build_plan3d(Plan &p, const ac_instance3d *inst, int32_t n, int64_t ns
     const int OX = LX - 2 * K, OY = LY - 2 * K;
     Tile3D t3{LX, LY, LZ, K, threads};
     const int cpt = stream3d_cells_per_thread(t3);
+    // register items need the 512-thread workgroup of 8 waves x 4 rows
+    const bool use_reg = mixed && threads == 64 * (32 / kReg3dRows);
+    const int LZR = kRegBatchLZ;
     std::vector<BatchInst> hi(n);
     std::vector<int4> items;
+    bool any_reg = false;
     for (int32_t i = 0; i < n; ++i) {
         const int tx = (inst[i].nx + OX - 1) / OX, ty = (inst[i].ny + OY - 1) / OY;
         const int tz = (inst[i].nz + LZ - 1) / LZ;
+        const bool reg = use_reg && inst[i].nx >= 64;
+        const int rtx = reg2d_tiles_1d(inst[i].nx, 64, K), rty = reg2d_tiles_1d(inst[i].ny, 32, K);
         hi[i] = BatchInst{inst[i].phi, inst[i].work, inst[i].nx, inst[i].ny, alpha[i], r[i],
-                          inst[i].nz, tx};
-        for (int z = 0; z < tz; ++z)
-            for (int y = 0; y < ty; ++y)
-                for (int x = 0; x < tx; ++x) items.push_back(int4{i, y * tx + x, z, 0});
+                          inst[i].nz, tx, rtx, 0};
+        if (reg) {
+            any_reg = true;
+            for (int z = 0; z < (inst[i].nz + LZR - 1) / LZR; ++z)
+                for (int y = 0; y < rty; ++y)
+                    for (int x = 0; x < rtx; ++x) items.push_back(int4{i, y * rtx + x, z, 1});
+        } else {
+            for (int z = 0; z < tz; ++z)
+                for (int y = 0; y < ty; ++y)
+                    for (int x = 0; x < tx; ++x) items.push_back(int4{i, y * tx + x, z, 0});
+        }
     }
     // whole phases of K steps, then one phase of the remaining steps
     const int64_t q = nsteps / K, rem = nsteps % K;
@@ -729,9 +781,10 @@ ac_status build_plan3d(Plan &p, const ac_instance3d *inst, int32_t n, int64_t ns
     const void *kB = rem ? (f64 ? kernel3_of<double>((int)rem, cpt) : kernel3_of<float>((int)rem, cpt))
                          : nullptr;
     if (!kA || (rem && !kB)) return fail(AC_ERR_UNSUPPORTED, "no batched 3D kernel for this shape");
-    const size_t ldsA = stream3d_lds_bytes(t3, elem);
     Tile3D tB{LX, LY, LZ, (int)(rem ? rem : K), threads};
-    const size_t ldsB = stream3d_lds_bytes(tB, elem);
+    const size_t ldsA = std::max(stream3d_lds_bytes(t3, elem), any_reg ? reg3d_lds_bytes(K, 32, elem) : 0);
+    const size_t ldsB = std::max(stream3d_lds_bytes(tB, elem),
+                                 any_reg ? reg3d_lds_bytes(tB.K, 32, elem) : 0);
     set_lds_limit(kA, ldsA);
     if (kB) set_lds_limit(kB, ldsB);
     int per_cu = 0;
@@ -785,7 +838,7 @@ ac_status build_plan3d(Plan &p, const ac_instance3d *inst, int32_t n, int64_t ns
             const int ph = (int)b, copy = b == phases;
             const bool last_rem = rem && b == phases - 1;
             void *pargs[] = {&p.d_inst, &p.d_items, (void *)&ni, (void *)&LX, (void *)&LY,
-                             (void *)&LZ, (void *)&ph, (void *)&copy};
+                             (void *)&LZ, (void *)&LZR, (void *)&ph, (void *)&copy};
             le = hipLaunchKernel(last_rem ? pB : pA, dim3(phase_grid), dim3(threads), pargs,
                                  last_rem ? ldsB : ldsA, cs);
         }
@@ -795,7 +848,7 @@ ac_status build_plan3d(Plan &p, const ac_instance3d *inst, int32_t n, int64_t ns
         hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, cs, p.d_bar);
         const int nph = (int)q, ph0 = 0, cbA = rem ? 0 : cb;
         void *args[] = {&p.d_inst, &p.d_items, (void *)&ni, (void *)&LX, (void *)&LY, (void *)&LZ,
-                        (void *)&nph, (void *)&ph0, (void *)&cbA, &p.d_bar, &p.d_err,
+                        (void *)&LZR, (void *)&nph, (void *)&ph0, (void *)&cbA, &p.d_bar, &p.d_err,
                         (void *)&spin, (void *)&wall};
         le = hipLaunchKernel(kA, dim3(grid), dim3(threads), args, ldsA, cs);
     }
@@ -804,7 +857,7 @@ ac_status build_plan3d(Plan &p, const ac_instance3d *inst, int32_t n, int64_t ns
         hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, cs, p.d_bar);
         const int nph = 1, ph0 = (int)q, cbB = cb;
         void *args[] = {&p.d_inst, &p.d_items, (void *)&ni, (void *)&LX, (void *)&LY, (void *)&LZ,
-                        (void *)&nph, (void *)&ph0, (void *)&cbB, &p.d_bar, &p.d_err,
+                        (void *)&LZR, (void *)&nph, (void *)&ph0, (void *)&cbB, &p.d_bar, &p.d_err,
                         (void *)&spin, (void *)&wall};
         le = hipLaunchKernel(kB, dim3(grid), dim3(threads), args, ldsB, cs);
     }

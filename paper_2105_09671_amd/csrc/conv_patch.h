@@ -37,6 +37,11 @@
 namespace ac {
 namespace sur {
 
+// float -> bf16, round to nearest even, by the hardware conversion
+// (v_cvt_pk_bf16_f32): one instruction where f2bf's NaN test branches.  The
+// two agree on every finite value.
+__device__ __forceinline__ bf16_t f2bf_rn(float f) { return __builtin_bit_cast(bf16_t, (__bf16)f); }
+
 constexpr int PC = 32;          // channels per patch chunk
 constexpr int PP = PC + 8;      // LDS pitch of a patch pixel (bf16 units)
 constexpr int PW = 66;          // patch width: 64 columns + the two pad columns
@@ -45,24 +50,124 @@ template <int RW>
 constexpr int patch_lds_bytes() { return (4 * RW + 2) * PW * PP * 2; }
 template <int RW, int CN>
 constexpr int stage_lds_bytes() { return 4 * RW * 64 * (CN + 8) * 2; }
-template <int RW, int CN>
+// Pointers of the optional prologue / epilogue stages.
+struct ConvAux {
+    const float *phi;      // FIRST: the FP32 state the first layer reads; HEAD: the residual
+    float *out;            // HEAD: phi + U
+    const float *wh, *hb;  // HEAD: 1x1 head weights [32] and bias
+    const float *w1, *b1;  // FIRST: first-layer weights [32][9] (BF16 values held as FP32), bias [32]
+    bf16_t *e1a;           // FIRST: if not null, the first layer's output at the tile's pixels
+};
+
+// FIRST: the FP32 phi patch (TY + 4 rows x 68 columns) follows the e1a patch
+template <int RW>
+constexpr int phi_patch_bytes() { return (4 * RW + 4) * 68 * 4; }
+template <int RW, int CN, bool FIRST = false>
 constexpr int conv3p_lds_bytes() {
-    return patch_lds_bytes<RW>() > stage_lds_bytes<RW, CN>() ? patch_lds_bytes<RW>()
-                                                             : stage_lds_bytes<RW, CN>();
+    return patch_lds_bytes<RW>() + (FIRST ? phi_patch_bytes<RW>() : 0) > stage_lds_bytes<RW, CN>()
+               ? patch_lds_bytes<RW>() + (FIRST ? phi_patch_bytes<RW>() : 0)
+               : stage_lds_bytes<RW, CN>();
+}
+
+// The patch of the first layer's output, e1a = relu(b1 + sum_tap w1[c][tap] *
+// bf16(phi)[neighbour]) rounded to BF16, for (TY + 2) x 66 pixels (rows and
+// columns clamped like any patch; each pixel's own 3 x 3 neighbourhood
+// clamped again) and 32 channels, written at the patch pitch.  It is a GEMM
+// of 16-pixel fragments: A = the 9 neighbours of each pixel at K = 0..8 (K =
+// 9..31 zero), B = the weights at the same K, FP32 accumulation on the MFMA
+// unit, then the bias.
+template <int TY>
+__device__ inline void first_layer_patch(const ConvAux &aux, bf16_t *lds, int n, int H, int W,
+                                         int y0, int x0)
+{
+    constexpr int PR = TY + 4, PCOL = 68, NPIX = (TY + 2) * PW, NF = (NPIX + 15) / 16;
+    float *ph = reinterpret_cast<float *>(lds + (TY + 2) * PW * PP);
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6, lr = lane & 15, lq = lane >> 4;
+    const float *img = aux.phi + (size_t)n * H * W;
+    for (int v = t; v < PR * PCOL; v += 256) {
+        const int r = v / PCOL, c = v - r * PCOL;
+        const int gy = min(max(y0 - 2 + r, 0), H - 1), gx = min(max(x0 - 2 + c, 0), W - 1);
+        ph[v] = bf2f(f2bf(img[(size_t)gy * W + gx]));
+    }
+    // B fragments: lane supplies K = 8 lq .. 8 lq + 7 of output channel 16 j + lr
+    bf16x8 bw[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int k = 8 * lq + e;
+            bw[j][e] = __builtin_bit_cast(__bf16, k < 9 ? f2bf(aux.w1[(16 * j + lr) * 9 + k]) : (bf16_t)0);
+        }
+    float bias[2][4];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const float b = aux.b1[16 * j + lr];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) bias[j][q] = b;
+    }
+    __syncthreads();
+    for (int f = w; f < NF; f += 4) {
+        // A: lane's pixel 16 f + lr, K = 8 lq .. + 7 = taps 8 lq .. (taps >= 9: 0)
+        const int pix = min(16 * f + lr, NPIX - 1);
+        const int pr = pix / PW, pc = pix - pr * PW;
+        const int gy = min(max(y0 - 1 + pr, 0), H - 1), gx = min(max(x0 - 1 + pc, 0), W - 1);
+        // phi patch row / column of image row / column Y: Y - (y0 - 2)
+        int ro[3], co[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            ro[d] = (min(max(gy + d - 1, 0), H - 1) - (y0 - 2)) * PCOL;
+            co[d] = min(max(gx + d - 1, 0), W - 1) - (x0 - 2);
+        }
+        // lanes lq = 0: taps 0..7; lq = 1: tap 8, then zeros; lq >= 2: zeros
+        const float v8 = ph[ro[2] + co[2]];
+        bf16x8 a;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const float v = ph[ro[e / 3] + co[e % 3]];
+            a[e] = (__bf16)(lq == 0 ? v : (e == 0 && lq == 1 ? v8 : 0.f));
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            floatx4 acc = {};
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[j], acc, 0, 0, 0);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int p = 16 * f + 4 * lq + q;
+                float v = acc[q] + bias[j][q];
+                if (p < NPIX) lds[p * PP + 16 * j + lr] = f2bf_rn(v > 0.f ? v : 0.f);
+            }
+        }
+    }
+    if (aux.e1a) {
+        __syncthreads();
+        // the tile's own pixels: patch rows 1..TY, columns 1..64
+        for (int v = t; v < TY * 64 * 4; v += 256) {
+            const int q = v & 3, p = v >> 2, ty = p >> 6, tx = p & 63;
+            const int y = y0 + ty, x = x0 + tx;
+            if (y >= H || x >= W) continue;
+            *reinterpret_cast<uint4 *>(aux.e1a + ((size_t)(n * H + y) * W + x) * 32 + 8 * q) =
+                *reinterpret_cast<const uint4 *>(lds + ((ty + 1) * PW + tx + 1) * PP + 8 * q);
+        }
+    }
 }
 
 // Row-major tile grid over B images of H x W: (image, tile row, tile column);
 // consecutive workgroups take horizontally, then vertically adjacent tiles of
 // one image, and with the XCD-aware numbering (xcd_tile) each XCD takes a
 // contiguous band, so the halo rows two tiles share are read through one L2.
-template <int CIN, int CN, int RW, int LOWC, bool POOL, bool HEAD>
+//
+// FIRST: the layer's input is the first layer's output e1a = relu(conv3(phi;
+// 1 -> 32)), computed into the patch from an FP32 phi patch (rounded to BF16,
+// as the network's input) with FP32 sums in tap order; the first layer's
+// output is then never stored unless aux.e1a asks for it (training keeps it
+// for the backward pass).
+template <int CIN, int CN, int RW, int LOWC, bool POOL, bool HEAD, bool FIRST = false, int PFD = 2>
 __global__ void __launch_bounds__(256)
 conv3_patch_kernel(View X, View Xlo, int B, int H, int W, const bf16_t *__restrict__ Wf,
-                   const float *__restrict__ bias, int Cout, View Y, View P,
-                   const float *__restrict__ wh, const float *__restrict__ hb,
-                   const float *__restrict__ phi, float *__restrict__ out)
+                   const float *__restrict__ bias, int Cout, View Y, View P, ConvAux aux)
 {
     static_assert(CIN % PC == 0 && LOWC % PC == 0 && LOWC <= CIN, "32-channel chunks");
+    static_assert(!FIRST || (CIN == 32 && LOWC == 0), "the first layer has 32 outputs");
     static_assert(CN == 32 || CN == 64, "channel slice of 32 or 64");
     static_assert(!HEAD || CN == 32, "the head needs all 32 channels of a pixel");
     constexpr int TY = 4 * RW, NI = 4 * RW, NJ = CN / 16, NCH = CIN / PC;
@@ -87,14 +192,19 @@ conv3_patch_kernel(View X, View Xlo, int B, int H, int W, const bf16_t *__restri
     const bf16_t *wlane = Wf + ((size_t)(n0 >> 4) * 64 + lane) * 8;
 
     floatx4 acc[NI][NJ] = {};
-    bf16x8 bcur[NJ], bnext[NJ];
+    // B fragments: PFD = 9 loads the 9 taps' fragments of a chunk into
+    // registers when the chunk starts (their L2 latency overlaps the patch
+    // copy, and the taps then wait on nothing but LDS); PFD = 1 keeps one K
+    // step in flight (fewer registers)
+    constexpr int NBQ = PFD == 9 ? 9 : 2;
+    bf16x8 bq[NBQ][NJ];
     auto loadB = [&](int chunk, int tap, bf16x8 (&dst)[NJ]) {
 #pragma unroll
         for (int j = 0; j < NJ; ++j)
             dst[j] = *reinterpret_cast<const bf16x8 *>(
                 wlane + ((size_t)(chunk * 9 + tap) * ntile16 + j) * 512);
     };
-    loadB(0, 0, bcur);
+    if constexpr (PFD == 1) loadB(0, 0, bq[0]);
 
     for (int ch = 0; ch < NCH; ++ch) {
         // ---- stage the patch of this 32-channel chunk (clamped = replicate pad)
@@ -103,23 +213,34 @@ conv3_patch_kernel(View X, View Xlo, int B, int H, int W, const bf16_t *__restri
         const int cofs = low ? ch * PC : ch * PC - LOWC;
         const int Hs = low ? (H >> 1) : H, Ws = low ? (W >> 1) : W;
         if (ch > 0) __syncthreads();                 // every wave is done with the previous chunk
-        constexpr int NV = (TY + 2) * PW * 4;        // 16-byte vectors in the patch
+        if constexpr (PFD == 9) {
+#pragma unroll
+            for (int tap = 0; tap < 9; ++tap) loadB(ch, tap, bq[tap]);
+        }
+        if constexpr (FIRST) {
+            first_layer_patch<TY>(aux, lds, n, H, W, y0, x0);
+        } else {
+            constexpr int NV = (TY + 2) * PW * 4;    // 16-byte vectors in the patch
 #pragma unroll 4
-        for (int v = t; v < NV; v += 256) {
-            const int q = v & 3, pix = v >> 2, pr = pix / PW, pc = pix - pr * PW;
-            int gy = min(max(y0 - 1 + pr, 0), H - 1), gx = min(max(x0 - 1 + pc, 0), W - 1);
-            if (low) { gy >>= 1; gx >>= 1; }
-            const uint4 val = *reinterpret_cast<const uint4 *>(
-                S.p + ((size_t)(n * Hs + gy) * Ws + gx) * S.Cs + S.Co + cofs + 8 * q);
-            *reinterpret_cast<uint4 *>(lds + pix * PP + 8 * q) = val;
+            for (int v = t; v < NV; v += 256) {
+                const int q = v & 3, pix = v >> 2, pr = pix / PW, pc = pix - pr * PW;
+                int gy = min(max(y0 - 1 + pr, 0), H - 1), gx = min(max(x0 - 1 + pc, 0), W - 1);
+                if (low) { gy >>= 1; gx >>= 1; }
+                const uint4 val = *reinterpret_cast<const uint4 *>(
+                    S.p + ((size_t)(n * Hs + gy) * Ws + gx) * S.Cs + S.Co + cofs + 8 * q);
+                *reinterpret_cast<uint4 *>(lds + pix * PP + 8 * q) = val;
+            }
         }
         __syncthreads();
-        // ---- 9 taps of this chunk: A from the patch, B one step ahead
+        // ---- 9 taps of this chunk: A from the patch
 #pragma unroll
         for (int tap = 0; tap < 9; ++tap) {
             const int dy = tap / 3, dx = tap % 3;
-            if (tap < 8) loadB(ch, tap + 1, bnext);
-            else if (ch + 1 < NCH) loadB(ch + 1, 0, bnext);
+            const int cur = PFD == 9 ? tap : 0;
+            if constexpr (PFD == 1) {
+                if (tap < 8) loadB(ch, tap + 1, bq[1]);
+                else if (ch + 1 < NCH) loadB(ch + 1, 0, bq[1]);
+            }
             bf16x8 a[NI];
 #pragma unroll
             for (int i = 0; i < NI; ++i)
@@ -128,9 +249,11 @@ conv3_patch_kernel(View X, View Xlo, int B, int H, int W, const bf16_t *__restri
             for (int i = 0; i < NI; ++i)
 #pragma unroll
                 for (int j = 0; j < NJ; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bcur[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bq[cur][j], acc[i][j], 0, 0, 0);
+            if constexpr (PFD == 1) {
 #pragma unroll
-            for (int j = 0; j < NJ; ++j) bcur[j] = bnext[j];
+                for (int j = 0; j < NJ; ++j) bq[0][j] = bq[1][j];
+            }
         }
     }
 
@@ -148,7 +271,7 @@ conv3_patch_kernel(View X, View Xlo, int B, int H, int W, const bf16_t *__restri
                 const int pix = (RW * w + i / 4) * 64 + 16 * (i % 4) + 4 * lq + q;
                 float v = acc[i][j][q] + bv;
                 v = v > 0.f ? v : 0.f;
-                lds[pix * SP + col] = f2bf(v);
+                lds[pix * SP + col] = f2bf_rn(v);
             }
         }
     __syncthreads();
@@ -158,11 +281,11 @@ conv3_patch_kernel(View X, View Xlo, int B, int H, int W, const bf16_t *__restri
             const int y = y0 + (pix >> 6), x = x0 + (pix & 63);
             if (y >= H || x >= W) continue;
             const bf16_t *a = lds + pix * SP;
-            float s = hb[0];
+            float s = aux.hb[0];
 #pragma unroll
-            for (int c = 0; c < 32; ++c) s += bf2f(a[c]) * wh[c];
+            for (int c = 0; c < 32; ++c) s += bf2f(a[c]) * aux.wh[c];
             const size_t g = (size_t)(n * H + y) * W + x;
-            out[g] = phi[g] + s;
+            aux.out[g] = aux.phi[g] + s;
         }
         return;
     }
@@ -194,7 +317,7 @@ conv3_patch_kernel(View X, View Xlo, int B, int H, int W, const bf16_t *__restri
             uint4 o;
             bf16_t *oe = reinterpret_cast<bf16_t *>(&o);
 #pragma unroll
-            for (int k = 0; k < 8; ++k) oe[k] = f2bf(0.25f * s[k]);
+            for (int k = 0; k < 8; ++k) oe[k] = f2bf_rn(0.25f * s[k]);
             *reinterpret_cast<uint4 *>(P.p + ((size_t)(n * Ho + oy) * Wo + ox) * P.Cs + P.Co + n0 + 8 * q) = o;
         }
     }

@@ -559,6 +559,12 @@ __global__ void pack_weights_kernel(const float *w, int Cout, int taps, int cin,
     }
 }
 
+// w -> bf16(w) held as FP32 (the first layer's weights for its VALU form)
+__global__ void round_first_weights_kernel(const float *w, int n, float *out)
+{
+    for (int i = threadIdx.x; i < n; i += blockDim.x) out[i] = bf2f(f2bf(w[i]));
+}
+
 // [Cout][taps][Cin] -> [taps][Cin][Cout]
 __global__ void transpose_w_kernel(const bf16_t *w, int Cout, int taps, int Cin, bf16_t *wt)
 {
@@ -623,6 +629,7 @@ struct ac_sur {
     float *w32 = nullptr, *m = nullptr, *v = nullptr, *g = nullptr, *g_first = nullptr;
     bf16_t *wb = nullptr, *wt = nullptr, *wf = nullptr;   // wf: fragment order (3x3, Cin >= 32)
     bf16_t *u2lo = nullptr, *u1lo = nullptr;             // decoder 1x1 outputs at low resolution (inference)
+    float *w1f = nullptr;                                // first-layer weights rounded to BF16, [32][9]
     float *out = nullptr, *dU = nullptr, *loss = nullptr;
     bf16_t *x0, *e1a, *cat1, *p1, *e2a, *cat2, *p2, *bt, *d2, *d1;
     bf16_t *dd1, *dcat1, *du1, *dd2, *dcat2, *du2, *dbt, *dp2, *de2a, *dp1, *de1a;
@@ -667,28 +674,35 @@ void launch_fwd(ac_sur *s, int l, View X, int lgcin, int B, int H, int W, View Y
 // 3x3 layer (relu) from an LDS patch: Y (and the pooled P, or the head
 // output `out`) from X, with the first LOWC input channels from Xlo at half
 // resolution.
-template <int CIN, int CN, int RW, int LOWC, bool POOL, bool HEAD>
+// weight fragments in registers ahead of their use (conv3_patch_kernel): the
+// whole chunk (9) for 32-channel slices, one K step (1) for 64-channel ones
+constexpr int kConvPFD = 1;
+
+// FIRST (layer E1B only): the first layer runs inside the patch load from
+// the FP32 input `phi`; e1a_out (may be null) receives its output.
+template <int CIN, int CN, int RW, int LOWC, bool POOL, bool HEAD, bool FIRST = false,
+          int PFD = CN == 32 ? 9 : kConvPFD>
 void launch_c3p(ac_sur *s, int l, View X, View Xlo, int B, int H, int W, View Y, View P,
-                const float *phi = nullptr, float *out = nullptr) {
+                const float *phi = nullptr, float *out = nullptr, bf16_t *e1a_out = nullptr) {
     const LayerDef &L = kLayers[l];
-    constexpr int lds = conv3p_lds_bytes<RW, CN>();
-    const void *kern = reinterpret_cast<const void *>(&conv3_patch_kernel<CIN, CN, RW, LOWC, POOL, HEAD>);
+    constexpr int lds = conv3p_lds_bytes<RW, CN, FIRST>();
+    const void *kern =
+        reinterpret_cast<const void *>(&conv3_patch_kernel<CIN, CN, RW, LOWC, POOL, HEAD, FIRST, PFD>);
     set_lds_limit(kern, lds);
     const int ntiles = B * ((H + 4 * RW - 1) / (4 * RW)) * ((W + 63) / 64);
     dim3 grid(xcd_grid(ntiles), L.cout / CN);
-    hipLaunchKernelGGL((conv3_patch_kernel<CIN, CN, RW, LOWC, POOL, HEAD>), grid, dim3(256), lds, s->st,
-                       X, Xlo, B, H, W, s->wf + s->kwoff[l], bias_of(s, l), L.cout, Y, P,
-                       s->w32 + s->woff[L_HEAD], s->w32 + s->boff[L_HEAD], phi, out);
+    const ConvAux aux{phi, out, s->w32 + s->woff[L_HEAD], s->w32 + s->boff[L_HEAD], s->w1f,
+                      bias_of(s, L_E1A), e1a_out};
+    hipLaunchKernelGGL((conv3_patch_kernel<CIN, CN, RW, LOWC, POOL, HEAD, FIRST, PFD>), grid, dim3(256), lds,
+                       s->st, X, Xlo, B, H, W, s->wf + s->kwoff[l], bias_of(s, l), L.cout, Y, P, aux);
 }
 
+// the 1x1 layers (the 3x3 ones run as launch_c3p)
 void conv_fwd(ac_sur *s, int l, View X, int B, int H, int W, View Y, bool relu, bool up) {
     const LayerDef &L = kLayers[l];
-    const int lg = lg2(l == L_E1A ? 8 : L.cin);
+    const int lg = lg2(L.cin);
     const bool narrow = L.cout <= 32;          // 128 x 32 tiles
-    if (L.k == 3) {
-        if (narrow) launch_fwd<3, false, 4, 1>(s, l, X, lg, B, H, W, Y, relu);
-        else launch_fwd<3, false, 2, 2>(s, l, X, lg, B, H, W, Y, relu);
-    } else if (up) {
+    if (up) {
         if (narrow) launch_fwd<1, true, 4, 1>(s, l, X, lg, B, H, W, Y, relu);
         else launch_fwd<1, true, 2, 2>(s, l, X, lg, B, H, W, Y, relu);
     } else {
@@ -755,6 +769,8 @@ void conv_bwd(ac_sur *s, int l, View X, View dZ, int B, int H, int W, float *dWd
 }
 
 void refresh_weights(ac_sur *s) {
+    hipLaunchKernelGGL(round_first_weights_kernel, dim3(1), dim3(320), 0, s->st, s->w32 + s->woff[L_E1A],
+                       32 * 9, s->w1f);
     for (int l = 0; l < NL; ++l) {
         if (l == L_HEAD) continue;   // the head reads the FP32 master directly
         const LayerDef &L = kLayers[l];
@@ -816,6 +832,7 @@ ac_status ac_sur_create(ac_sur **out, int32_t batch_max, int32_t hw, void *strea
     A((void **)&s->g, o * 4); A((void **)&s->g_first, 32 * 72 * 4);
     A((void **)&s->wb, ko * B2); A((void **)&s->wt, ko * B2); A((void **)&s->wf, ko * B2);
     A((void **)&s->u2lo, n3 * 64 * B2); A((void **)&s->u1lo, n2 * 32 * B2);
+    A((void **)&s->w1f, 32 * 9 * 4);
     A((void **)&s->out, n1 * 4); A((void **)&s->dU, n1 * 4); A((void **)&s->loss, 16);
     A((void **)&s->x0, n1 * 8 * B2); A((void **)&s->e1a, n1 * 32 * B2); A((void **)&s->cat1, n1 * 64 * B2);
     A((void **)&s->p1, n2 * 32 * B2); A((void **)&s->e2a, n2 * 64 * B2); A((void **)&s->cat2, n2 * 128 * B2);
@@ -884,15 +901,15 @@ ac_status ac_sur_forward(ac_sur *s, const float *phi_in, float *phi_out, int32_t
     const int n1 = B * H * W;
     hipLaunchKernelGGL(pack_input_kernel, grid1(n1), dim3(256), 0, s->st, phi_in, s->x0, n1);
     const View none{nullptr, 0, 0};
-    conv_fwd(s, L_E1A, V(s->x0, 8), B, H, W, V(s->e1a, 32), true, false);
-    launch_c3p<32, 32, 2, 0, true, false>(s, L_E1B, V(s->e1a, 32), none, B, H, W, V(s->cat1, 64, 32),
-                                          V(s->p1, 32));
-    launch_c3p<32, 64, 2, 0, false, false>(s, L_E2A, V(s->p1, 32), none, B, H2, W2, V(s->e2a, 64), none);
-    launch_c3p<64, 64, 2, 0, true, false>(s, L_E2B, V(s->e2a, 64), none, B, H2, W2, V(s->cat2, 128, 64),
+    // first two layers in one kernel (e1a kept for the backward pass)
+    launch_c3p<32, 32, 1, 0, true, false, true>(s, L_E1B, none, none, B, H, W, V(s->cat1, 64, 32),
+                                                V(s->p1, 32), phi_in, nullptr, s->e1a);
+    launch_c3p<32, 64, 1, 0, false, false>(s, L_E2A, V(s->p1, 32), none, B, H2, W2, V(s->e2a, 64), none);
+    launch_c3p<64, 64, 1, 0, true, false>(s, L_E2B, V(s->e2a, 64), none, B, H2, W2, V(s->cat2, 128, 64),
                                           V(s->p2, 64));
-    launch_c3p<64, 64, 2, 0, false, false>(s, L_BT, V(s->p2, 64), none, B, H4, W4, V(s->bt, 128), none);
+    launch_c3p<64, 64, 1, 0, false, false>(s, L_BT, V(s->p2, 64), none, B, H4, W4, V(s->bt, 128), none);
     conv_fwd(s, L_U2, V(s->bt, 128), B, H4, W4, V(s->cat2, 128, 0), false, true);
-    launch_c3p<128, 64, 2, 0, false, false>(s, L_D2, V(s->cat2, 128), none, B, H2, W2, V(s->d2, 64), none);
+    launch_c3p<128, 64, 1, 0, false, false>(s, L_D2, V(s->cat2, 128), none, B, H2, W2, V(s->d2, 64), none);
     conv_fwd(s, L_U1, V(s->d2, 64), B, H2, W2, V(s->cat1, 64, 0), false, true);
     launch_c3p<64, 32, 2, 0, false, false>(s, L_D1, V(s->cat1, 64), none, B, H, W, V(s->d1, 32), none);
     float *o = phi_out ? phi_out : s->out;
@@ -917,19 +934,18 @@ ac_status ac_sur_infer(ac_sur *s, const float *phi_in, float *phi_out, int32_t b
     if (batch < 1 || batch > s->Bmax) return fail(AC_ERR_INVALID_ARG, "batch %d outside 1..%d", batch, s->Bmax);
     const int B = batch, H = s->H, W = s->W, H2 = H / 2, W2 = W / 2, H4 = H / 4, W4 = W / 4;
     const int n1 = B * H * W;
-    hipLaunchKernelGGL(pack_input_kernel, grid1(n1), dim3(256), 0, s->st, phi_in, s->x0, n1);
     const View none{nullptr, 0, 0};
-    conv_fwd(s, L_E1A, V(s->x0, 8), B, H, W, V(s->e1a, 32), true, false);
-    launch_c3p<32, 32, 2, 0, true, false>(s, L_E1B, V(s->e1a, 32), none, B, H, W, V(s->cat1, 64, 32),
-                                          V(s->p1, 32));
-    launch_c3p<32, 64, 2, 0, false, false>(s, L_E2A, V(s->p1, 32), none, B, H2, W2, V(s->e2a, 64), none);
-    launch_c3p<64, 64, 2, 0, true, false>(s, L_E2B, V(s->e2a, 64), none, B, H2, W2, V(s->cat2, 128, 64),
+    // first two layers in one kernel: the first layer's output is never stored
+    launch_c3p<32, 32, 1, 0, true, false, true>(s, L_E1B, none, none, B, H, W, V(s->cat1, 64, 32),
+                                                V(s->p1, 32), phi_in);
+    launch_c3p<32, 64, 1, 0, false, false>(s, L_E2A, V(s->p1, 32), none, B, H2, W2, V(s->e2a, 64), none);
+    launch_c3p<64, 64, 1, 0, true, false>(s, L_E2B, V(s->e2a, 64), none, B, H2, W2, V(s->cat2, 128, 64),
                                           V(s->p2, 64));
-    launch_c3p<64, 64, 2, 0, false, false>(s, L_BT, V(s->p2, 64), none, B, H4, W4, V(s->bt, 128), none);
+    launch_c3p<64, 64, 1, 0, false, false>(s, L_BT, V(s->p2, 64), none, B, H4, W4, V(s->bt, 128), none);
     // decoder 1x1 layers at low resolution; the next 3x3 layer reads them
     // through the nearest upsampling
     conv_fwd(s, L_U2, V(s->bt, 128), B, H4, W4, V(s->u2lo, 64), false, false);
-    launch_c3p<128, 64, 2, 64, false, false>(s, L_D2, V(s->cat2, 128, 64), V(s->u2lo, 64), B, H2, W2,
+    launch_c3p<128, 64, 1, 64, false, false>(s, L_D2, V(s->cat2, 128, 64), V(s->u2lo, 64), B, H2, W2,
                                              V(s->d2, 64), none);
     conv_fwd(s, L_U1, V(s->d2, 64), B, H2, W2, V(s->u1lo, 32), false, false);
     // last 3x3 layer with the head and the residual in its epilogue

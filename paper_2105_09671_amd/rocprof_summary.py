@@ -5,6 +5,10 @@ Usage (each reads the directory rocprofv3 wrote with ``-d DIR --output-format cs
   python -m paper_2105_09671_amd.rocprof_summary trace DIR OUT.txt --command "..."
       kernel table from *_kernel_stats.csv (calls, total, mean, min, max).
 
+  python -m paper_2105_09671_amd.rocprof_summary counters OUT.txt DIR [DIR ...] --kernel NAME ...
+      mean per dispatch of every counter of each matching kernel (several
+      --pmc runs, one directory each), with per-wave instruction counts.
+
   python -m paper_2105_09671_amd.rocprof_summary traffic FETCH_DIR WRITE_DIR OUT.txt \\
       --kernel tile2d_kernel --copy-bytes 268435456 --alg-bytes N --src FILE --json OUT.json
       HBM bytes per dispatch of the kernel from FETCH_SIZE and WRITE_SIZE (KiB per
@@ -100,6 +104,40 @@ def traffic(fetch_dir, write_dir, out, kernel, copy_bytes, alg_bytes, src, out_j
                    "src_sha256": sha, "command": command}, open(out_json, "w"), indent=1)
 
 
+def counters(dirs, out: str, kernels, command: str) -> None:
+    """Mean value per dispatch of every counter collected in the given runs,
+    for each kernel whose name contains one of `kernels`, plus derived ratios
+    when their inputs are present."""
+    per = {}          # kernel -> counter -> [values]
+    for d in dirs:
+        for r in csv.DictReader(open(_find(d, "_counter_collection.csv"))):
+            name = r["Kernel_Name"]
+            k = next((k for k in kernels if k in name), None)
+            if k is None:
+                continue
+            per.setdefault(_short(name, 60), {}).setdefault(r["Counter_Name"], []).append(
+                float(r["Counter_Value"]))
+    lines = ["# rocprofv3 --pmc, mean per dispatch", "# command: " + command, ""]
+    for kname in sorted(per):
+        c = {n: statistics.mean(v) for n, v in per[kname].items()}
+        n_disp = max(len(v) for v in per[kname].values())
+        lines.append("%s  (%d dispatches)" % (kname, n_disp))
+        for n in sorted(c):
+            lines.append("    %-28s %16.1f" % (n, c[n]))
+        waves = c.get("SQ_WAVES")
+        if waves:
+            for n in ("SQ_INSTS_VALU", "SQ_INSTS_MFMA", "SQ_INSTS_LDS", "SQ_INSTS_SALU", "SQ_INSTS_VMEM"):
+                if n in c:
+                    lines.append("    %-28s %16.2f" % (n + " per wave", c[n] / waves))
+        if c.get("SQ_BUSY_CYCLES") and "SQ_VALU_MFMA_BUSY_CYCLES" in c:
+            lines.append("    %-28s %16.4f" % ("MFMA busy / SQ busy", c["SQ_VALU_MFMA_BUSY_CYCLES"] / c["SQ_BUSY_CYCLES"]))
+        if c.get("SQ_INSTS_LDS") and "SQ_LDS_BANK_CONFLICT" in c and c.get("SQ_LDS_IDX_ACTIVE"):
+            lines.append("    %-28s %16.4f" % ("LDS bank-conflict / active", c["SQ_LDS_BANK_CONFLICT"] / c["SQ_LDS_IDX_ACTIVE"]))
+        lines.append("")
+    open(out, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -117,7 +155,15 @@ def main():
     f.add_argument("--src", default="", help="comma-separated kernel source files")
     f.add_argument("--json", default="")
     f.add_argument("--command", default="")
+    c = sub.add_parser("counters")
+    c.add_argument("out")
+    c.add_argument("dirs", nargs="+")
+    c.add_argument("--kernel", action="append", required=True)
+    c.add_argument("--command", default="")
     a = ap.parse_args()
+    if a.cmd == "counters":
+        counters(a.dirs, a.out, a.kernel, a.command)
+        return
     if a.cmd == "trace":
         trace(a.dir, a.out, a.command)
     else:

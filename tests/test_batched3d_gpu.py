@@ -25,8 +25,10 @@ def mode(request):
 
 
 def _small_batch():
+    # (nz, ny, nx); in FP32 the grids at least 64 wide run on register tiles
     shapes = [(5, 1, 1), (9, 40, 7), (33, 33, 33), (20, 17, 61), (2, 70, 45), (40, 8, 3),
-              (64, 64, 24), (1, 1, 30), (26, 29, 31)]
+              (64, 64, 24), (1, 1, 30), (26, 29, 31), (12, 37, 70), (7, 50, 130), (35, 33, 64),
+              (3, 1, 66)]
     fields, prm = [], []
     for i, (nz, ny, nx) in enumerate(shapes):
         h = 1.0 / max(8, min(nx, ny, nz))
@@ -38,7 +40,8 @@ def _small_batch():
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 @pytest.mark.parametrize("nsteps,tune", [(7, None), (9, None), (4, None), (1, None),
                                          (11, dict(tb_depth=3, tile_x=32, tile_y=16, tile_z=16)),
-                                         (6, dict(tb_depth=2, tile_x=16, tile_y=16, tile_z=8))])
+                                         (6, dict(tb_depth=2, tile_x=16, tile_y=16, tile_z=8)),
+                                         (9, dict(kernel=2)), (10, dict(kernel=5, tb_depth=4))])
 def test_batch3d_matches_single_and_oracle(mode, dtype, nsteps, tune):
     fields, prm = _small_batch()
     fields = [f.astype(NP[dtype]) for f in fields]
