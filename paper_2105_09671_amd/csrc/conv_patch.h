@@ -37,6 +37,9 @@
 namespace ac {
 namespace sur {
 
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
 // float -> bf16, round to nearest even, by the hardware conversion
 // (v_cvt_pk_bf16_f32): one instruction where f2bf's NaN test branches.  The
 // two agree on every finite value.
@@ -73,42 +76,39 @@ constexpr int conv3p_lds_bytes() {
 // bf16(phi)[neighbour]) rounded to BF16, for (TY + 2) x 66 pixels (rows and
 // columns clamped like any patch; each pixel's own 3 x 3 neighbourhood
 // clamped again) and 32 channels, written at the patch pitch.  It is a GEMM
-// of 16-pixel fragments: A = the 9 neighbours of each pixel at K = 0..8 (K =
-// 9..31 zero), B = the weights at the same K, FP32 accumulation on the MFMA
-// unit, then the bias.
+// of 32-pixel fragments on v_mfma_f32_32x32x16_bf16, computed transposed:
+// A = the weights (32 channels x K), B = each pixel's 9 BF16 neighbours of
+// phi at K = 0..8 (K = 9..15 zero), FP32 accumulation, then the bias.
 template <int TY>
 __device__ inline void first_layer_patch(const ConvAux &aux, bf16_t *lds, int n, int H, int W,
                                          int y0, int x0)
 {
-    constexpr int PR = TY + 4, PCOL = 68, NPIX = (TY + 2) * PW, NF = (NPIX + 15) / 16;
+    constexpr int PR = TY + 4, PCOL = 68, NPIX = (TY + 2) * PW, NF = (NPIX + 31) / 32;
     float *ph = reinterpret_cast<float *>(lds + (TY + 2) * PW * PP);
-    const int t = threadIdx.x, lane = t & 63, w = t >> 6, lr = lane & 15, lq = lane >> 4;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6, l32 = lane & 31, hi = lane >> 5;
     const float *img = aux.phi + (size_t)n * H * W;
     for (int v = t; v < PR * PCOL; v += 256) {
         const int r = v / PCOL, c = v - r * PCOL;
         const int gy = min(max(y0 - 2 + r, 0), H - 1), gx = min(max(x0 - 2 + c, 0), W - 1);
         ph[v] = bf2f(f2bf(img[(size_t)gy * W + gx]));
     }
-    // B fragments: lane supplies K = 8 lq .. 8 lq + 7 of output channel 16 j + lr
-    bf16x8 bw[2];
+    // A operand: lane supplies K = 8 hi .. 8 hi + 7 of output channel l32
+    // (lanes 0..31: taps 0..7; lanes 32..63: tap 8, then zeros)
+    bf16x8 wa;
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int k = 8 * lq + e;
-            bw[j][e] = __builtin_bit_cast(__bf16, k < 9 ? f2bf(aux.w1[(16 * j + lr) * 9 + k]) : (bf16_t)0);
-        }
-    float bias[2][4];
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-        const float b = aux.b1[16 * j + lr];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) bias[j][q] = b;
+    for (int e = 0; e < 8; ++e) {
+        const int k = 8 * hi + e;
+        wa[e] = __builtin_bit_cast(__bf16, k < 9 ? f2bf(aux.w1[l32 * 9 + k]) : (bf16_t)0);
     }
+    // the product's lane holds channels 8 g + 4 hi + r (g, r = 0..3) of one pixel
+    float bias[4][4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) bias[g][r] = aux.b1[8 * g + 4 * hi + r];
     __syncthreads();
     for (int f = w; f < NF; f += 4) {
-        // A: lane's pixel 16 f + lr, K = 8 lq .. + 7 = taps 8 lq .. (taps >= 9: 0)
-        const int pix = min(16 * f + lr, NPIX - 1);
+        const int pix = min(32 * f + l32, NPIX - 1);
         const int pr = pix / PW, pc = pix - pr * PW;
         const int gy = min(max(y0 - 1 + pr, 0), H - 1), gx = min(max(x0 - 1 + pc, 0), W - 1);
         // phi patch row / column of image row / column Y: Y - (y0 - 2)
@@ -118,23 +118,25 @@ __device__ inline void first_layer_patch(const ConvAux &aux, bf16_t *lds, int n,
             ro[d] = (min(max(gy + d - 1, 0), H - 1) - (y0 - 2)) * PCOL;
             co[d] = min(max(gx + d - 1, 0), W - 1) - (x0 - 2);
         }
-        // lanes lq = 0: taps 0..7; lq = 1: tap 8, then zeros; lq >= 2: zeros
         const float v8 = ph[ro[2] + co[2]];
-        bf16x8 a;
+        bf16x8 b;
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const float v = ph[ro[e / 3] + co[e % 3]];
-            a[e] = (__bf16)(lq == 0 ? v : (e == 0 && lq == 1 ? v8 : 0.f));
+            b[e] = (__bf16)(hi == 0 ? v : (e == 0 ? v8 : 0.f));
         }
+        floatx16 acc = {};
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wa, b, acc, 0, 0, 0);
+        if (32 * f + l32 < NPIX) {
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            floatx4 acc = {};
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[j], acc, 0, 0, 0);
+            for (int g = 0; g < 4; ++g) {
+                bf16x4 o;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int p = 16 * f + 4 * lq + q;
-                float v = acc[q] + bias[j][q];
-                if (p < NPIX) lds[p * PP + 16 * j + lr] = f2bf_rn(v > 0.f ? v : 0.f);
+                for (int r = 0; r < 4; ++r) {
+                    const float v = acc[4 * g + r] + bias[g][r];
+                    o[r] = (__bf16)(v > 0.f ? v : 0.f);
+                }
+                *reinterpret_cast<bf16x4 *>(lds + (32 * f + l32) * PP + 8 * g + 4 * hi) = o;
             }
         }
     }
@@ -161,8 +163,15 @@ __device__ inline void first_layer_patch(const ConvAux &aux, bf16_t *lds, int n,
 // as the network's input) with FP32 sums in tap order; the first layer's
 // output is then never stored unless aux.e1a asks for it (training keeps it
 // for the backward pass).
-template <int CIN, int CN, int RW, int LOWC, bool POOL, bool HEAD, bool FIRST = false, int PFD = 2>
-__global__ void __launch_bounds__(256)
+// Three waves per SIMD asked of the register allocator where it fits without
+// spills (not the 128-channel layer, not the training copy of the last
+// layer): about 1 % faster over the forward pass than the default allocation.
+constexpr bool kConv3pWaves3 = true;
+template <int CIN, int RW, bool HEAD>
+constexpr int conv3p_waves() { return kConv3pWaves3 && !(CIN == 128 || (RW == 2 && !HEAD)) ? 3 : 1; }
+
+template <int CIN, int CN, int RW, int LOWC, bool POOL, bool HEAD, bool FIRST = false>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(conv3p_waves<CIN, RW, HEAD>())))
 conv3_patch_kernel(View X, View Xlo, int B, int H, int W, const bf16_t *__restrict__ Wf,
                    const float *__restrict__ bias, int Cout, View Y, View P, ConvAux aux)
 {
@@ -187,25 +196,34 @@ conv3_patch_kernel(View X, View Xlo, int B, int H, int W, const bf16_t *__restri
 #pragma unroll
     for (int i = 0; i < NI; ++i)
         abase[i] = ((RW * w + i / 4) * PW + 16 * (i % 4) + lr) * PP + 8 * lq;
-    // B fragment (chunk, tap, j): Wf + (((chunk * 9 + tap) * (Cout / 16) + n0 / 16 + j) * 64 + lane) * 8
+    // B fragment (chunk, tap, j) of this workgroup's channel slice: lane's 16
+    // bytes at Wf + (((chunk * 9 + tap) * (Cout / 16) + n0 / 16 + j) * 64 + lane) * 8;
+    // the step part is uniform (scalar arithmetic), the lane part a fixed
+    // 32-bit offset
     const int ntile16 = Cout >> 4;
-    const bf16_t *wlane = Wf + ((size_t)(n0 >> 4) * 64 + lane) * 8;
+    const bf16_t *wslice = Wf + (size_t)(n0 >> 4) * 512;
+    const int wl = lane * 8;
 
     floatx4 acc[NI][NJ] = {};
-    // B fragments: PFD = 9 loads the 9 taps' fragments of a chunk into
-    // registers when the chunk starts (their L2 latency overlaps the patch
-    // copy, and the taps then wait on nothing but LDS); PFD = 1 keeps one K
-    // step in flight (fewer registers)
-    constexpr int NBQ = PFD == 9 ? 9 : 2;
-    bf16x8 bq[NBQ][NJ];
-    auto loadB = [&](int chunk, int tap, bf16x8 (&dst)[NJ]) {
+    // two slots of B fragments: K step s (over all chunks) uses slot s & 1 and
+    // loads step s + 1 into the other; the chunk loop is unrolled (at most 4
+    // chunks), so every slot index is static and nothing is copied
+    bf16x8 bq[2][NJ];
+    auto loadB = [&](int step, bf16x8 (&dst)[NJ]) {
+        const bf16_t *wb = wslice + (size_t)step * ntile16 * 512;
 #pragma unroll
-        for (int j = 0; j < NJ; ++j)
-            dst[j] = *reinterpret_cast<const bf16x8 *>(
-                wlane + ((size_t)(chunk * 9 + tap) * ntile16 + j) * 512);
+        for (int j = 0; j < NJ; ++j) dst[j] = *reinterpret_cast<const bf16x8 *>(wb + j * 512 + wl);
     };
-    if constexpr (PFD == 1) loadB(0, 0, bq[0]);
+    loadB(0, bq[0]);
 
+    // patch copy: in every patch row, lanes 16 k .. 16 k + 15 of wave w move
+    // 16-byte group k of patch columns 16 w .. 16 w + 15 (sixteen consecutive
+    // pixels of one group per quarter-wave, as the fragment reads: no bank
+    // conflict at the 80-byte pitch); all rows' loads are issued before their
+    // LDS writes; threads 0 .. 8 (TY + 2) - 1 move the two columns beyond
+    const int pq = (t >> 4) & 3, pcol = (t & 15) + 16 * w;
+    const int ex_q = t & 3, ex_r = t >> 3, ex_c = 64 + ((t >> 2) & 1);
+#pragma unroll
     for (int ch = 0; ch < NCH; ++ch) {
         // ---- stage the patch of this 32-channel chunk (clamped = replicate pad)
         const bool low = ch * PC < LOWC;
@@ -213,34 +231,39 @@ conv3_patch_kernel(View X, View Xlo, int B, int H, int W, const bf16_t *__restri
         const int cofs = low ? ch * PC : ch * PC - LOWC;
         const int Hs = low ? (H >> 1) : H, Ws = low ? (W >> 1) : W;
         if (ch > 0) __syncthreads();                 // every wave is done with the previous chunk
-        if constexpr (PFD == 9) {
-#pragma unroll
-            for (int tap = 0; tap < 9; ++tap) loadB(ch, tap, bq[tap]);
-        }
         if constexpr (FIRST) {
             first_layer_patch<TY>(aux, lds, n, H, W, y0, x0);
         } else {
-            constexpr int NV = (TY + 2) * PW * 4;    // 16-byte vectors in the patch
-#pragma unroll 4
-            for (int v = t; v < NV; v += 256) {
-                const int q = v & 3, pix = v >> 2, pr = pix / PW, pc = pix - pr * PW;
-                int gy = min(max(y0 - 1 + pr, 0), H - 1), gx = min(max(x0 - 1 + pc, 0), W - 1);
-                if (low) { gy >>= 1; gx >>= 1; }
-                const uint4 val = *reinterpret_cast<const uint4 *>(
-                    S.p + ((size_t)(n * Hs + gy) * Ws + gx) * S.Cs + S.Co + cofs + 8 * q);
-                *reinterpret_cast<uint4 *>(lds + pix * PP + 8 * q) = val;
+            const bf16_t *img = S.p + (size_t)n * Hs * Ws * S.Cs + S.Co + cofs + 8 * pq;
+            int gx = min(max(x0 - 1 + pcol, 0), W - 1);
+            if (low) gx >>= 1;
+            uint4 val[TY + 2];
+#pragma unroll
+            for (int pr = 0; pr < TY + 2; ++pr) {
+                int gy = min(max(y0 - 1 + pr, 0), H - 1);
+                if (low) gy >>= 1;
+                val[pr] = *reinterpret_cast<const uint4 *>(img + ((size_t)gy * Ws + gx) * S.Cs);
             }
+            uint4 vex = {};
+            const bool ex = ex_r < TY + 2;
+            if (ex) {
+                int gy = min(max(y0 - 1 + ex_r, 0), H - 1), gxe = min(max(x0 - 1 + ex_c, 0), W - 1);
+                if (low) { gy >>= 1; gxe >>= 1; }
+                vex = *reinterpret_cast<const uint4 *>(img + 8 * (ex_q - pq) +
+                                                       ((size_t)gy * Ws + gxe) * S.Cs);
+            }
+#pragma unroll
+            for (int pr = 0; pr < TY + 2; ++pr)
+                *reinterpret_cast<uint4 *>(lds + (pr * PW + pcol) * PP + 8 * pq) = val[pr];
+            if (ex) *reinterpret_cast<uint4 *>(lds + (ex_r * PW + ex_c) * PP + 8 * ex_q) = vex;
         }
         __syncthreads();
-        // ---- 9 taps of this chunk: A from the patch
+        // ---- 9 taps of this chunk: A from the patch, B one step ahead
 #pragma unroll
         for (int tap = 0; tap < 9; ++tap) {
             const int dy = tap / 3, dx = tap % 3;
-            const int cur = PFD == 9 ? tap : 0;
-            if constexpr (PFD == 1) {
-                if (tap < 8) loadB(ch, tap + 1, bq[1]);
-                else if (ch + 1 < NCH) loadB(ch + 1, 0, bq[1]);
-            }
+            const int step = ch * 9 + tap;
+            if (step + 1 < NCH * 9) loadB(step + 1, bq[(step + 1) & 1]);
             bf16x8 a[NI];
 #pragma unroll
             for (int i = 0; i < NI; ++i)
@@ -249,31 +272,34 @@ conv3_patch_kernel(View X, View Xlo, int B, int H, int W, const bf16_t *__restri
             for (int i = 0; i < NI; ++i)
 #pragma unroll
                 for (int j = 0; j < NJ; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bq[cur][j], acc[i][j], 0, 0, 0);
-            if constexpr (PFD == 1) {
-#pragma unroll
-                for (int j = 0; j < NJ; ++j) bq[0][j] = bq[1][j];
-            }
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bq[step & 1][j], a[i], acc[i][j], 0, 0, 0);
         }
     }
 
-    // ---- epilogue: bias + relu -> bf16, staged in LDS as [pixel][CN]
+    // ---- epilogue: bias + relu -> bf16, staged in LDS as [pixel][CN].  The
+    // products are computed transposed (weights as the MFMA's A operand), so
+    // a lane holds 4 consecutive channels 16 j + 4 (lane / 16) + r of one
+    // pixel: one 8-byte LDS write per fragment
     __syncthreads();                                 // the patch is dead
     constexpr int SP = CN + 8;
 #pragma unroll
-    for (int i = 0; i < NI; ++i)
+    for (int j = 0; j < NJ; ++j) {
+        const int c0 = 16 * j + 4 * lq;
+        float bv[4];
 #pragma unroll
-        for (int j = 0; j < NJ; ++j) {
-            const int col = 16 * j + lr;
-            const float bv = bias[n0 + col];
+        for (int r = 0; r < 4; ++r) bv[r] = bias[n0 + c0 + r];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int pix = (RW * w + i / 4) * 64 + 16 * (i % 4) + 4 * lq + q;
-                float v = acc[i][j][q] + bv;
-                v = v > 0.f ? v : 0.f;
-                lds[pix * SP + col] = f2bf_rn(v);
+        for (int i = 0; i < NI; ++i) {
+            const int pix = (RW * w + i / 4) * 64 + 16 * (i % 4) + lr;
+            bf16x4 o;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float v = acc[i][j][r] + bv[r];
+                o[r] = (__bf16)(v > 0.f ? v : 0.f);
             }
+            *reinterpret_cast<bf16x4 *>(lds + pix * SP + c0) = o;
         }
+    }
     __syncthreads();
     if constexpr (HEAD) {
         // one thread per pixel: out = phi + (hb + sum_c a_c wh_c), c in order
@@ -290,6 +316,9 @@ conv3_patch_kernel(View X, View Xlo, int B, int H, int W, const bf16_t *__restri
         return;
     }
     constexpr int CQ = CN / 8;                       // 16-byte groups per pixel
+    // consecutive lanes write consecutive 16-byte groups of a pixel (whole
+    // 64- or 128-byte pixel rows per lane group: measured faster than the
+    // LDS-conflict-free order of sixteen pixels per quarter-wave)
     for (int v = t; v < TY * 64 * CQ; v += 256) {
         const int q = v % CQ, pix = v / CQ;
         const int y = y0 + pix / 64, x = x0 + (pix & 63);

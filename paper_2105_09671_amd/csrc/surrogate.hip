@@ -674,26 +674,21 @@ void launch_fwd(ac_sur *s, int l, View X, int lgcin, int B, int H, int W, View Y
 // 3x3 layer (relu) from an LDS patch: Y (and the pooled P, or the head
 // output `out`) from X, with the first LOWC input channels from Xlo at half
 // resolution.
-// weight fragments in registers ahead of their use (conv3_patch_kernel): the
-// whole chunk (9) for 32-channel slices, one K step (1) for 64-channel ones
-constexpr int kConvPFD = 1;
-
 // FIRST (layer E1B only): the first layer runs inside the patch load from
 // the FP32 input `phi`; e1a_out (may be null) receives its output.
-template <int CIN, int CN, int RW, int LOWC, bool POOL, bool HEAD, bool FIRST = false,
-          int PFD = CN == 32 ? 9 : kConvPFD>
+template <int CIN, int CN, int RW, int LOWC, bool POOL, bool HEAD, bool FIRST = false>
 void launch_c3p(ac_sur *s, int l, View X, View Xlo, int B, int H, int W, View Y, View P,
                 const float *phi = nullptr, float *out = nullptr, bf16_t *e1a_out = nullptr) {
     const LayerDef &L = kLayers[l];
     constexpr int lds = conv3p_lds_bytes<RW, CN, FIRST>();
     const void *kern =
-        reinterpret_cast<const void *>(&conv3_patch_kernel<CIN, CN, RW, LOWC, POOL, HEAD, FIRST, PFD>);
+        reinterpret_cast<const void *>(&conv3_patch_kernel<CIN, CN, RW, LOWC, POOL, HEAD, FIRST>);
     set_lds_limit(kern, lds);
     const int ntiles = B * ((H + 4 * RW - 1) / (4 * RW)) * ((W + 63) / 64);
     dim3 grid(xcd_grid(ntiles), L.cout / CN);
     const ConvAux aux{phi, out, s->w32 + s->woff[L_HEAD], s->w32 + s->boff[L_HEAD], s->w1f,
                       bias_of(s, L_E1A), e1a_out};
-    hipLaunchKernelGGL((conv3_patch_kernel<CIN, CN, RW, LOWC, POOL, HEAD, FIRST, PFD>), grid, dim3(256), lds,
+    hipLaunchKernelGGL((conv3_patch_kernel<CIN, CN, RW, LOWC, POOL, HEAD, FIRST>), grid, dim3(256), lds,
                        s->st, X, Xlo, B, H, W, s->wf + s->kwoff[l], bias_of(s, l), L.cout, Y, P, aux);
 }
 

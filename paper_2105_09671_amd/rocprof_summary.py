@@ -104,7 +104,8 @@ def traffic(fetch_dir, write_dir, out, kernel, copy_bytes, alg_bytes, src, out_j
                    "src_sha256": sha, "command": command}, open(out_json, "w"), indent=1)
 
 
-def counters(dirs, out: str, kernels, command: str) -> None:
+def counters(dirs, out: str, kernels, command: str, fetch_scale: float = 2.0,
+             write_scale: float = 1.0) -> None:
     """Mean value per dispatch of every counter collected in the given runs,
     for each kernel whose name contains one of `kernels`, plus derived ratios
     when their inputs are present."""
@@ -129,8 +130,16 @@ def counters(dirs, out: str, kernels, command: str) -> None:
             for n in ("SQ_INSTS_VALU", "SQ_INSTS_MFMA", "SQ_INSTS_LDS", "SQ_INSTS_SALU", "SQ_INSTS_VMEM"):
                 if n in c:
                     lines.append("    %-28s %16.2f" % (n + " per wave", c[n] / waves))
-        if c.get("SQ_BUSY_CYCLES") and "SQ_VALU_MFMA_BUSY_CYCLES" in c:
-            lines.append("    %-28s %16.4f" % ("MFMA busy / SQ busy", c["SQ_VALU_MFMA_BUSY_CYCLES"] / c["SQ_BUSY_CYCLES"]))
+        if "FETCH_SIZE" in c and "WRITE_SIZE" in c:
+            # KiB per dispatch, scaled as the copy reference of the traffic
+            # records reads (FETCH_SIZE counts half of a copy's bytes)
+            hb = (c["FETCH_SIZE"] * fetch_scale + c["WRITE_SIZE"] * write_scale) * 1024.0
+            lines.append("    %-28s %16.1f" % ("HBM MiB (F x%.1f + W x%.1f)" % (fetch_scale, write_scale),
+                                               hb / 2 ** 20))
+        if c.get("SQ_WAVE_CYCLES") and "SQ_WAIT_INST_ANY" in c:
+            lines.append("    %-28s %16.4f" % ("wait-any / wave cycles", c["SQ_WAIT_INST_ANY"] / c["SQ_WAVE_CYCLES"]))
+        if c.get("SQ_WAVE_CYCLES") and "SQ_ACTIVE_INST_VALU" in c:
+            lines.append("    %-28s %16.4f" % ("VALU active / wave cycles", c["SQ_ACTIVE_INST_VALU"] / c["SQ_WAVE_CYCLES"]))
         if c.get("SQ_INSTS_LDS") and "SQ_LDS_BANK_CONFLICT" in c and c.get("SQ_LDS_IDX_ACTIVE"):
             lines.append("    %-28s %16.4f" % ("LDS bank-conflict / active", c["SQ_LDS_BANK_CONFLICT"] / c["SQ_LDS_IDX_ACTIVE"]))
         lines.append("")
