@@ -278,14 +278,14 @@ __device__ void copy_tile3d_reg(const T *src, T *dst, int nx, int ny, int nz, in
 // LY tile and LZ-plane segment, it.w = 1 (FP32, 512 threads) the register
 // body on a flush 64 x 32 tile and LZR-plane segment.  Both give the bits of
 // ac_step_3d.  copy: the final copy phase of the item's output region.
-template <typename T, int K, int CPT>
+template <typename T, int K, int CPT, bool REG>
 __device__ __forceinline__ void batch3d_item(const BatchInst &I, int4 it, int phase, bool copy, int LX,
                                              int LY, int LZ, int LZR, unsigned char *smem_raw)
 {
     if (!copy) {
         const T *src = static_cast<const T *>((phase & 1) ? I.work : I.phi);
         T *dst = static_cast<T *>((phase & 1) ? I.phi : I.work);
-        if constexpr (sizeof(T) == 4) {
+        if constexpr (REG && sizeof(T) == 4) {
             if (it.w) {
                 reg3d_body<T, K, kReg3dRows, true>(src, dst, I.nx, I.ny, I.nz, (T)I.alpha, (T)I.r, LZR,
                                                    I.rtiles_x, it.y, it.z,
@@ -295,7 +295,7 @@ __device__ __forceinline__ void batch3d_item(const BatchInst &I, int4 it, int ph
         }
         stream3d_body<T, K, CPT>(src, dst, I.nx, I.ny, I.nz, (T)I.alpha, (T)I.r, LX, LY, LZ,
                                  I.tiles_x, it.y, it.z, smem_raw);
-    } else if (it.w) {
+    } else if (REG && it.w) {
         copy_tile3d_reg<T>(static_cast<const T *>(I.work), static_cast<T *>(I.phi), I.nx, I.ny, I.nz, K,
                            LZR, I.rtiles_x, it.y, it.z);
     } else {
@@ -308,7 +308,7 @@ __device__ __forceinline__ void batch3d_item(const BatchInst &I, int4 it, int ph
 // item by K steps with a z-streaming body of ac_step_3d (batch3d_item).  Phases are
 // numbered from phase0 for the phi/work ping-pong, so a second launch can run
 // a shorter remainder phase.  Scheduling as in batched_kernel.
-template <typename T, int K, int CPT>
+template <typename T, int K, int CPT, bool REG>
 __global__ void __launch_bounds__(512)
 batched3d_kernel(const BatchInst *__restrict__ inst, const int4 *__restrict__ items, int n_items,
                  int LX, int LY, int LZ, int LZR, int nphase, int phase0, int copy_back,
@@ -333,7 +333,7 @@ batched3d_kernel(const BatchInst *__restrict__ inst, const int4 *__restrict__ it
             unsigned next = 0;
             if (threadIdx.x == 0) next = atomicAdd(tickets, 1u);
             const BatchInst I = inst[it.x];
-            batch3d_item<T, K, CPT>(I, it, phase0 + b, b >= nphase, LX, LY, LZ, LZR, smem_raw);
+            batch3d_item<T, K, CPT, REG>(I, it, phase0 + b, b >= nphase, LX, LY, LZ, LZR, smem_raw);
             if (threadIdx.x == 0) s_ticket = next;
             __syncthreads();
             t = s_ticket;
@@ -347,7 +347,7 @@ batched3d_kernel(const BatchInst *__restrict__ inst, const int4 *__restrict__ it
 
 // Phase-graph mode for 3D batches: one launch per phase, one workgroup per item
 // (XCD-aware slices as in batched_phase_kernel).  copy: the final copy phase.
-template <typename T, int K, int CPT>
+template <typename T, int K, int CPT, bool REG>
 __global__ void __launch_bounds__(512)
 batched3d_phase_kernel(const BatchInst *__restrict__ inst, const int4 *__restrict__ items,
                        int n_items, int LX, int LY, int LZ, int LZR, int phase, int copy)
@@ -358,7 +358,7 @@ batched3d_phase_kernel(const BatchInst *__restrict__ inst, const int4 *__restric
     if ((int)(blockIdx.x >> 3) >= per || i >= n_items) return;     // whole workgroup
     const int4 it = items[i];
     const BatchInst I = inst[it.x];
-    batch3d_item<T, K, CPT>(I, it, phase, copy != 0, LX, LY, LZ, LZR, smem_raw);
+    batch3d_item<T, K, CPT, REG>(I, it, phase, copy != 0, LX, LY, LZ, LZR, smem_raw);
 }
 
 // ---------------------------------------------------------------- host ----
@@ -676,42 +676,54 @@ ac_status validate_batch3(const ac_instance3d *inst, int32_t n, int64_t nsteps, 
     return AC_OK;
 }
 
-template <typename T, int K>
+// REG: the batch has register-tile items (the kernel then carries both
+// bodies; without them it keeps the LDS body's register count)
+template <typename T, int K, bool REG>
 const void *kernel3_cpt(int cpt) {
-    if (cpt <= 1) return (const void *)batched3d_kernel<T, K, 1>;
-    if (cpt <= 2) return (const void *)batched3d_kernel<T, K, 2>;
-    if (cpt <= 4) return (const void *)batched3d_kernel<T, K, 4>;
+    if (cpt <= 1) return (const void *)batched3d_kernel<T, K, 1, REG>;
+    if (cpt <= 2) return (const void *)batched3d_kernel<T, K, 2, REG>;
+    if (cpt <= 4) return (const void *)batched3d_kernel<T, K, 4, REG>;
     return nullptr;
 }
 
-template <typename T, int K>
+template <typename T, int K, bool REG>
 const void *phase3_cpt(int cpt) {
-    if (cpt <= 1) return (const void *)batched3d_phase_kernel<T, K, 1>;
-    if (cpt <= 2) return (const void *)batched3d_phase_kernel<T, K, 2>;
-    if (cpt <= 4) return (const void *)batched3d_phase_kernel<T, K, 4>;
+    if (cpt <= 1) return (const void *)batched3d_phase_kernel<T, K, 1, REG>;
+    if (cpt <= 2) return (const void *)batched3d_phase_kernel<T, K, 2, REG>;
+    if (cpt <= 4) return (const void *)batched3d_phase_kernel<T, K, 4, REG>;
     return nullptr;
 }
 
-template <typename T>
+template <typename T, bool REG>
 const void *phase3_of(int K, int cpt) {
     switch (K) {
-    case 1: return phase3_cpt<T, 1>(cpt);
-    case 2: return phase3_cpt<T, 2>(cpt);
-    case 3: return phase3_cpt<T, 3>(cpt);
-    case 4: return phase3_cpt<T, 4>(cpt);
+    case 1: return phase3_cpt<T, 1, REG>(cpt);
+    case 2: return phase3_cpt<T, 2, REG>(cpt);
+    case 3: return phase3_cpt<T, 3, REG>(cpt);
+    case 4: return phase3_cpt<T, 4, REG>(cpt);
     default: return nullptr;
     }
 }
 
-template <typename T>
+template <typename T, bool REG>
 const void *kernel3_of(int K, int cpt) {
     switch (K) {
-    case 1: return kernel3_cpt<T, 1>(cpt);
-    case 2: return kernel3_cpt<T, 2>(cpt);
-    case 3: return kernel3_cpt<T, 3>(cpt);
-    case 4: return kernel3_cpt<T, 4>(cpt);
+    case 1: return kernel3_cpt<T, 1, REG>(cpt);
+    case 2: return kernel3_cpt<T, 2, REG>(cpt);
+    case 3: return kernel3_cpt<T, 3, REG>(cpt);
+    case 4: return kernel3_cpt<T, 4, REG>(cpt);
     default: return nullptr;
     }
+}
+
+// the kernels of a 3D batch: FP64 never has register items
+const void *kernel3_sel(bool f64, bool reg, int K, int cpt) {
+    return f64 ? kernel3_of<double, false>(K, cpt)
+               : (reg ? kernel3_of<float, true>(K, cpt) : kernel3_of<float, false>(K, cpt));
+}
+const void *phase3_sel(bool f64, bool reg, int K, int cpt) {
+    return f64 ? phase3_of<double, false>(K, cpt)
+               : (reg ? phase3_of<float, true>(K, cpt) : phase3_of<float, false>(K, cpt));
 }
 
 ac_status build_plan3d(Plan &p, const ac_instance3d *inst, int32_t n, int64_t nsteps,
@@ -777,9 +789,8 @@ ac_status build_plan3d(Plan &p, const ac_instance3d *inst, int32_t n, int64_t ns
         return fail(AC_ERR_UNSUPPORTED, "%zu tiles x %lld phases exceed the 32-bit work counters",
                     items.size(), (long long)phases);
     const bool f64 = dtype == AC_F64;
-    const void *kA = f64 ? kernel3_of<double>(K, cpt) : kernel3_of<float>(K, cpt);
-    const void *kB = rem ? (f64 ? kernel3_of<double>((int)rem, cpt) : kernel3_of<float>((int)rem, cpt))
-                         : nullptr;
+    const void *kA = kernel3_sel(f64, any_reg, K, cpt);
+    const void *kB = rem ? kernel3_sel(f64, any_reg, (int)rem, cpt) : nullptr;
     if (!kA || (rem && !kB)) return fail(AC_ERR_UNSUPPORTED, "no batched 3D kernel for this shape");
     Tile3D tB{LX, LY, LZ, (int)(rem ? rem : K), threads};
     const size_t ldsA = std::max(stream3d_lds_bytes(t3, elem), any_reg ? reg3d_lds_bytes(K, 32, elem) : 0);
@@ -829,9 +840,8 @@ ac_status build_plan3d(Plan &p, const ac_instance3d *inst, int32_t n, int64_t ns
     const int phase_grid = 8 * ((ni + 7) / 8);
     if (!g_persistent) {
         // one launch per phase: q of K steps, one of the remaining steps, a copy
-        const void *pA = f64 ? phase3_of<double>(K, cpt) : phase3_of<float>(K, cpt);
-        const void *pB = rem ? (f64 ? phase3_of<double>((int)rem, cpt) : phase3_of<float>((int)rem, cpt))
-                             : nullptr;
+        const void *pA = phase3_sel(f64, any_reg, K, cpt);
+        const void *pB = rem ? phase3_sel(f64, any_reg, (int)rem, cpt) : nullptr;
         set_lds_limit(pA, ldsA);
         if (pB) set_lds_limit(pB, ldsB);
         for (int64_t b = 0; b < phases + cb && le == hipSuccess; ++b) {
