@@ -351,10 +351,8 @@ ac_status make_plan3d(int nx, int ny, int nz, int64_t nsteps, size_t elem, const
         // leave fewer workgroups.  LDS tiles: lengthen them only while the grid
         // still has about eight rounds of resident workgroups (measured: 1024^3
         // gains 15 % at 128 planes, 256^3 loses at anything above 32).
-        // FP32 register tiles (3 workgroups per CU): while one full round
-        // remains (measured: 512^3 1446 -> 1505 GLUPS at 64 planes, 1024^3
-        // +2 % at 128; 256^3 keeps 32).  FP64 register tiles (2 per CU) keep
-        // the eight-round rule (512^3: 697 GLUPS at 32 planes, 598 at 128).
+        // FP32 register tiles: below.  FP64 register tiles (2 per CU) keep the
+        // eight-round rule (512^3: 697 GLUPS at 32 planes, 598 at 128).
         const int64_t xy = reg ? (int64_t)ac::reg2d_tiles_1d(nx, 64, K) * ac::reg2d_tiles_1d(ny, LY, K)
                                : (int64_t)((nx + LX - 2 * K - 1) / (LX - 2 * K)) *
                                      ((ny + LY - 2 * K - 1) / (LY - 2 * K));
@@ -364,7 +362,35 @@ ac_status make_plan3d(int nx, int ny, int nz, int64_t nsteps, size_t elem, const
                                                      1) *
                                        dev.cus
                                  : 32LL * dev.cus;
-        while (LZ < 128 && xy * ((nz + 2 * LZ - 1) / (2 * LZ)) >= want) LZ *= 2;
+        const int64_t two_per_cu = 2LL * std::max(dev.cus, 1);
+        if (reg && !f64 && xy * ((nz + 31) / 32) < 2 * two_per_cu) {
+            // FP32 register tiles on a grid of less than two rounds of
+            // 32-plane segments: S = floor(2 CUs / xy) segments of floor(nz /
+            // S) planes, the remainder in one short extra segment, so no CU
+            // takes more than two long segments.  Measured on MI355X at 256^3,
+            // depth 4: 28 planes 1211 GLUPS against 1112 at 32, 947 at 26 (all
+            // ten segments long) and 905 at 64 (one workgroup per CU); depth 5
+            // (S = 8): 32 planes, its best.
+            const int64_t S = std::max<int64_t>(1, two_per_cu / std::max<int64_t>(xy, 1));
+            LZ = (int)std::max<int64_t>(16, std::min<int64_t>(128, nz / S));
+        } else if (reg && !f64) {
+            // longer segments re-stream fewer halo planes, but the last round
+            // of resident workgroups may run part-empty: the length in {32, 64,
+            // 128} with the least (rounds, rounded up) x (LZ + 1.5 K).
+            // Measured: 512^3 64 planes (1506 GLUPS; 128: 1468, 1.5 rounds),
+            // 1024^3 128 (+2 % over 64)
+            double best = 0;
+            for (int lz = 32; lz <= 128; lz *= 2) {
+                const int64_t rounds = (xy * ((nz + lz - 1) / lz) + want - 1) / want;
+                const double cost = (double)rounds * (lz + 1.5 * K);
+                if (lz == 32 || cost < best) {
+                    best = cost;
+                    LZ = lz;
+                }
+            }
+        } else {
+            while (LZ < 128 && xy * ((nz + 2 * LZ - 1) / (2 * LZ)) >= want) LZ *= 2;
+        }
     }
     ac::Tile3D t{LX, LY, LZ, K, threads};
     if (!reg && ac::stream3d_cells_per_thread(t) > 4)

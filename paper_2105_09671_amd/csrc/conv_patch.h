@@ -39,6 +39,7 @@ namespace sur {
 
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 // float -> bf16, round to nearest even, by the hardware conversion
 // (v_cvt_pk_bf16_f32): one instruction where f2bf's NaN test branches.  The
@@ -72,25 +73,51 @@ constexpr int conv3p_lds_bytes() {
                : stage_lds_bytes<RW, CN>();
 }
 
+// The FP32 phi values of a tile's (TY + 4) x 68 phi patch (rows and columns
+// clamped to the image) that thread t < 204 stages: column t % 68 of rows
+// t / 68 + 3 i.  Loaded one tile ahead of their use.
+template <int TY>
+constexpr int phi_rows() { return (TY + 4 + 2) / 3; }
+
+template <int TY>
+__device__ __forceinline__ void phi_issue(const ConvAux &aux, float (&pv)[phi_rows<TY>()], int n, int H,
+                                          int W, int y0, int x0)
+{
+    const int t = threadIdx.x;
+    if (t >= 204) return;
+    const int c = t % 68, rg = t / 68;
+    const float *col = aux.phi + (size_t)n * H * W + min(max(x0 - 2 + c, 0), W - 1);
+#pragma unroll
+    for (int i = 0; i < phi_rows<TY>(); ++i) {
+        const int r = rg + 3 * i;
+        if (r < TY + 4) pv[i] = col[(size_t)min(max(y0 - 2 + r, 0), H - 1) * W];
+    }
+}
+
 // The patch of the first layer's output, e1a = relu(b1 + sum_tap w1[c][tap] *
 // bf16(phi)[neighbour]) rounded to BF16, for (TY + 2) x 66 pixels (rows and
-// columns clamped like any patch; each pixel's own 3 x 3 neighbourhood
-// clamped again) and 32 channels, written at the patch pitch.  It is a GEMM
-// of 32-pixel fragments on v_mfma_f32_32x32x16_bf16, computed transposed:
-// A = the weights (32 channels x K), B = each pixel's 9 BF16 neighbours of
-// phi at K = 0..8 (K = 9..15 zero), FP32 accumulation, then the bias.
+// columns clamped like any patch, so a pixel outside the image repeats the
+// nearest one inside) and 32 channels, written at the patch pitch.  It is a
+// GEMM of 32-pixel fragments on v_mfma_f32_32x32x16_bf16, computed
+// transposed: A = the weights (32 channels x K), B = each pixel's 9 BF16
+// neighbours of phi at K = 0..8, FP32 accumulation, then the bias.  K = 9..15
+// carry zero weights (lanes 32..63 feed them taps 1..7 of the same
+// neighbourhood, finite values, so no lane needs a select).  pv: the tile's
+// phi values from phi_issue; the caller may reload pv once this returns.
 template <int TY>
-__device__ inline void first_layer_patch(const ConvAux &aux, bf16_t *lds, int n, int H, int W,
-                                         int y0, int x0)
+__device__ inline void first_layer_patch(const ConvAux &aux, const float (&pv)[phi_rows<TY>()],
+                                         bf16_t *lds, int n, int H, int W, int y0, int x0)
 {
     constexpr int PR = TY + 4, PCOL = 68, NPIX = (TY + 2) * PW, NF = (NPIX + 31) / 32;
     float *ph = reinterpret_cast<float *>(lds + (TY + 2) * PW * PP);
     const int t = threadIdx.x, lane = t & 63, w = t >> 6, l32 = lane & 31, hi = lane >> 5;
-    const float *img = aux.phi + (size_t)n * H * W;
-    for (int v = t; v < PR * PCOL; v += 256) {
-        const int r = v / PCOL, c = v - r * PCOL;
-        const int gy = min(max(y0 - 2 + r, 0), H - 1), gx = min(max(x0 - 2 + c, 0), W - 1);
-        ph[v] = bf2f(f2bf(img[(size_t)gy * W + gx]));
+    if (t < 204) {
+        const int c = t % 68, rg = t / 68;
+#pragma unroll
+        for (int i = 0; i < phi_rows<TY>(); ++i) {
+            const int r = rg + 3 * i;
+            if (r < PR) ph[r * PCOL + c] = bf2f(f2bf_rn(pv[i]));
+        }
     }
     // A operand: lane supplies K = 8 hi .. 8 hi + 7 of output channel l32
     // (lanes 0..31: taps 0..7; lanes 32..63: tap 8, then zeros)
@@ -98,7 +125,7 @@ __device__ inline void first_layer_patch(const ConvAux &aux, bf16_t *lds, int n,
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
         const int k = 8 * hi + e;
-        wa[e] = __builtin_bit_cast(__bf16, k < 9 ? f2bf(aux.w1[l32 * 9 + k]) : (bf16_t)0);
+        wa[e] = k < 9 ? (__bf16)aux.w1[l32 * 9 + k] : (__bf16)0.f;
     }
     // the product's lane holds channels 8 g + 4 hi + r (g, r = 0..3) of one pixel
     float bias[4][4];
@@ -110,21 +137,16 @@ __device__ inline void first_layer_patch(const ConvAux &aux, bf16_t *lds, int n,
     for (int f = w; f < NF; f += 4) {
         const int pix = min(32 * f + l32, NPIX - 1);
         const int pr = pix / PW, pc = pix - pr * PW;
-        const int gy = min(max(y0 - 1 + pr, 0), H - 1), gx = min(max(x0 - 1 + pc, 0), W - 1);
-        // phi patch row / column of image row / column Y: Y - (y0 - 2)
-        int ro[3], co[3];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            ro[d] = (min(max(gy + d - 1, 0), H - 1) - (y0 - 2)) * PCOL;
-            co[d] = min(max(gx + d - 1, 0), W - 1) - (x0 - 2);
-        }
-        const float v8 = ph[ro[2] + co[2]];
+        // the pixel itself clamped to the image, in phi-patch coordinates;
+        // the patch was loaded clamped, so its 3 x 3 neighbourhood there is
+        // the replicate-padded one
+        const int cy = min(max(y0 - 1 + pr, 0), H - 1) - (y0 - 2);
+        const int cx = min(max(x0 - 1 + pc, 0), W - 1) - (x0 - 2);
+        const float *nb = ph + (cy - 1) * PCOL + (cx - 1);
         bf16x8 b;
+        b[0] = (__bf16)nb[hi ? 2 * PCOL + 2 : 0];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const float v = ph[ro[e / 3] + co[e % 3]];
-            b[e] = (__bf16)(hi == 0 ? v : (e == 0 ? v8 : 0.f));
-        }
+        for (int e = 1; e < 8; ++e) b[e] = (__bf16)nb[(e / 3) * PCOL + e % 3];
         floatx16 acc = {};
         acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wa, b, acc, 0, 0, 0);
         if (32 * f + l32 < NPIX) {
@@ -153,10 +175,13 @@ __device__ inline void first_layer_patch(const ConvAux &aux, bf16_t *lds, int n,
     }
 }
 
-// Row-major tile grid over B images of H x W: (image, tile row, tile column);
-// consecutive workgroups take horizontally, then vertically adjacent tiles of
-// one image, and with the XCD-aware numbering (xcd_tile) each XCD takes a
-// contiguous band, so the halo rows two tiles share are read through one L2.
+// Tiles: (image, tile row, tile column), row-major over B images of H x W.
+// The launch is persistent: the tiles are cut into eight contiguous bands,
+// one per XCD (workgroup b runs on XCD b % 8), and each workgroup walks its
+// band with a stride of gridDim.x / 8, so adjacent tiles (which share halo
+// rows) meet in one L2.  While a chunk's 9 taps run, the patch of the next
+// chunk -- or of the next tile's first chunk -- is already being loaded into
+// registers, so a workgroup's MFMAs do not wait for its loads.
 //
 // FIRST: the layer's input is the first layer's output e1a = relu(conv3(phi;
 // 1 -> 32)), computed into the patch from an FP32 phi patch (rounded to BF16,
@@ -167,35 +192,44 @@ __device__ inline void first_layer_patch(const ConvAux &aux, bf16_t *lds, int n,
 // spills (not the 128-channel layer, not the training copy of the last
 // layer): about 1 % faster over the forward pass than the default allocation.
 constexpr bool kConv3pWaves3 = true;
-template <int CIN, int RW, bool HEAD>
-constexpr int conv3p_waves() { return kConv3pWaves3 && !(CIN == 128 || (RW == 2 && !HEAD)) ? 3 : 1; }
+// kConvPrefetch: load the next chunk's patch (or the next tile's first) into
+// registers while the current chunk's taps run
+constexpr bool kConvPrefetch = false;
+// kConvPersistent: the launch holds one round of resident workgroups, each
+// walking its band of tiles; else one workgroup per tile
+constexpr bool kConvPersistent = false;
+template <int CIN, int CN, int RW, bool HEAD>
+constexpr int conv3p_waves() { return CIN <= 64 && RW == 1 ? 3 : 2; }
 
 template <int CIN, int CN, int RW, int LOWC, bool POOL, bool HEAD, bool FIRST = false>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(conv3p_waves<CIN, RW, HEAD>())))
-conv3_patch_kernel(View X, View Xlo, int B, int H, int W, const bf16_t *__restrict__ Wf,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(conv3p_waves<CIN, CN, RW, HEAD>())))
+conv3_patch_kernel(View X, View Xlo, int B, int H, int W, const bf16_t *Wf,
                    const float *__restrict__ bias, int Cout, View Y, View P, ConvAux aux)
 {
     static_assert(CIN % PC == 0 && LOWC % PC == 0 && LOWC <= CIN, "32-channel chunks");
     static_assert(!FIRST || (CIN == 32 && LOWC == 0), "the first layer has 32 outputs");
     static_assert(CN == 32 || CN == 64, "channel slice of 32 or 64");
     static_assert(!HEAD || CN == 32, "the head needs all 32 channels of a pixel");
-    constexpr int TY = 4 * RW, NI = 4 * RW, NJ = CN / 16, NCH = CIN / PC;
+    constexpr int TY = 4 * RW, NI = 4 * RW, NJ = CN / 16, NCH = CIN / PC, PR = TY + 2;
+    constexpr bool kTapBarrier = !FIRST;
     extern __shared__ __align__(16) bf16_t lds[];
     const int tiles_x = (W + 63) >> 6, tiles_y = (H + TY - 1) / TY;
-    const int ntiles = B * tiles_y * tiles_x;
-    const int tile = xcd_tile(ntiles);
-    if (tile >= ntiles) return;                      // padding workgroup (whole group)
-    const int n = tile / (tiles_y * tiles_x), rem = tile - n * tiles_y * tiles_x;
-    const int y0 = (rem / tiles_x) * TY, x0 = (rem % tiles_x) * 64;
+    const int tpi = tiles_y * tiles_x;
+    const int ntiles = B * tpi;
+    // this workgroup's tiles: band of XCD blockIdx.x % 8, stride gridDim.x / 8
+    const int per = (ntiles + 7) >> 3;
+    const int band_end = min(((int)blockIdx.x & 7) * per + per, ntiles);
+    const int stride = (int)gridDim.x >> 3;
+    int tile = ((int)blockIdx.x & 7) * per + ((int)blockIdx.x >> 3);
+    if (tile >= band_end) return;                    // no tile (whole group)
     const int n0 = blockIdx.y * CN;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int lr = lane & 15, lq = lane >> 4;
 
-    // per-lane A base of fragment i = (row r, 16-pixel group g), bf16 units
-    int abase[NI];
-#pragma unroll
-    for (int i = 0; i < NI; ++i)
-        abase[i] = ((RW * w + i / 4) * PW + 16 * (i % 4) + lr) * PP + 8 * lq;
+    // wave w owns the 16-column strip 16 w .. 16 w + 15 of all TY tile rows:
+    // fragment i = tile row i.  Per-lane A base of patch row 0, bf16 units; the
+    // fragment of patch row r shifted by dx columns is at fbase + (r PW + dx) PP
+    const int fbase = (16 * w + lr) * PP + 8 * lq;
     // B fragment (chunk, tap, j) of this workgroup's channel slice: lane's 16
     // bytes at Wf + (((chunk * 9 + tap) * (Cout / 16) + n0 / 16 + j) * 64 + lane) * 8;
     // the step part is uniform (scalar arithmetic), the lane part a fixed
@@ -203,152 +237,191 @@ conv3_patch_kernel(View X, View Xlo, int B, int H, int W, const bf16_t *__restri
     const int ntile16 = Cout >> 4;
     const bf16_t *wslice = Wf + (size_t)(n0 >> 4) * 512;
     const int wl = lane * 8;
-
-    floatx4 acc[NI][NJ] = {};
-    // two slots of B fragments: K step s (over all chunks) uses slot s & 1 and
-    // loads step s + 1 into the other; the chunk loop is unrolled (at most 4
-    // chunks), so every slot index is static and nothing is copied
-    bf16x8 bq[2][NJ];
-    auto loadB = [&](int step, bf16x8 (&dst)[NJ]) {
-        const bf16_t *wb = wslice + (size_t)step * ntile16 * 512;
+    // K steps run chunk by chunk, per chunk column shift dx by dx and per dx
+    // row shift dy by dy: step q is tap 3 dy + dx of chunk q / 9
+    auto loadB = [&](int q, bf16x8 (&dst)[NJ]) __attribute__((always_inline)) {
+        const int ch = q / 9, dx = (q % 9) / 3, dy = q % 3;
+        const bf16_t *wb = wslice + (size_t)(ch * 9 + 3 * dy + dx) * ntile16 * 512;
 #pragma unroll
         for (int j = 0; j < NJ; ++j) dst[j] = *reinterpret_cast<const bf16x8 *>(wb + j * 512 + wl);
     };
-    loadB(0, bq[0]);
 
     // patch copy: in every patch row, lanes 16 k .. 16 k + 15 of wave w move
     // 16-byte group k of patch columns 16 w .. 16 w + 15 (sixteen consecutive
     // pixels of one group per quarter-wave, as the fragment reads: no bank
-    // conflict at the 80-byte pitch); all rows' loads are issued before their
-    // LDS writes; threads 0 .. 8 (TY + 2) - 1 move the two columns beyond
+    // conflict at the 80-byte pitch); threads 0 .. 8 (TY + 2) - 1 also move
+    // the two columns beyond.  issue() loads a chunk's rows into registers,
+    // commit() writes them to LDS.
     const int pq = (t >> 4) & 3, pcol = (t & 15) + 16 * w;
     const int ex_q = t & 3, ex_r = t >> 3, ex_c = 64 + ((t >> 2) & 1);
-#pragma unroll
-    for (int ch = 0; ch < NCH; ++ch) {
-        // ---- stage the patch of this 32-channel chunk (clamped = replicate pad)
-        const bool low = ch * PC < LOWC;
-        const View S = low ? Xlo : X;
-        const int cofs = low ? ch * PC : ch * PC - LOWC;
-        const int Hs = low ? (H >> 1) : H, Ws = low ? (W >> 1) : W;
-        if (ch > 0) __syncthreads();                 // every wave is done with the previous chunk
+    const bool ex = ex_r < PR;
+    u32x4 val[FIRST ? 1 : PR], vex = {};
+    float pv[phi_rows<TY>()];
+    auto issue = [&](int tl, int ch) __attribute__((always_inline)) {
+        const int n = tl / tpi, rem = tl - n * tpi;
+        const int y0 = (rem / tiles_x) * TY, x0 = (rem % tiles_x) * 64;
         if constexpr (FIRST) {
-            first_layer_patch<TY>(aux, lds, n, H, W, y0, x0);
+            phi_issue<TY>(aux, pv, n, H, W, y0, x0);
         } else {
+            const bool low = ch * PC < LOWC;
+            const View S = low ? Xlo : X;
+            const int cofs = low ? ch * PC : ch * PC - LOWC;
+            const int Hs = low ? (H >> 1) : H, Ws = low ? (W >> 1) : W;
             const bf16_t *img = S.p + (size_t)n * Hs * Ws * S.Cs + S.Co + cofs + 8 * pq;
             int gx = min(max(x0 - 1 + pcol, 0), W - 1);
             if (low) gx >>= 1;
-            uint4 val[TY + 2];
 #pragma unroll
-            for (int pr = 0; pr < TY + 2; ++pr) {
+            for (int pr = 0; pr < PR; ++pr) {
                 int gy = min(max(y0 - 1 + pr, 0), H - 1);
                 if (low) gy >>= 1;
-                val[pr] = *reinterpret_cast<const uint4 *>(img + ((size_t)gy * Ws + gx) * S.Cs);
+                val[pr] = *reinterpret_cast<const u32x4 *>(img + ((size_t)gy * Ws + gx) * S.Cs);
             }
-            uint4 vex = {};
-            const bool ex = ex_r < TY + 2;
             if (ex) {
                 int gy = min(max(y0 - 1 + ex_r, 0), H - 1), gxe = min(max(x0 - 1 + ex_c, 0), W - 1);
                 if (low) { gy >>= 1; gxe >>= 1; }
-                vex = *reinterpret_cast<const uint4 *>(img + 8 * (ex_q - pq) +
-                                                       ((size_t)gy * Ws + gxe) * S.Cs);
+                vex = *reinterpret_cast<const u32x4 *>(img + 8 * (ex_q - pq) + ((size_t)gy * Ws + gxe) * S.Cs);
             }
+        }
+    };
+    auto commit = [&]() __attribute__((always_inline)) {
 #pragma unroll
-            for (int pr = 0; pr < TY + 2; ++pr)
-                *reinterpret_cast<uint4 *>(lds + (pr * PW + pcol) * PP + 8 * pq) = val[pr];
-            if (ex) *reinterpret_cast<uint4 *>(lds + (ex_r * PW + ex_c) * PP + 8 * ex_q) = vex;
+        for (int pr = 0; pr < PR; ++pr)
+            *reinterpret_cast<u32x4 *>(lds + (pr * PW + pcol) * PP + 8 * pq) = val[pr];
+        if (ex) *reinterpret_cast<u32x4 *>(lds + (ex_r * PW + ex_c) * PP + 8 * ex_q) = vex;
+    };
+
+    if (kConvPrefetch) issue(tile, 0);
+    for (bool first = true;; first = false) {
+        const int n = tile / tpi, rem = tile - n * tpi;
+        const int y0 = (rem / tiles_x) * TY, x0 = (rem % tiles_x) * 64;
+        const int next = tile + stride;
+        const bool more = next < band_end;
+        floatx4 acc[NI][NJ] = {};
+        // two slots of B fragments: K step s (over all chunks) uses slot s & 1
+        // and loads step s + 1 into the other; the chunk loop is unrolled (at
+        // most 4 chunks), so every slot index is static and nothing is copied
+        bf16x8 bq[2][NJ];
+        loadB(0, bq[0]);
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) {
+            // ---- stage the patch of this 32-channel chunk (clamped = replicate
+            // pad) once every wave is done with the LDS, then start the next load
+            if (!first || ch > 0) __syncthreads();
+            if (!kConvPrefetch) issue(tile, ch);
+            if constexpr (FIRST) {
+                first_layer_patch<TY>(aux, pv, lds, n, H, W, y0, x0);
+                if (kConvPrefetch && more) issue(next, 0);
+            } else {
+                commit();
+                if (kConvPrefetch) {
+                    if (ch + 1 < NCH) issue(tile, ch + 1);
+                    else if (more) issue(next, 0);
+                }
+            }
+            __syncthreads();
+            // ---- 9 taps of this chunk.  Per column shift dx the wave reads the
+            // TY + 2 patch rows of its strip once; tile row i takes tap (dy, dx)
+            // from patch row i + dy, so each fragment read serves three taps
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) {
+                bf16x8 a[TY + 2];
+#pragma unroll
+                for (int r = 0; r < TY + 2; ++r)
+                    a[r] = *reinterpret_cast<const bf16x8 *>(lds + fbase + (r * PW + dx) * PP);
+#pragma unroll
+                for (int dy = 0; dy < 3; ++dy) {
+                    const int step = ch * 9 + 3 * dx + dy;
+                    if (step + 1 < NCH * 9) loadB(step + 1, bq[(step + 1) & 1]);
+#pragma unroll
+                    for (int i = 0; i < NI; ++i)
+#pragma unroll
+                        for (int j = 0; j < NJ; ++j)
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bq[step & 1][j], a[i + dy],
+                                                                                 acc[i][j], 0, 0, 0);
+                    // the 128-channel layers: keep each tap's loads within the
+                    // tap, or the scheduler's early loads spill
+                    if constexpr (kTapBarrier) __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+        }
+
+        // ---- epilogue: bias + relu -> bf16, staged in LDS as [pixel][CN].  The
+        // products are computed transposed (weights as the MFMA's A operand), so
+        // a lane holds 4 consecutive channels 16 j + 4 (lane / 16) + r of one
+        // pixel: one 8-byte LDS write per fragment
+        __syncthreads();                             // the patch is dead
+        constexpr int SP = CN + 8;
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            const int c0 = 16 * j + 4 * lq;
+            float bv[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) bv[r] = bias[n0 + c0 + r];
+#pragma unroll
+            for (int i = 0; i < NI; ++i) {
+                const int pix = i * 64 + 16 * w + lr;
+                bf16x4 o;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const float v = acc[i][j][r] + bv[r];
+                    o[r] = (__bf16)(v > 0.f ? v : 0.f);
+                }
+                *reinterpret_cast<bf16x4 *>(lds + pix * SP + c0) = o;
+            }
         }
         __syncthreads();
-        // ---- 9 taps of this chunk: A from the patch, B one step ahead
+        if constexpr (HEAD) {
+            // one thread per pixel: out = phi + (hb + sum_c a_c wh_c), c in order
+            for (int pix = t; pix < TY * 64; pix += 256) {
+                const int y = y0 + (pix >> 6), x = x0 + (pix & 63);
+                if (y >= H || x >= W) continue;
+                const bf16_t *a = lds + pix * SP;
+                float s = aux.hb[0];
 #pragma unroll
-        for (int tap = 0; tap < 9; ++tap) {
-            const int dy = tap / 3, dx = tap % 3;
-            const int step = ch * 9 + tap;
-            if (step + 1 < NCH * 9) loadB(step + 1, bq[(step + 1) & 1]);
-            bf16x8 a[NI];
-#pragma unroll
-            for (int i = 0; i < NI; ++i)
-                a[i] = *reinterpret_cast<const bf16x8 *>(lds + abase[i] + (dy * PW + dx) * PP);
-#pragma unroll
-            for (int i = 0; i < NI; ++i)
-#pragma unroll
-                for (int j = 0; j < NJ; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bq[step & 1][j], a[i], acc[i][j], 0, 0, 0);
-        }
-    }
-
-    // ---- epilogue: bias + relu -> bf16, staged in LDS as [pixel][CN].  The
-    // products are computed transposed (weights as the MFMA's A operand), so
-    // a lane holds 4 consecutive channels 16 j + 4 (lane / 16) + r of one
-    // pixel: one 8-byte LDS write per fragment
-    __syncthreads();                                 // the patch is dead
-    constexpr int SP = CN + 8;
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-        const int c0 = 16 * j + 4 * lq;
-        float bv[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) bv[r] = bias[n0 + c0 + r];
-#pragma unroll
-        for (int i = 0; i < NI; ++i) {
-            const int pix = (RW * w + i / 4) * 64 + 16 * (i % 4) + lr;
-            bf16x4 o;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const float v = acc[i][j][r] + bv[r];
-                o[r] = (__bf16)(v > 0.f ? v : 0.f);
+                for (int c = 0; c < 32; ++c) s += bf2f(a[c]) * aux.wh[c];
+                const size_t g = (size_t)(n * H + y) * W + x;
+                aux.out[g] = aux.phi[g] + s;
             }
-            *reinterpret_cast<bf16x4 *>(lds + pix * SP + c0) = o;
-        }
-    }
-    __syncthreads();
-    if constexpr (HEAD) {
-        // one thread per pixel: out = phi + (hb + sum_c a_c wh_c), c in order
-        for (int pix = t; pix < TY * 64; pix += 256) {
-            const int y = y0 + (pix >> 6), x = x0 + (pix & 63);
-            if (y >= H || x >= W) continue;
-            const bf16_t *a = lds + pix * SP;
-            float s = aux.hb[0];
-#pragma unroll
-            for (int c = 0; c < 32; ++c) s += bf2f(a[c]) * aux.wh[c];
-            const size_t g = (size_t)(n * H + y) * W + x;
-            aux.out[g] = aux.phi[g] + s;
-        }
-        return;
-    }
-    constexpr int CQ = CN / 8;                       // 16-byte groups per pixel
-    // consecutive lanes write consecutive 16-byte groups of a pixel (whole
-    // 64- or 128-byte pixel rows per lane group: measured faster than the
-    // LDS-conflict-free order of sixteen pixels per quarter-wave)
-    for (int v = t; v < TY * 64 * CQ; v += 256) {
-        const int q = v % CQ, pix = v / CQ;
-        const int y = y0 + pix / 64, x = x0 + (pix & 63);
-        if (y >= H || x >= W) continue;
-        *reinterpret_cast<uint4 *>(Y.p + ((size_t)(n * H + y) * W + x) * Y.Cs + Y.Co + n0 + 8 * q) =
-            *reinterpret_cast<const uint4 *>(lds + pix * SP + 8 * q);
-    }
-    if constexpr (POOL) {
-        // 2 x 2 averages of the tile (TY and the tile origin are even), summed
-        // in the order (y, x), (y, x+1), (y+1, x), (y+1, x+1) like pool_kernel
-        const int Ho = H >> 1, Wo = W >> 1;
-        for (int v = t; v < (TY / 2) * 32 * CQ; v += 256) {
-            const int q = v % CQ, pp = v / CQ, py = pp / 32, px = pp % 32;
-            const int oy = (y0 >> 1) + py, ox = (x0 >> 1) + px;
-            if (oy >= Ho || ox >= Wo) continue;
-            float s[8] = {};
-#pragma unroll
-            for (int d = 0; d < 4; ++d) {
-                const int pix = (2 * py + (d >> 1)) * 64 + 2 * px + (d & 1);
-                const uint4 u = *reinterpret_cast<const uint4 *>(lds + pix * SP + 8 * q);
-                const bf16_t *e = reinterpret_cast<const bf16_t *>(&u);
-#pragma unroll
-                for (int k = 0; k < 8; ++k) s[k] += bf2f(e[k]);
+        } else {
+            constexpr int CQ = CN / 8;               // 16-byte groups per pixel
+            // consecutive lanes write consecutive 16-byte groups of a pixel
+            // (whole 64- or 128-byte pixel rows per lane group: measured faster
+            // than the LDS-conflict-free order of sixteen pixels per quarter-wave)
+            for (int v = t; v < TY * 64 * CQ; v += 256) {
+                const int q = v % CQ, pix = v / CQ;
+                const int y = y0 + pix / 64, x = x0 + (pix & 63);
+                if (y >= H || x >= W) continue;
+                *reinterpret_cast<uint4 *>(Y.p + ((size_t)(n * H + y) * W + x) * Y.Cs + Y.Co + n0 + 8 * q) =
+                    *reinterpret_cast<const uint4 *>(lds + pix * SP + 8 * q);
             }
-            uint4 o;
-            bf16_t *oe = reinterpret_cast<bf16_t *>(&o);
+            if constexpr (POOL) {
+                // 2 x 2 averages of the tile (TY and the tile origin are even),
+                // summed in the order (y, x), (y, x+1), (y+1, x), (y+1, x+1) like
+                // pool_kernel
+                const int Ho = H >> 1, Wo = W >> 1;
+                for (int v = t; v < (TY / 2) * 32 * CQ; v += 256) {
+                    const int q = v % CQ, pp = v / CQ, py = pp / 32, px = pp % 32;
+                    const int oy = (y0 >> 1) + py, ox = (x0 >> 1) + px;
+                    if (oy >= Ho || ox >= Wo) continue;
+                    float s[8] = {};
 #pragma unroll
-            for (int k = 0; k < 8; ++k) oe[k] = f2bf_rn(0.25f * s[k]);
-            *reinterpret_cast<uint4 *>(P.p + ((size_t)(n * Ho + oy) * Wo + ox) * P.Cs + P.Co + n0 + 8 * q) = o;
+                    for (int d = 0; d < 4; ++d) {
+                        const int pix = (2 * py + (d >> 1)) * 64 + 2 * px + (d & 1);
+                        const uint4 u = *reinterpret_cast<const uint4 *>(lds + pix * SP + 8 * q);
+                        const bf16_t *e = reinterpret_cast<const bf16_t *>(&u);
+#pragma unroll
+                        for (int k = 0; k < 8; ++k) s[k] += bf2f(e[k]);
+                    }
+                    uint4 o;
+                    bf16_t *oe = reinterpret_cast<bf16_t *>(&o);
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) oe[k] = f2bf_rn(0.25f * s[k]);
+                    *reinterpret_cast<uint4 *>(P.p + ((size_t)(n * Ho + oy) * Wo + ox) * P.Cs + P.Co + n0 + 8 * q) = o;
+                }
+            }
         }
+        if (!kConvPersistent || !more) break;
+        tile = next;
     }
 }
 

@@ -684,8 +684,24 @@ void launch_c3p(ac_sur *s, int l, View X, View Xlo, int B, int H, int W, View Y,
     const void *kern =
         reinterpret_cast<const void *>(&conv3_patch_kernel<CIN, CN, RW, LOWC, POOL, HEAD, FIRST>);
     set_lds_limit(kern, lds);
+    // persistent launch: at most one round of resident workgroups (a multiple
+    // of 8, one band of tiles per XCD), each walking its band of tiles
+    static int resident = 0;
+    if (resident == 0) {
+        int dev = 0, cus = 0, per_cu = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, lds) != hipSuccess ||
+            cus * per_cu <= 0) {
+            (void)hipGetLastError();
+            cus = 256;
+            per_cu = 2;
+        }
+        resident = 8 * ((cus * per_cu + 7) / 8);
+    }
     const int ntiles = B * ((H + 4 * RW - 1) / (4 * RW)) * ((W + 63) / 64);
-    dim3 grid(xcd_grid(ntiles), L.cout / CN);
+    dim3 grid(kConvPersistent ? std::min<unsigned>(xcd_grid(ntiles), (unsigned)resident) : xcd_grid(ntiles),
+              L.cout / CN);
     const ConvAux aux{phi, out, s->w32 + s->woff[L_HEAD], s->w32 + s->boff[L_HEAD], s->w1f,
                       bias_of(s, L_E1A), e1a_out};
     hipLaunchKernelGGL((conv3_patch_kernel<CIN, CN, RW, LOWC, POOL, HEAD, FIRST>), grid, dim3(256), lds,
@@ -930,8 +946,11 @@ ac_status ac_sur_infer(ac_sur *s, const float *phi_in, float *phi_out, int32_t b
     const int B = batch, H = s->H, W = s->W, H2 = H / 2, W2 = W / 2, H4 = H / 4, W4 = W / 4;
     const int n1 = B * H * W;
     const View none{nullptr, 0, 0};
-    // first two layers in one kernel: the first layer's output is never stored
-    launch_c3p<32, 32, 1, 0, true, false, true>(s, L_E1B, none, none, B, H, W, V(s->cat1, 64, 32),
+    // first two layers in one kernel: the first layer's output is never stored.
+    // The skip output goes to a dense 32-channel tensor (the e1a buffer, unused
+    // here), not into the concatenation: the last layer then reads whole
+    // 64-byte pixels instead of half of every 128-byte one
+    launch_c3p<32, 32, 1, 0, true, false, true>(s, L_E1B, none, none, B, H, W, V(s->e1a, 32),
                                                 V(s->p1, 32), phi_in);
     launch_c3p<32, 64, 1, 0, false, false>(s, L_E2A, V(s->p1, 32), none, B, H2, W2, V(s->e2a, 64), none);
     launch_c3p<64, 64, 1, 0, true, false>(s, L_E2B, V(s->e2a, 64), none, B, H2, W2, V(s->cat2, 128, 64),
@@ -944,7 +963,7 @@ ac_status ac_sur_infer(ac_sur *s, const float *phi_in, float *phi_out, int32_t b
                                              V(s->d2, 64), none);
     conv_fwd(s, L_U1, V(s->d2, 64), B, H2, W2, V(s->u1lo, 32), false, false);
     // last 3x3 layer with the head and the residual in its epilogue
-    launch_c3p<64, 32, 2, 32, false, true>(s, L_D1, V(s->cat1, 64, 32), V(s->u1lo, 32), B, H, W, none,
+    launch_c3p<64, 32, 2, 32, false, true>(s, L_D1, V(s->e1a, 32), V(s->u1lo, 32), B, H, W, none,
                                            none, phi_in, phi_out);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "surrogate inference");
