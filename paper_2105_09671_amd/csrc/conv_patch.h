@@ -61,6 +61,9 @@ struct ConvAux {
     const float *wh, *hb;  // HEAD: 1x1 head weights [32] and bias
     const float *w1, *b1;  // FIRST: first-layer weights [32][9] (BF16 values held as FP32), bias [32]
     bf16_t *e1a;           // FIRST: if not null, the first layer's output at the tile's pixels
+    const bf16_t *wu;      // UPC: the fused 1x1 layer's weights in fragment order [CN/32][1][UPC/16][64][8]
+    const float *bu;       // UPC: its bias [UPC]
+    View up;               // UPC: its output, [pixel][UPC] at this layer's resolution
 };
 
 // FIRST: the FP32 phi patch (TY + 4 rows x 68 columns) follows the e1a patch
@@ -192,16 +195,18 @@ __device__ inline void first_layer_patch(const ConvAux &aux, const float (&pv)[p
 // spills (not the 128-channel layer, not the training copy of the last
 // layer): about 1 % faster over the forward pass than the default allocation.
 constexpr bool kConv3pWaves3 = true;
-// kConvPrefetch: load the next chunk's patch (or the next tile's first) into
-// registers while the current chunk's taps run
-constexpr bool kConvPrefetch = false;
+// conv3p_prefetch: load the next chunk's patch (or, persistent, the next
+// tile's first) into registers while the current chunk's taps run.  The
+// 128-channel layers (four chunks, two waves per SIMD either way) gain; the
+// others would lose their third wave per SIMD
+constexpr bool conv3p_prefetch(int nch) { return nch >= 4; }
 // kConvPersistent: the launch holds one round of resident workgroups, each
 // walking its band of tiles; else one workgroup per tile
 constexpr bool kConvPersistent = false;
 template <int CIN, int CN, int RW, bool HEAD>
 constexpr int conv3p_waves() { return CIN <= 64 && RW == 1 ? 3 : 2; }
 
-template <int CIN, int CN, int RW, int LOWC, bool POOL, bool HEAD, bool FIRST = false>
+template <int CIN, int CN, int RW, int LOWC, bool POOL, bool HEAD, bool FIRST = false, int UPC = 0>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(conv3p_waves<CIN, CN, RW, HEAD>())))
 conv3_patch_kernel(View X, View Xlo, int B, int H, int W, const bf16_t *Wf,
                    const float *__restrict__ bias, int Cout, View Y, View P, ConvAux aux)
@@ -210,8 +215,9 @@ conv3_patch_kernel(View X, View Xlo, int B, int H, int W, const bf16_t *Wf,
     static_assert(!FIRST || (CIN == 32 && LOWC == 0), "the first layer has 32 outputs");
     static_assert(CN == 32 || CN == 64, "channel slice of 32 or 64");
     static_assert(!HEAD || CN == 32, "the head needs all 32 channels of a pixel");
+    static_assert(UPC == 0 || ((UPC == 32 || UPC == 64) && !HEAD && !POOL), "fused 1x1 of 32 or 64 outputs");
     constexpr int TY = 4 * RW, NI = 4 * RW, NJ = CN / 16, NCH = CIN / PC, PR = TY + 2;
-    constexpr bool kTapBarrier = !FIRST;
+    constexpr bool kTapBarrier = !FIRST, kConvPrefetch = conv3p_prefetch(NCH);
     extern __shared__ __align__(16) bf16_t lds[];
     const int tiles_x = (W + 63) >> 6, tiles_y = (H + TY - 1) / TY;
     const int tpi = tiles_y * tiles_x;
@@ -383,11 +389,53 @@ conv3_patch_kernel(View X, View Xlo, int B, int H, int W, const bf16_t *Wf,
                 aux.out[g] = aux.phi[g] + s;
             }
         } else {
+            if constexpr (UPC > 0) {
+                // the decoder's 1x1 layer fused: out[pix][co] = bu[co] + sum_c
+                // a[pix][c] wu[co][c] over this layer's CN outputs (the whole
+                // layer: one channel slice), FP32 sums, no activation.  Wave w
+                // takes the pixels it produced; transposed products again, so a
+                // lane ends with 4 consecutive outputs of one pixel
+                constexpr int UJ = UPC / 16, UK = CN / 32;
+                floatx4 u[NI][UJ] = {};
+#pragma unroll
+                for (int ks = 0; ks < UK; ++ks) {
+                    bf16x8 wq[UJ];
+#pragma unroll
+                    for (int j = 0; j < UJ; ++j)
+                        wq[j] = *reinterpret_cast<const bf16x8 *>(aux.wu + ((ks * UJ + j) * 64 + lane) * 8);
+#pragma unroll
+                    for (int i = 0; i < NI; ++i) {
+                        const int pix = i * 64 + 16 * w + lr;
+                        const bf16x8 a = *reinterpret_cast<const bf16x8 *>(lds + pix * SP + 32 * ks + 8 * lq);
+#pragma unroll
+                        for (int j = 0; j < UJ; ++j)
+                            u[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wq[j], a, u[i][j], 0, 0, 0);
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < UJ; ++j) {
+                    const int c0 = 16 * j + 4 * lq;
+                    float bv[4];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) bv[r] = aux.bu[c0 + r];
+#pragma unroll
+                    for (int i = 0; i < NI; ++i) {
+                        const int y = y0 + i, x = x0 + 16 * w + lr;
+                        if (y >= H || x >= W) continue;
+                        bf16x4 o;
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) o[r] = (__bf16)(u[i][j][r] + bv[r]);
+                        *reinterpret_cast<bf16x4 *>(aux.up.p + ((size_t)(n * H + y) * W + x) * aux.up.Cs +
+                                                    aux.up.Co + c0) = o;
+                    }
+                }
+            }
             constexpr int CQ = CN / 8;               // 16-byte groups per pixel
             // consecutive lanes write consecutive 16-byte groups of a pixel
             // (whole 64- or 128-byte pixel rows per lane group: measured faster
-            // than the LDS-conflict-free order of sixteen pixels per quarter-wave)
-            for (int v = t; v < TY * 64 * CQ; v += 256) {
+            // than the LDS-conflict-free order of sixteen pixels per quarter-wave).
+            // With a fused 1x1 layer the 3x3 output itself is optional (Y.p null)
+            for (int v = t; (UPC == 0 || Y.p) && v < TY * 64 * CQ; v += 256) {
                 const int q = v % CQ, pix = v / CQ;
                 const int y = y0 + pix / 64, x = x0 + (pix & 63);
                 if (y >= H || x >= W) continue;
@@ -425,17 +473,18 @@ conv3_patch_kernel(View X, View Xlo, int B, int H, int W, const bf16_t *Wf,
     }
 }
 
-// FP32 canonical weights [Cout][3][3][Cin] -> bf16 fragment order
-// [Cin/32][9][Cout/16][64 lanes][8]: lane l of tile (chunk, tap, jt) holds
-// output channel 16 jt + l % 16, input channels 32 chunk + 8 (l / 16) .. + 7.
-__global__ void pack_frag_weights_kernel(const float *w, int Cout, int Cin, bf16_t *out)
+// FP32 canonical weights [Cout][k][k][Cin] (taps = k * k = 9 or 1) -> bf16
+// fragment order [Cin/32][taps][Cout/16][64 lanes][8]: lane l of tile (chunk,
+// tap, jt) holds output channel 16 jt + l % 16, input channels 32 chunk +
+// 8 (l / 16) .. + 7.
+__global__ void pack_frag_weights_kernel(const float *w, int Cout, int taps, int Cin, bf16_t *out)
 {
-    const int total = Cout * 9 * Cin;
+    const int total = Cout * taps * Cin;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
         const int e = i & 7, lane = (i >> 3) & 63, rest = i >> 9;
-        const int jt = rest % (Cout >> 4), r2 = rest / (Cout >> 4), tap = r2 % 9, chunk = r2 / 9;
+        const int jt = rest % (Cout >> 4), r2 = rest / (Cout >> 4), tap = r2 % taps, chunk = r2 / taps;
         const int co = 16 * jt + (lane & 15), ci = 32 * chunk + 8 * (lane >> 4) + e;
-        out[i] = f2bf(w[((size_t)co * 9 + tap) * Cin + ci]);
+        out[i] = f2bf(w[((size_t)co * taps + tap) * Cin + ci]);
     }
 }
 

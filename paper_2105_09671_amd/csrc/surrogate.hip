@@ -483,6 +483,25 @@ __global__ void up_bwd_kernel(View dHigh, int C, int B, int Hl, int Wl, View dLo
     }
 }
 
+// dHigh (2 Hl x 2 Wl) = nearest 2x upsampling of dLow; C a multiple of 8,
+// 16 bytes per thread
+__global__ void up_copy_kernel(View low, int C, int B, int Hl, int Wl, View high)
+{
+    const int q8 = C >> 3;
+    const long long total = (long long)B * 4 * Hl * Wl * q8;
+    for (long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x; id < total;
+         id += (long long)gridDim.x * blockDim.x) {
+        const int q = (int)(id % q8);
+        const long long pix = id / q8;
+        const int Wh = 2 * Wl, Hh = 2 * Hl;
+        const int n = (int)(pix / ((long long)Hh * Wh)), rem = (int)(pix % ((long long)Hh * Wh));
+        const int y = rem / Wh, x = rem % Wh;
+        const size_t lp = ((size_t)n * Hl + (y >> 1)) * Wl + (x >> 1);
+        *reinterpret_cast<uint4 *>(high.p + (size_t)pix * high.Cs + high.Co + 8 * q) =
+            *reinterpret_cast<const uint4 *>(low.p + lp * low.Cs + low.Co + 8 * q);
+    }
+}
+
 // out = phi + b + sum_c d1[c] w[c]   (the 1x1 head, C = 32)
 __global__ void head_fwd_kernel(View d1, const float *wh, const float *bh, const float *phi,
                                 float *out, int M)
@@ -627,7 +646,7 @@ struct ac_sur {
     int64_t woff[NL], boff[NL];     // canonical flat offsets (weights, bias)
     int64_t kwoff[NL];              // offsets into the bf16 kernel-layout weights
     float *w32 = nullptr, *m = nullptr, *v = nullptr, *g = nullptr, *g_first = nullptr;
-    bf16_t *wb = nullptr, *wt = nullptr, *wf = nullptr;   // wf: fragment order (3x3, Cin >= 32)
+    bf16_t *wb = nullptr, *wt = nullptr, *wf = nullptr;   // wf: fragment order (Cin >= 32, Cout >= 16)
     bf16_t *u2lo = nullptr, *u1lo = nullptr;             // decoder 1x1 outputs at low resolution (inference)
     float *w1f = nullptr;                                // first-layer weights rounded to BF16, [32][9]
     float *out = nullptr, *dU = nullptr, *loss = nullptr;
@@ -676,13 +695,15 @@ void launch_fwd(ac_sur *s, int l, View X, int lgcin, int B, int H, int W, View Y
 // resolution.
 // FIRST (layer E1B only): the first layer runs inside the patch load from
 // the FP32 input `phi`; e1a_out (may be null) receives its output.
-template <int CIN, int CN, int RW, int LOWC, bool POOL, bool HEAD, bool FIRST = false>
+// ul: the decoder 1x1 layer fused into the epilogue (UPC > 0), writing `up`
+template <int CIN, int CN, int RW, int LOWC, bool POOL, bool HEAD, bool FIRST = false, int UPC = 0>
 void launch_c3p(ac_sur *s, int l, View X, View Xlo, int B, int H, int W, View Y, View P,
-                const float *phi = nullptr, float *out = nullptr, bf16_t *e1a_out = nullptr) {
+                const float *phi = nullptr, float *out = nullptr, bf16_t *e1a_out = nullptr,
+                int ul = -1, View up = View{nullptr, 0, 0}) {
     const LayerDef &L = kLayers[l];
     constexpr int lds = conv3p_lds_bytes<RW, CN, FIRST>();
     const void *kern =
-        reinterpret_cast<const void *>(&conv3_patch_kernel<CIN, CN, RW, LOWC, POOL, HEAD, FIRST>);
+        reinterpret_cast<const void *>(&conv3_patch_kernel<CIN, CN, RW, LOWC, POOL, HEAD, FIRST, UPC>);
     set_lds_limit(kern, lds);
     // persistent launch: at most one round of resident workgroups (a multiple
     // of 8, one band of tiles per XCD), each walking its band of tiles
@@ -703,8 +724,9 @@ void launch_c3p(ac_sur *s, int l, View X, View Xlo, int B, int H, int W, View Y,
     dim3 grid(kConvPersistent ? std::min<unsigned>(xcd_grid(ntiles), (unsigned)resident) : xcd_grid(ntiles),
               L.cout / CN);
     const ConvAux aux{phi, out, s->w32 + s->woff[L_HEAD], s->w32 + s->boff[L_HEAD], s->w1f,
-                      bias_of(s, L_E1A), e1a_out};
-    hipLaunchKernelGGL((conv3_patch_kernel<CIN, CN, RW, LOWC, POOL, HEAD, FIRST>), grid, dim3(256), lds,
+                      bias_of(s, L_E1A), e1a_out, ul >= 0 ? s->wf + s->kwoff[ul] : nullptr,
+                      ul >= 0 ? bias_of(s, ul) : nullptr, up};
+    hipLaunchKernelGGL((conv3_patch_kernel<CIN, CN, RW, LOWC, POOL, HEAD, FIRST, UPC>), grid, dim3(256), lds,
                        s->st, X, Xlo, B, H, W, s->wf + s->kwoff[l], bias_of(s, l), L.cout, Y, P, aux);
 }
 
@@ -791,9 +813,9 @@ void refresh_weights(ac_sur *s) {
                            L.cout, taps, L.cin, cin_pad, s->wb + s->kwoff[l]);
         hipLaunchKernelGGL(transpose_w_kernel, grid1(n), dim3(256), 0, s->st, s->wb + s->kwoff[l],
                            L.cout, taps, cin_pad, s->wt + s->kwoff[l]);
-        if (L.k == 3 && L.cin >= 32)
+        if (L.cin >= 32 && L.cout >= 16)   // 3x3 layers but the first; the decoder's 1x1 layers
             hipLaunchKernelGGL(pack_frag_weights_kernel, grid1(n), dim3(256), 0, s->st,
-                               s->w32 + s->woff[l], L.cout, L.cin, s->wf + s->kwoff[l]);
+                               s->w32 + s->woff[l], L.cout, taps, L.cin, s->wf + s->kwoff[l]);
     }
 }
 
@@ -920,8 +942,12 @@ ac_status ac_sur_forward(ac_sur *s, const float *phi_in, float *phi_out, int32_t
                                           V(s->p2, 64));
     launch_c3p<64, 64, 1, 0, false, false>(s, L_BT, V(s->p2, 64), none, B, H4, W4, V(s->bt, 128), none);
     conv_fwd(s, L_U2, V(s->bt, 128), B, H4, W4, V(s->cat2, 128, 0), false, true);
-    launch_c3p<128, 64, 1, 0, false, false>(s, L_D2, V(s->cat2, 128), none, B, H2, W2, V(s->d2, 64), none);
-    conv_fwd(s, L_U1, V(s->d2, 64), B, H2, W2, V(s->cat1, 64, 0), false, true);
+    // D2 with U1 fused (U1 at low resolution, then upsampled into the concatenation)
+    launch_c3p<128, 64, 1, 0, false, false, false, 32>(s, L_D2, V(s->cat2, 128), none, B, H2, W2,
+                                                       V(s->d2, 64), none, nullptr, nullptr, nullptr,
+                                                       L_U1, V(s->u1lo, 32));
+    hipLaunchKernelGGL(up_copy_kernel, grid1((long long)n1 * 4), dim3(256), 0, s->st, V(s->u1lo, 32), 32, B,
+                       H2, W2, V(s->cat1, 64, 0));
     launch_c3p<64, 32, 2, 0, false, false>(s, L_D1, V(s->cat1, 64), none, B, H, W, V(s->d1, 32), none);
     float *o = phi_out ? phi_out : s->out;
     hipLaunchKernelGGL(head_fwd_kernel, grid1(n1), dim3(256), 0, s->st, V(s->d1, 32),
@@ -959,9 +985,10 @@ ac_status ac_sur_infer(ac_sur *s, const float *phi_in, float *phi_out, int32_t b
     // decoder 1x1 layers at low resolution; the next 3x3 layer reads them
     // through the nearest upsampling
     conv_fwd(s, L_U2, V(s->bt, 128), B, H4, W4, V(s->u2lo, 64), false, false);
-    launch_c3p<128, 64, 1, 64, false, false>(s, L_D2, V(s->cat2, 128, 64), V(s->u2lo, 64), B, H2, W2,
-                                             V(s->d2, 64), none);
-    conv_fwd(s, L_U1, V(s->d2, 64), B, H2, W2, V(s->u1lo, 32), false, false);
+    // D2 with U1 fused into its epilogue: only U1's output is stored
+    launch_c3p<128, 64, 1, 64, false, false, false, 32>(s, L_D2, V(s->cat2, 128, 64), V(s->u2lo, 64), B,
+                                                        H2, W2, none, none, nullptr, nullptr, nullptr,
+                                                        L_U1, V(s->u1lo, 32));
     // last 3x3 layer with the head and the residual in its epilogue
     launch_c3p<64, 32, 2, 32, false, true>(s, L_D1, V(s->e1a, 32), V(s->u1lo, 32), B, H, W, none,
                                            none, phi_in, phi_out);
