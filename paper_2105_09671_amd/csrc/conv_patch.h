@@ -204,7 +204,7 @@ constexpr bool conv3p_prefetch(int nch) { return nch >= 4; }
 // walking its band of tiles; else one workgroup per tile
 constexpr bool kConvPersistent = false;
 template <int CIN, int CN, int RW, bool HEAD>
-constexpr int conv3p_waves() { return CIN <= 64 && RW == 1 ? 3 : 2; }
+constexpr int conv3p_waves() { return CIN <= 64 && RW == 1 && CN <= 64 ? 3 : 2; }
 
 template <int CIN, int CN, int RW, int LOWC, bool POOL, bool HEAD, bool FIRST = false, int UPC = 0>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(conv3p_waves<CIN, CN, RW, HEAD>())))
@@ -213,11 +213,11 @@ conv3_patch_kernel(View X, View Xlo, int B, int H, int W, const bf16_t *Wf,
 {
     static_assert(CIN % PC == 0 && LOWC % PC == 0 && LOWC <= CIN, "32-channel chunks");
     static_assert(!FIRST || (CIN == 32 && LOWC == 0), "the first layer has 32 outputs");
-    static_assert(CN == 32 || CN == 64, "channel slice of 32 or 64");
+    static_assert(CN == 32 || CN == 64 || (CN == 128 && UPC > 0), "channel slice of 32 or 64 (128: with a fused 1x1)");
     static_assert(!HEAD || CN == 32, "the head needs all 32 channels of a pixel");
     static_assert(UPC == 0 || ((UPC == 32 || UPC == 64) && !HEAD && !POOL), "fused 1x1 of 32 or 64 outputs");
     constexpr int TY = 4 * RW, NI = 4 * RW, NJ = CN / 16, NCH = CIN / PC, PR = TY + 2;
-    constexpr bool kTapBarrier = !FIRST, kConvPrefetch = conv3p_prefetch(NCH);
+    constexpr bool kTapBarrier = !FIRST && NJ < 8, kConvPrefetch = conv3p_prefetch(NCH);
     extern __shared__ __align__(16) bf16_t lds[];
     const int tiles_x = (W + 63) >> 6, tiles_y = (H + TY - 1) / TY;
     const int tpi = tiles_y * tiles_x;
@@ -306,8 +306,11 @@ conv3_patch_kernel(View X, View Xlo, int B, int H, int W, const bf16_t *Wf,
         // two slots of B fragments: K step s (over all chunks) uses slot s & 1
         // and loads step s + 1 into the other; the chunk loop is unrolled (at
         // most 4 chunks), so every slot index is static and nothing is copied
-        bf16x8 bq[2][NJ];
-        loadB(0, bq[0]);
+        // (128-channel slices: one slot, each step loads its own fragments,
+        // for the registers)
+        constexpr int NSLOT = NJ >= 8 ? 1 : 2;
+        bf16x8 bq[NSLOT][NJ];
+        if (NSLOT == 2) loadB(0, bq[0]);
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch) {
             // ---- stage the patch of this 32-channel chunk (clamped = replicate
@@ -337,12 +340,13 @@ conv3_patch_kernel(View X, View Xlo, int B, int H, int W, const bf16_t *Wf,
 #pragma unroll
                 for (int dy = 0; dy < 3; ++dy) {
                     const int step = ch * 9 + 3 * dx + dy;
-                    if (step + 1 < NCH * 9) loadB(step + 1, bq[(step + 1) & 1]);
+                    if (NSLOT == 1) loadB(step, bq[0]);
+                    else if (step + 1 < NCH * 9) loadB(step + 1, bq[(step + 1) % NSLOT]);
 #pragma unroll
                     for (int i = 0; i < NI; ++i)
 #pragma unroll
                         for (int j = 0; j < NJ; ++j)
-                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bq[step & 1][j], a[i + dy],
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bq[step % NSLOT][j], a[i + dy],
                                                                                  acc[i][j], 0, 0, 0);
                     // the 128-channel layers: keep each tap's loads within the
                     // tap, or the scheduler's early loads spill

@@ -940,8 +940,12 @@ ac_status ac_sur_forward(ac_sur *s, const float *phi_in, float *phi_out, int32_t
     launch_c3p<32, 64, 1, 0, false, false>(s, L_E2A, V(s->p1, 32), none, B, H2, W2, V(s->e2a, 64), none);
     launch_c3p<64, 64, 1, 0, true, false>(s, L_E2B, V(s->e2a, 64), none, B, H2, W2, V(s->cat2, 128, 64),
                                           V(s->p2, 64));
-    launch_c3p<64, 64, 1, 0, false, false>(s, L_BT, V(s->p2, 64), none, B, H4, W4, V(s->bt, 128), none);
-    conv_fwd(s, L_U2, V(s->bt, 128), B, H4, W4, V(s->cat2, 128, 0), false, true);
+    // BT (all 128 channels per workgroup) with U2 fused, U2 upsampled into the concatenation
+    launch_c3p<64, 128, 1, 0, false, false, false, 64>(s, L_BT, V(s->p2, 64), none, B, H4, W4,
+                                                       V(s->bt, 128), none, nullptr, nullptr, nullptr,
+                                                       L_U2, V(s->u2lo, 64));
+    hipLaunchKernelGGL(up_copy_kernel, grid1((long long)n1), dim3(256), 0, s->st, V(s->u2lo, 64), 64, B,
+                       H4, W4, V(s->cat2, 128, 0));
     // D2 with U1 fused (U1 at low resolution, then upsampled into the concatenation)
     launch_c3p<128, 64, 1, 0, false, false, false, 32>(s, L_D2, V(s->cat2, 128), none, B, H2, W2,
                                                        V(s->d2, 64), none, nullptr, nullptr, nullptr,
@@ -981,10 +985,10 @@ ac_status ac_sur_infer(ac_sur *s, const float *phi_in, float *phi_out, int32_t b
     launch_c3p<32, 64, 1, 0, false, false>(s, L_E2A, V(s->p1, 32), none, B, H2, W2, V(s->e2a, 64), none);
     launch_c3p<64, 64, 1, 0, true, false>(s, L_E2B, V(s->e2a, 64), none, B, H2, W2, V(s->cat2, 128, 64),
                                           V(s->p2, 64));
-    launch_c3p<64, 64, 1, 0, false, false>(s, L_BT, V(s->p2, 64), none, B, H4, W4, V(s->bt, 128), none);
-    // decoder 1x1 layers at low resolution; the next 3x3 layer reads them
-    // through the nearest upsampling
-    conv_fwd(s, L_U2, V(s->bt, 128), B, H4, W4, V(s->u2lo, 64), false, false);
+    // BT with the decoder's 1x1 layer U2 fused (only U2's output is stored, at
+    // low resolution; the next 3x3 layer reads it through the nearest upsampling)
+    launch_c3p<64, 128, 1, 0, false, false, false, 64>(s, L_BT, V(s->p2, 64), none, B, H4, W4, none, none,
+                                                       nullptr, nullptr, nullptr, L_U2, V(s->u2lo, 64));
     // D2 with U1 fused into its epilogue: only U1's output is stored
     launch_c3p<128, 64, 1, 64, false, false, false, 32>(s, L_D2, V(s->cat2, 128, 64), V(s->u2lo, 64), B,
                                                         H2, W2, none, none, nullptr, nullptr, nullptr,
