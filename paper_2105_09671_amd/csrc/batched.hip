@@ -47,7 +47,9 @@ struct BatchInst {
     int nx, ny;
     double alpha, r;
     int nz, tiles_x;   // 3D batches: depth and xy tiles along x (LDS tiles)
-    int rtiles_x, pad; // 3D batches: xy tiles along x of the register tiles
+    int rtiles_x;      // 3D batches: xy tiles along x of the register tiles
+    int lx, ly;        // 3D batches: this instance's LDS tile
+    int pad;
 };
 
 // sync[0]: items finished (over all phases); sync[1 + x]: tickets taken from
@@ -293,14 +295,14 @@ __device__ __forceinline__ void batch3d_item(const BatchInst &I, int4 it, int ph
                 return;
             }
         }
-        stream3d_body<T, K, CPT>(src, dst, I.nx, I.ny, I.nz, (T)I.alpha, (T)I.r, LX, LY, LZ,
+        stream3d_body<T, K, CPT>(src, dst, I.nx, I.ny, I.nz, (T)I.alpha, (T)I.r, I.lx, I.ly, LZ,
                                  I.tiles_x, it.y, it.z, smem_raw);
     } else if (REG && it.w) {
         copy_tile3d_reg<T>(static_cast<const T *>(I.work), static_cast<T *>(I.phi), I.nx, I.ny, I.nz, K,
                            LZR, I.rtiles_x, it.y, it.z);
     } else {
         copy_tile3d<T>(static_cast<const T *>(I.work), static_cast<T *>(I.phi), I.nx, I.ny, I.nz,
-                       LX - 2 * K, LY - 2 * K, LZ, I.tiles_x, it.y, it.z);
+                       I.lx - 2 * K, I.ly - 2 * K, LZ, I.tiles_x, it.y, it.z);
     }
 }
 
@@ -369,6 +371,7 @@ long long g_spin_limit = 20000000;   // ~2 s of polling per barrier
 bool g_persistent = false;           // false: a graph of one launch per phase
 constexpr int64_t kMaxGraphBlocks = 2048;   // temporal blocks per captured graph
 constexpr int kRegBatchLZ = 32;             // z segment of a register-tile 3D batch item
+constexpr int kBatch3dCellsPerThread = 2;   // largest per-instance LDS tile: this many cells per thread
 
 struct Plan {
     // key
@@ -752,9 +755,35 @@ ac_status build_plan3d(Plan &p, const ac_instance3d *inst, int32_t n, int64_t ns
     ac_plan tp;
     ac_status s = make_plan3d(256, 256, 256, nsteps, elem, &tl, dev, &tp);
     if (s != AC_OK) return s;
-    const int LX = tp.tile_x, LY = tp.tile_y, LZ = tp.tile_z, K = tp.tb_depth, threads = tp.threads;
+    const int LZ = tp.tile_z, K = tp.tb_depth, threads = tp.threads;
     if (K > 4) return fail(AC_ERR_UNSUPPORTED, "batched 3D supports tb_depth 1..4, got %d", K);
-    const int OX = LX - 2 * K, OY = LY - 2 * K;
+    // LDS tiles: the caller's shape for every instance, or (no shape given)
+    // per instance the shape of at most kBatch3dCellsPerThread * threads cells
+    // that computes the fewest cells over the instance's xy extent -- a tile
+    // computes its K-cell halo too, and on grids of 24..128 cells a fixed
+    // 32 x 32 tile computes about 2.7 cells per useful one
+    const bool own_shape = tune.tile_x <= 0 && tune.tile_y <= 0;
+    auto span = [&](int n, int L) { return (int64_t)((n + L - 2 * K - 1) / (L - 2 * K)) * L; };
+    std::vector<int2> shape(n);
+    int max_cells = tp.tile_x * tp.tile_y;
+    for (int32_t i = 0; i < n; ++i) {
+        int2 best{tp.tile_x, tp.tile_y};
+        if (own_shape) {
+            int64_t bc = span(inst[i].nx, best.x) * span(inst[i].ny, best.y);
+            for (int lx = 64; lx >= std::max(16, 2 * K + 1); --lx)
+                for (int ly = 64; ly >= 2 * K + 1; --ly) {
+                    if (lx * ly > kBatch3dCellsPerThread * threads) continue;
+                    const int64_t c = span(inst[i].nx, lx) * span(inst[i].ny, ly);
+                    if (c < bc) {
+                        bc = c;
+                        best = int2{lx, ly};
+                    }
+                }
+        }
+        shape[i] = best;
+        max_cells = std::max(max_cells, best.x * best.y);
+    }
+    const int LX = tp.tile_x, LY = (max_cells + LX - 1) / LX;   // LDS and cells per thread: the largest
     Tile3D t3{LX, LY, LZ, K, threads};
     const int cpt = stream3d_cells_per_thread(t3);
     // register items need the 512-thread workgroup of 8 waves x 4 rows
@@ -764,12 +793,13 @@ ac_status build_plan3d(Plan &p, const ac_instance3d *inst, int32_t n, int64_t ns
     std::vector<int4> items;
     bool any_reg = false;
     for (int32_t i = 0; i < n; ++i) {
+        const int OX = shape[i].x - 2 * K, OY = shape[i].y - 2 * K;
         const int tx = (inst[i].nx + OX - 1) / OX, ty = (inst[i].ny + OY - 1) / OY;
         const int tz = (inst[i].nz + LZ - 1) / LZ;
         const bool reg = use_reg && inst[i].nx >= 64;
         const int rtx = reg2d_tiles_1d(inst[i].nx, 64, K), rty = reg2d_tiles_1d(inst[i].ny, 32, K);
         hi[i] = BatchInst{inst[i].phi, inst[i].work, inst[i].nx, inst[i].ny, alpha[i], r[i],
-                          inst[i].nz, tx, rtx, 0};
+                          inst[i].nz, tx, rtx, shape[i].x, shape[i].y, 0};
         if (reg) {
             any_reg = true;
             for (int z = 0; z < (inst[i].nz + LZR - 1) / LZR; ++z)
@@ -780,6 +810,19 @@ ac_status build_plan3d(Plan &p, const ac_instance3d *inst, int32_t n, int64_t ns
                 for (int y = 0; y < ty; ++y)
                     for (int x = 0; x < tx; ++x) items.push_back(int4{i, y * tx + x, z, 0});
         }
+    }
+    // the phase kernels hand XCD x the x-th eighth of the items, in order:
+    // within each eighth the full-length z segments go first and the short
+    // last segments of the grids fill the tail
+    {
+        const size_t per = (items.size() + 7) / 8;
+        auto planes = [&](const int4 &it) {
+            const int L = it.w ? LZR : LZ;
+            return std::min(L, inst[it.x].nz - it.z * L);
+        };
+        for (size_t b = 0; per > 0 && b < items.size(); b += per)
+            std::stable_sort(items.begin() + b, items.begin() + std::min(items.size(), b + per),
+                             [&](const int4 &u, const int4 &v) { return planes(u) > planes(v); });
     }
     // whole phases of K steps, then one phase of the remaining steps
     const int64_t q = nsteps / K, rem = nsteps % K;
