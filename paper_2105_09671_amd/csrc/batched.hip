@@ -49,7 +49,7 @@ struct BatchInst {
     int nz, tiles_x;   // 3D batches: depth and xy tiles along x (LDS tiles)
     int rtiles_x;      // 3D batches: xy tiles along x of the register tiles
     int lx, ly;        // 3D batches: this instance's LDS tile
-    int pad;
+    int lz;            // 3D batches: this instance's z segment (LDS tiles)
 };
 
 // sync[0]: items finished (over all phases); sync[1 + x]: tickets taken from
@@ -295,14 +295,14 @@ __device__ __forceinline__ void batch3d_item(const BatchInst &I, int4 it, int ph
                 return;
             }
         }
-        stream3d_body<T, K, CPT>(src, dst, I.nx, I.ny, I.nz, (T)I.alpha, (T)I.r, I.lx, I.ly, LZ,
+        stream3d_body<T, K, CPT>(src, dst, I.nx, I.ny, I.nz, (T)I.alpha, (T)I.r, I.lx, I.ly, I.lz,
                                  I.tiles_x, it.y, it.z, smem_raw);
     } else if (REG && it.w) {
         copy_tile3d_reg<T>(static_cast<const T *>(I.work), static_cast<T *>(I.phi), I.nx, I.ny, I.nz, K,
                            LZR, I.rtiles_x, it.y, it.z);
     } else {
         copy_tile3d<T>(static_cast<const T *>(I.work), static_cast<T *>(I.phi), I.nx, I.ny, I.nz,
-                       I.lx - 2 * K, I.ly - 2 * K, LZ, I.tiles_x, it.y, it.z);
+                       I.lx - 2 * K, I.ly - 2 * K, I.lz, I.tiles_x, it.y, it.z);
     }
 }
 
@@ -742,13 +742,14 @@ ac_status build_plan3d(Plan &p, const ac_instance3d *inst, int32_t n, int64_t ns
     ac_tune tl = tune;
     const bool mixed = tl.kernel == AC_KERNEL_3D_REG && dtype == AC_F32;
     tl.kernel = AC_KERNEL_3D_STREAM;
-    // FP32 default: depth 3 on 32 x 32 tiles, 16-plane segments, fastest
-    // measured on the 64-grid batch of sides 24..128 (692 GLUPS; the
-    // single-grid default, depth 4 with 32-plane segments: 652)
+    // FP32 default: depth 2, per-instance tiles (below), segments of about 24
+    // planes.  Measured on the 64-grid batch of sides 24..128: 915 GLUPS;
+    // depth 2 with segments of 12..32 planes 800..915, depth 3 730..830 (one
+    // fixed 32 x 32 tile at depth 3 with 16-plane segments: 692)
     if (dtype == AC_F32 && !tl.tb_depth && !tl.tile_x && !tl.tile_y && !tl.tile_z) {
-        tl.tb_depth = 3;
+        tl.tb_depth = 2;
         tl.tile_x = tl.tile_y = 32;
-        tl.tile_z = 16;
+        tl.tile_z = 24;
     }
     if (tune.kernel != 0 && tune.kernel != AC_KERNEL_3D_STREAM && tune.kernel != AC_KERNEL_3D_REG)
         return fail(AC_ERR_UNSUPPORTED, "kernel %d is not a 3D kernel", tune.kernel);
@@ -795,11 +796,15 @@ ac_status build_plan3d(Plan &p, const ac_instance3d *inst, int32_t n, int64_t ns
     for (int32_t i = 0; i < n; ++i) {
         const int OX = shape[i].x - 2 * K, OY = shape[i].y - 2 * K;
         const int tx = (inst[i].nx + OX - 1) / OX, ty = (inst[i].ny + OY - 1) / OY;
-        const int tz = (inst[i].nz + LZ - 1) / LZ;
+        // z segments: the instance's depth cut evenly into segments of about LZ
+        // planes (no short remainder segment)
+        const int segs = std::max(1, (inst[i].nz + LZ / 2) / LZ);
+        const int lz = (inst[i].nz + segs - 1) / segs;
+        const int tz = (inst[i].nz + lz - 1) / lz;
         const bool reg = use_reg && inst[i].nx >= 64;
         const int rtx = reg2d_tiles_1d(inst[i].nx, 64, K), rty = reg2d_tiles_1d(inst[i].ny, 32, K);
         hi[i] = BatchInst{inst[i].phi, inst[i].work, inst[i].nx, inst[i].ny, alpha[i], r[i],
-                          inst[i].nz, tx, rtx, shape[i].x, shape[i].y, 0};
+                          inst[i].nz, tx, rtx, shape[i].x, shape[i].y, lz};
         if (reg) {
             any_reg = true;
             for (int z = 0; z < (inst[i].nz + LZR - 1) / LZR; ++z)
@@ -817,7 +822,7 @@ ac_status build_plan3d(Plan &p, const ac_instance3d *inst, int32_t n, int64_t ns
     {
         const size_t per = (items.size() + 7) / 8;
         auto planes = [&](const int4 &it) {
-            const int L = it.w ? LZR : LZ;
+            const int L = it.w ? LZR : hi[it.x].lz;
             return std::min(L, inst[it.x].nz - it.z * L);
         };
         for (size_t b = 0; per > 0 && b < items.size(); b += per)
