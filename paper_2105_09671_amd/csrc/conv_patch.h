@@ -195,11 +195,20 @@ __device__ inline void first_layer_patch(const ConvAux &aux, const float (&pv)[p
 // spills (not the 128-channel layer, not the training copy of the last
 // layer): about 1 % faster over the forward pass than the default allocation.
 constexpr bool kConv3pWaves3 = true;
+constexpr int kConvBSlots3 = 3;
 // conv3p_prefetch: load the next chunk's patch (or, persistent, the next
 // tile's first) into registers while the current chunk's taps run.  The
 // 128-channel layers (four chunks, two waves per SIMD either way) gain; the
 // others would lose their third wave per SIMD
 constexpr bool conv3p_prefetch(int nch) { return nch >= 4; }
+// Slots of B fragments: step s loads step s + NSLOT - 1, so a fragment is
+// requested NSLOT - 1 steps (each NI x NJ MFMAs) before its use.  One slot
+// (loaded at its step) where the accumulators take 128 VGPRs, three where
+// the registers allow it, else two
+template <int CIN, int CN, int RW, bool FIRST>
+constexpr int conv3p_bslots() {
+    return (4 * RW) * (CN / 16) >= 32 ? 1 : CIN == 32 ? kConvBSlots3 : 2;
+}
 // kConvPersistent: the launch holds one round of resident workgroups, each
 // walking its band of tiles; else one workgroup per tile
 constexpr bool kConvPersistent = false;
@@ -217,7 +226,7 @@ conv3_patch_kernel(View X, View Xlo, int B, int H, int W, const bf16_t *Wf,
     static_assert(!HEAD || CN == 32, "the head needs all 32 channels of a pixel");
     static_assert(UPC == 0 || ((UPC == 32 || UPC == 64) && !HEAD && !POOL), "fused 1x1 of 32 or 64 outputs");
     constexpr int TY = 4 * RW, NI = 4 * RW, NJ = CN / 16, NCH = CIN / PC, PR = TY + 2;
-    constexpr bool kTapBarrier = !FIRST && NJ < 8, kConvPrefetch = conv3p_prefetch(NCH);
+    constexpr bool kTapBarrier = !FIRST && NJ < 8, kConvPrefetch = conv3p_prefetch(NCH) && RW == 1;
     extern __shared__ __align__(16) bf16_t lds[];
     const int tiles_x = (W + 63) >> 6, tiles_y = (H + TY - 1) / TY;
     const int tpi = tiles_y * tiles_x;
@@ -303,14 +312,14 @@ conv3_patch_kernel(View X, View Xlo, int B, int H, int W, const bf16_t *Wf,
         const int next = tile + stride;
         const bool more = next < band_end;
         floatx4 acc[NI][NJ] = {};
-        // two slots of B fragments: K step s (over all chunks) uses slot s & 1
-        // and loads step s + 1 into the other; the chunk loop is unrolled (at
-        // most 4 chunks), so every slot index is static and nothing is copied
-        // (128-channel slices: one slot, each step loads its own fragments,
-        // for the registers)
-        constexpr int NSLOT = NJ >= 8 ? 1 : 2;
+        // NSLOT slots of B fragments: K step s (over all chunks) uses slot s %
+        // NSLOT and loads step s + NSLOT - 1 into a free one; the chunk loop is
+        // unrolled (at most 4 chunks), so every slot index is static and
+        // nothing is copied
+        constexpr int NSLOT = conv3p_bslots<CIN, CN, RW, FIRST>();
         bf16x8 bq[NSLOT][NJ];
-        if (NSLOT == 2) loadB(0, bq[0]);
+#pragma unroll
+        for (int q = 0; q + 1 < NSLOT; ++q) loadB(q, bq[q]);
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch) {
             // ---- stage the patch of this 32-channel chunk (clamped = replicate
@@ -340,8 +349,7 @@ conv3_patch_kernel(View X, View Xlo, int B, int H, int W, const bf16_t *Wf,
 #pragma unroll
                 for (int dy = 0; dy < 3; ++dy) {
                     const int step = ch * 9 + 3 * dx + dy;
-                    if (NSLOT == 1) loadB(step, bq[0]);
-                    else if (step + 1 < NCH * 9) loadB(step + 1, bq[(step + 1) % NSLOT]);
+                    if (step + NSLOT - 1 < NCH * 9) loadB(step + NSLOT - 1, bq[(step + NSLOT - 1) % NSLOT]);
 #pragma unroll
                     for (int i = 0; i < NI; ++i)
 #pragma unroll

@@ -947,7 +947,7 @@ ac_status ac_sur_forward(ac_sur *s, const float *phi_in, float *phi_out, int32_t
     hipLaunchKernelGGL(up_copy_kernel, grid1((long long)n1), dim3(256), 0, s->st, V(s->u2lo, 64), 64, B,
                        H4, W4, V(s->cat2, 128, 0));
     // D2 with U1 fused (U1 at low resolution, then upsampled into the concatenation)
-    launch_c3p<128, 64, 1, 0, false, false, false, 32>(s, L_D2, V(s->cat2, 128), none, B, H2, W2,
+    launch_c3p<128, 64, 2, 0, false, false, false, 32>(s, L_D2, V(s->cat2, 128), none, B, H2, W2,
                                                        V(s->d2, 64), none, nullptr, nullptr, nullptr,
                                                        L_U1, V(s->u1lo, 32));
     hipLaunchKernelGGL(up_copy_kernel, grid1((long long)n1 * 4), dim3(256), 0, s->st, V(s->u1lo, 32), 32, B,
@@ -974,7 +974,6 @@ ac_status ac_sur_infer(ac_sur *s, const float *phi_in, float *phi_out, int32_t b
     if (!s || !phi_in || !phi_out) return fail(AC_ERR_INVALID_ARG, "null handle, input or output");
     if (batch < 1 || batch > s->Bmax) return fail(AC_ERR_INVALID_ARG, "batch %d outside 1..%d", batch, s->Bmax);
     const int B = batch, H = s->H, W = s->W, H2 = H / 2, W2 = W / 2, H4 = H / 4, W4 = W / 4;
-    const int n1 = B * H * W;
     const View none{nullptr, 0, 0};
     // first two layers in one kernel: the first layer's output is never stored.
     // The skip output goes to a dense 32-channel tensor (the e1a buffer, unused
@@ -990,7 +989,7 @@ ac_status ac_sur_infer(ac_sur *s, const float *phi_in, float *phi_out, int32_t b
     launch_c3p<64, 128, 1, 0, false, false, false, 64>(s, L_BT, V(s->p2, 64), none, B, H4, W4, none, none,
                                                        nullptr, nullptr, nullptr, L_U2, V(s->u2lo, 64));
     // D2 with U1 fused into its epilogue: only U1's output is stored
-    launch_c3p<128, 64, 1, 64, false, false, false, 32>(s, L_D2, V(s->cat2, 128, 64), V(s->u2lo, 64), B,
+    launch_c3p<128, 64, 2, 64, false, false, false, 32>(s, L_D2, V(s->cat2, 128, 64), V(s->u2lo, 64), B,
                                                         H2, W2, none, none, nullptr, nullptr, nullptr,
                                                         L_U1, V(s->u1lo, 32));
     // last 3x3 layer with the head and the residual in its epilogue
