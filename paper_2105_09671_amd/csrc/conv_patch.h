@@ -178,13 +178,10 @@ __device__ inline void first_layer_patch(const ConvAux &aux, const float (&pv)[p
     }
 }
 
-// Tiles: (image, tile row, tile column), row-major over B images of H x W.
-// The launch is persistent: the tiles are cut into eight contiguous bands,
-// one per XCD (workgroup b runs on XCD b % 8), and each workgroup walks its
-// band with a stride of gridDim.x / 8, so adjacent tiles (which share halo
-// rows) meet in one L2.  While a chunk's 9 taps run, the patch of the next
-// chunk -- or of the next tile's first chunk -- is already being loaded into
-// registers, so a workgroup's MFMAs do not wait for its loads.
+// Row-major tile grid over B images of H x W: (image, tile row, tile column);
+// consecutive workgroups take horizontally, then vertically adjacent tiles of
+// one image, and with the XCD-aware numbering (xcd_tile) each XCD takes a
+// contiguous band, so the halo rows two tiles share are read through one L2.
 //
 // FIRST: the layer's input is the first layer's output e1a = relu(conv3(phi;
 // 1 -> 32)), computed into the patch from an FP32 phi patch (rounded to BF16,
@@ -194,29 +191,27 @@ __device__ inline void first_layer_patch(const ConvAux &aux, const float (&pv)[p
 // Three waves per SIMD asked of the register allocator where it fits without
 // spills (not the 128-channel layer, not the training copy of the last
 // layer): about 1 % faster over the forward pass than the default allocation.
-constexpr bool kConv3pWaves3 = true;
-constexpr int kConvBSlots3 = 3;
-// conv3p_prefetch: load the next chunk's patch (or, persistent, the next
-// tile's first) into registers while the current chunk's taps run.  The
-// 128-channel layers (four chunks, two waves per SIMD either way) gain; the
-// others would lose their third wave per SIMD
-constexpr bool conv3p_prefetch(int nch) { return nch >= 4; }
+// (Measured and left out: a persistent launch walking several tiles per
+// workgroup, and loading the next chunk's patch into registers during the
+// current chunk's taps.  The weight fragments are global loads issued a step
+// ahead, and the vector-memory counter retires loads in order, so each
+// step's wait for its weights also waits for the patch loads issued before
+// them: neither hid the patch loads, and both cost registers.)
+//
+// Waves per SIMD asked of the register allocator: three for the 32- and
+// 64-channel layers of 4-row tiles (the 128-channel slice and the 8-row tiles
+// need more registers).
+template <int CIN, int CN, int RW>
+constexpr int conv3p_waves() { return CIN <= 64 && RW == 1 && CN <= 64 ? 3 : 2; }
 // Slots of B fragments: step s loads step s + NSLOT - 1, so a fragment is
 // requested NSLOT - 1 steps (each NI x NJ MFMAs) before its use.  One slot
-// (loaded at its step) where the accumulators take 128 VGPRs, three where
-// the registers allow it, else two
-template <int CIN, int CN, int RW, bool FIRST>
-constexpr int conv3p_bslots() {
-    return (4 * RW) * (CN / 16) >= 32 ? 1 : CIN == 32 ? kConvBSlots3 : 2;
-}
-// kConvPersistent: the launch holds one round of resident workgroups, each
-// walking its band of tiles; else one workgroup per tile
-constexpr bool kConvPersistent = false;
-template <int CIN, int CN, int RW, bool HEAD>
-constexpr int conv3p_waves() { return CIN <= 64 && RW == 1 && CN <= 64 ? 3 : 2; }
+// (loaded at its step) where the accumulators take 128 VGPRs, three for the
+// layers with 32 input channels (registers to spare), else two
+template <int CIN, int CN, int RW>
+constexpr int conv3p_bslots() { return (4 * RW) * (CN / 16) >= 32 ? 1 : CIN == 32 ? 3 : 2; }
 
 template <int CIN, int CN, int RW, int LOWC, bool POOL, bool HEAD, bool FIRST = false, int UPC = 0>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(conv3p_waves<CIN, CN, RW, HEAD>())))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(conv3p_waves<CIN, CN, RW>())))
 conv3_patch_kernel(View X, View Xlo, int B, int H, int W, const bf16_t *Wf,
                    const float *__restrict__ bias, int Cout, View Y, View P, ConvAux aux)
 {
@@ -226,17 +221,15 @@ conv3_patch_kernel(View X, View Xlo, int B, int H, int W, const bf16_t *Wf,
     static_assert(!HEAD || CN == 32, "the head needs all 32 channels of a pixel");
     static_assert(UPC == 0 || ((UPC == 32 || UPC == 64) && !HEAD && !POOL), "fused 1x1 of 32 or 64 outputs");
     constexpr int TY = 4 * RW, NI = 4 * RW, NJ = CN / 16, NCH = CIN / PC, PR = TY + 2;
-    constexpr bool kTapBarrier = !FIRST && NJ < 8, kConvPrefetch = conv3p_prefetch(NCH) && RW == 1;
+    constexpr bool kTapBarrier = !FIRST && NJ < 8;
     extern __shared__ __align__(16) bf16_t lds[];
     const int tiles_x = (W + 63) >> 6, tiles_y = (H + TY - 1) / TY;
     const int tpi = tiles_y * tiles_x;
     const int ntiles = B * tpi;
-    // this workgroup's tiles: band of XCD blockIdx.x % 8, stride gridDim.x / 8
-    const int per = (ntiles + 7) >> 3;
-    const int band_end = min(((int)blockIdx.x & 7) * per + per, ntiles);
-    const int stride = (int)gridDim.x >> 3;
-    int tile = ((int)blockIdx.x & 7) * per + ((int)blockIdx.x >> 3);
-    if (tile >= band_end) return;                    // no tile (whole group)
+    const int tile = xcd_tile(ntiles);
+    if (tile >= ntiles) return;                      // padding workgroup (whole group)
+    const int n = tile / tpi, rem = tile - n * tpi;
+    const int y0 = (rem / tiles_x) * TY, x0 = (rem % tiles_x) * 64;
     const int n0 = blockIdx.y * CN;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int lr = lane & 15, lq = lane >> 4;
@@ -272,9 +265,7 @@ conv3_patch_kernel(View X, View Xlo, int B, int H, int W, const bf16_t *Wf,
     const bool ex = ex_r < PR;
     u32x4 val[FIRST ? 1 : PR], vex = {};
     float pv[phi_rows<TY>()];
-    auto issue = [&](int tl, int ch) __attribute__((always_inline)) {
-        const int n = tl / tpi, rem = tl - n * tpi;
-        const int y0 = (rem / tiles_x) * TY, x0 = (rem % tiles_x) * 64;
+    auto issue = [&](int ch) __attribute__((always_inline)) {
         if constexpr (FIRST) {
             phi_issue<TY>(aux, pv, n, H, W, y0, x0);
         } else {
@@ -305,183 +296,166 @@ conv3_patch_kernel(View X, View Xlo, int B, int H, int W, const bf16_t *Wf,
         if (ex) *reinterpret_cast<u32x4 *>(lds + (ex_r * PW + ex_c) * PP + 8 * ex_q) = vex;
     };
 
-    if (kConvPrefetch) issue(tile, 0);
-    for (bool first = true;; first = false) {
-        const int n = tile / tpi, rem = tile - n * tpi;
-        const int y0 = (rem / tiles_x) * TY, x0 = (rem % tiles_x) * 64;
-        const int next = tile + stride;
-        const bool more = next < band_end;
-        floatx4 acc[NI][NJ] = {};
-        // NSLOT slots of B fragments: K step s (over all chunks) uses slot s %
-        // NSLOT and loads step s + NSLOT - 1 into a free one; the chunk loop is
-        // unrolled (at most 4 chunks), so every slot index is static and
-        // nothing is copied
-        constexpr int NSLOT = conv3p_bslots<CIN, CN, RW, FIRST>();
-        bf16x8 bq[NSLOT][NJ];
+    floatx4 acc[NI][NJ] = {};
+    // NSLOT slots of B fragments: K step s (over all chunks) uses slot s %
+    // NSLOT and loads step s + NSLOT - 1 into a free one; the chunk loop is
+    // unrolled (at most 4 chunks), so every slot index is static and
+    // nothing is copied
+    constexpr int NSLOT = conv3p_bslots<CIN, CN, RW>();
+    bf16x8 bq[NSLOT][NJ];
 #pragma unroll
-        for (int q = 0; q + 1 < NSLOT; ++q) loadB(q, bq[q]);
+    for (int q = 0; q + 1 < NSLOT; ++q) loadB(q, bq[q]);
 #pragma unroll
-        for (int ch = 0; ch < NCH; ++ch) {
-            // ---- stage the patch of this 32-channel chunk (clamped = replicate
-            // pad) once every wave is done with the LDS, then start the next load
-            if (!first || ch > 0) __syncthreads();
-            if (!kConvPrefetch) issue(tile, ch);
-            if constexpr (FIRST) {
-                first_layer_patch<TY>(aux, pv, lds, n, H, W, y0, x0);
-                if (kConvPrefetch && more) issue(next, 0);
-            } else {
-                commit();
-                if (kConvPrefetch) {
-                    if (ch + 1 < NCH) issue(tile, ch + 1);
-                    else if (more) issue(next, 0);
-                }
-            }
-            __syncthreads();
-            // ---- 9 taps of this chunk.  Per column shift dx the wave reads the
-            // TY + 2 patch rows of its strip once; tile row i takes tap (dy, dx)
-            // from patch row i + dy, so each fragment read serves three taps
-#pragma unroll
-            for (int dx = 0; dx < 3; ++dx) {
-                bf16x8 a[TY + 2];
-#pragma unroll
-                for (int r = 0; r < TY + 2; ++r)
-                    a[r] = *reinterpret_cast<const bf16x8 *>(lds + fbase + (r * PW + dx) * PP);
-#pragma unroll
-                for (int dy = 0; dy < 3; ++dy) {
-                    const int step = ch * 9 + 3 * dx + dy;
-                    if (step + NSLOT - 1 < NCH * 9) loadB(step + NSLOT - 1, bq[(step + NSLOT - 1) % NSLOT]);
-#pragma unroll
-                    for (int i = 0; i < NI; ++i)
-#pragma unroll
-                        for (int j = 0; j < NJ; ++j)
-                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bq[step % NSLOT][j], a[i + dy],
-                                                                                 acc[i][j], 0, 0, 0);
-                    // the 128-channel layers: keep each tap's loads within the
-                    // tap, or the scheduler's early loads spill
-                    if constexpr (kTapBarrier) __builtin_amdgcn_sched_barrier(0);
-                }
-            }
-        }
-
-        // ---- epilogue: bias + relu -> bf16, staged in LDS as [pixel][CN].  The
-        // products are computed transposed (weights as the MFMA's A operand), so
-        // a lane holds 4 consecutive channels 16 j + 4 (lane / 16) + r of one
-        // pixel: one 8-byte LDS write per fragment
-        __syncthreads();                             // the patch is dead
-        constexpr int SP = CN + 8;
-#pragma unroll
-        for (int j = 0; j < NJ; ++j) {
-            const int c0 = 16 * j + 4 * lq;
-            float bv[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) bv[r] = bias[n0 + c0 + r];
-#pragma unroll
-            for (int i = 0; i < NI; ++i) {
-                const int pix = i * 64 + 16 * w + lr;
-                bf16x4 o;
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const float v = acc[i][j][r] + bv[r];
-                    o[r] = (__bf16)(v > 0.f ? v : 0.f);
-                }
-                *reinterpret_cast<bf16x4 *>(lds + pix * SP + c0) = o;
-            }
-        }
+    for (int ch = 0; ch < NCH; ++ch) {
+        // ---- stage the patch of this 32-channel chunk (clamped = replicate
+        // pad) once every wave is done with the LDS
+        if (ch > 0) __syncthreads();
+        issue(ch);
+        if constexpr (FIRST) first_layer_patch<TY>(aux, pv, lds, n, H, W, y0, x0);
+        else commit();
         __syncthreads();
-        if constexpr (HEAD) {
-            // one thread per pixel: out = phi + (hb + sum_c a_c wh_c), c in order
-            for (int pix = t; pix < TY * 64; pix += 256) {
-                const int y = y0 + (pix >> 6), x = x0 + (pix & 63);
-                if (y >= H || x >= W) continue;
-                const bf16_t *a = lds + pix * SP;
-                float s = aux.hb[0];
+        // ---- 9 taps of this chunk.  Per column shift dx the wave reads the
+        // TY + 2 patch rows of its strip once; tile row i takes tap (dy, dx)
+        // from patch row i + dy, so each fragment read serves three taps
 #pragma unroll
-                for (int c = 0; c < 32; ++c) s += bf2f(a[c]) * aux.wh[c];
-                const size_t g = (size_t)(n * H + y) * W + x;
-                aux.out[g] = aux.phi[g] + s;
+        for (int dx = 0; dx < 3; ++dx) {
+            bf16x8 a[TY + 2];
+#pragma unroll
+            for (int r = 0; r < TY + 2; ++r)
+                a[r] = *reinterpret_cast<const bf16x8 *>(lds + fbase + (r * PW + dx) * PP);
+#pragma unroll
+            for (int dy = 0; dy < 3; ++dy) {
+                const int step = ch * 9 + 3 * dx + dy;
+                if (step + NSLOT - 1 < NCH * 9) loadB(step + NSLOT - 1, bq[(step + NSLOT - 1) % NSLOT]);
+#pragma unroll
+                for (int i = 0; i < NI; ++i)
+#pragma unroll
+                    for (int j = 0; j < NJ; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bq[step % NSLOT][j], a[i + dy],
+                                                                             acc[i][j], 0, 0, 0);
+                // the 128-channel layers: keep each tap's loads within the
+                // tap, or the scheduler's early loads spill
+                if constexpr (kTapBarrier) __builtin_amdgcn_sched_barrier(0);
             }
-        } else {
-            if constexpr (UPC > 0) {
-                // the decoder's 1x1 layer fused: out[pix][co] = bu[co] + sum_c
-                // a[pix][c] wu[co][c] over this layer's CN outputs (the whole
-                // layer: one channel slice), FP32 sums, no activation.  Wave w
-                // takes the pixels it produced; transposed products again, so a
-                // lane ends with 4 consecutive outputs of one pixel
-                constexpr int UJ = UPC / 16, UK = CN / 32;
-                floatx4 u[NI][UJ] = {};
+        }
+    }
+
+    // ---- epilogue: bias + relu -> bf16, staged in LDS as [pixel][CN].  The
+    // products are computed transposed (weights as the MFMA's A operand), so
+    // a lane holds 4 consecutive channels 16 j + 4 (lane / 16) + r of one
+    // pixel: one 8-byte LDS write per fragment
+    __syncthreads();                             // the patch is dead
+    constexpr int SP = CN + 8;
 #pragma unroll
-                for (int ks = 0; ks < UK; ++ks) {
-                    bf16x8 wq[UJ];
+    for (int j = 0; j < NJ; ++j) {
+        const int c0 = 16 * j + 4 * lq;
+        float bv[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) bv[r] = bias[n0 + c0 + r];
+#pragma unroll
+        for (int i = 0; i < NI; ++i) {
+            const int pix = i * 64 + 16 * w + lr;
+            bf16x4 o;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float v = acc[i][j][r] + bv[r];
+                o[r] = (__bf16)(v > 0.f ? v : 0.f);
+            }
+            *reinterpret_cast<bf16x4 *>(lds + pix * SP + c0) = o;
+        }
+    }
+    __syncthreads();
+    if constexpr (HEAD) {
+        // one thread per pixel: out = phi + (hb + sum_c a_c wh_c), c in order
+        for (int pix = t; pix < TY * 64; pix += 256) {
+            const int y = y0 + (pix >> 6), x = x0 + (pix & 63);
+            if (y >= H || x >= W) continue;
+            const bf16_t *a = lds + pix * SP;
+            float s = aux.hb[0];
+#pragma unroll
+            for (int c = 0; c < 32; ++c) s += bf2f(a[c]) * aux.wh[c];
+            const size_t g = (size_t)(n * H + y) * W + x;
+            aux.out[g] = aux.phi[g] + s;
+        }
+    } else {
+        if constexpr (UPC > 0) {
+            // the decoder's 1x1 layer fused: out[pix][co] = bu[co] + sum_c
+            // a[pix][c] wu[co][c] over this layer's CN outputs (the whole
+            // layer: one channel slice), FP32 sums, no activation.  Wave w
+            // takes the pixels it produced; transposed products again, so a
+            // lane ends with 4 consecutive outputs of one pixel
+            constexpr int UJ = UPC / 16, UK = CN / 32;
+            floatx4 u[NI][UJ] = {};
+#pragma unroll
+            for (int ks = 0; ks < UK; ++ks) {
+                bf16x8 wq[UJ];
+#pragma unroll
+                for (int j = 0; j < UJ; ++j)
+                    wq[j] = *reinterpret_cast<const bf16x8 *>(aux.wu + ((ks * UJ + j) * 64 + lane) * 8);
+#pragma unroll
+                for (int i = 0; i < NI; ++i) {
+                    const int pix = i * 64 + 16 * w + lr;
+                    const bf16x8 a = *reinterpret_cast<const bf16x8 *>(lds + pix * SP + 32 * ks + 8 * lq);
 #pragma unroll
                     for (int j = 0; j < UJ; ++j)
-                        wq[j] = *reinterpret_cast<const bf16x8 *>(aux.wu + ((ks * UJ + j) * 64 + lane) * 8);
-#pragma unroll
-                    for (int i = 0; i < NI; ++i) {
-                        const int pix = i * 64 + 16 * w + lr;
-                        const bf16x8 a = *reinterpret_cast<const bf16x8 *>(lds + pix * SP + 32 * ks + 8 * lq);
-#pragma unroll
-                        for (int j = 0; j < UJ; ++j)
-                            u[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wq[j], a, u[i][j], 0, 0, 0);
-                    }
-                }
-#pragma unroll
-                for (int j = 0; j < UJ; ++j) {
-                    const int c0 = 16 * j + 4 * lq;
-                    float bv[4];
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) bv[r] = aux.bu[c0 + r];
-#pragma unroll
-                    for (int i = 0; i < NI; ++i) {
-                        const int y = y0 + i, x = x0 + 16 * w + lr;
-                        if (y >= H || x >= W) continue;
-                        bf16x4 o;
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) o[r] = (__bf16)(u[i][j][r] + bv[r]);
-                        *reinterpret_cast<bf16x4 *>(aux.up.p + ((size_t)(n * H + y) * W + x) * aux.up.Cs +
-                                                    aux.up.Co + c0) = o;
-                    }
+                        u[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wq[j], a, u[i][j], 0, 0, 0);
                 }
             }
-            constexpr int CQ = CN / 8;               // 16-byte groups per pixel
-            // consecutive lanes write consecutive 16-byte groups of a pixel
-            // (whole 64- or 128-byte pixel rows per lane group: measured faster
-            // than the LDS-conflict-free order of sixteen pixels per quarter-wave).
-            // With a fused 1x1 layer the 3x3 output itself is optional (Y.p null)
-            for (int v = t; (UPC == 0 || Y.p) && v < TY * 64 * CQ; v += 256) {
-                const int q = v % CQ, pix = v / CQ;
-                const int y = y0 + pix / 64, x = x0 + (pix & 63);
-                if (y >= H || x >= W) continue;
-                *reinterpret_cast<uint4 *>(Y.p + ((size_t)(n * H + y) * W + x) * Y.Cs + Y.Co + n0 + 8 * q) =
-                    *reinterpret_cast<const uint4 *>(lds + pix * SP + 8 * q);
-            }
-            if constexpr (POOL) {
-                // 2 x 2 averages of the tile (TY and the tile origin are even),
-                // summed in the order (y, x), (y, x+1), (y+1, x), (y+1, x+1) like
-                // pool_kernel
-                const int Ho = H >> 1, Wo = W >> 1;
-                for (int v = t; v < (TY / 2) * 32 * CQ; v += 256) {
-                    const int q = v % CQ, pp = v / CQ, py = pp / 32, px = pp % 32;
-                    const int oy = (y0 >> 1) + py, ox = (x0 >> 1) + px;
-                    if (oy >= Ho || ox >= Wo) continue;
-                    float s[8] = {};
 #pragma unroll
-                    for (int d = 0; d < 4; ++d) {
-                        const int pix = (2 * py + (d >> 1)) * 64 + 2 * px + (d & 1);
-                        const uint4 u = *reinterpret_cast<const uint4 *>(lds + pix * SP + 8 * q);
-                        const bf16_t *e = reinterpret_cast<const bf16_t *>(&u);
+            for (int j = 0; j < UJ; ++j) {
+                const int c0 = 16 * j + 4 * lq;
+                float bv[4];
 #pragma unroll
-                        for (int k = 0; k < 8; ++k) s[k] += bf2f(e[k]);
-                    }
-                    uint4 o;
-                    bf16_t *oe = reinterpret_cast<bf16_t *>(&o);
+                for (int r = 0; r < 4; ++r) bv[r] = aux.bu[c0 + r];
 #pragma unroll
-                    for (int k = 0; k < 8; ++k) oe[k] = f2bf_rn(0.25f * s[k]);
-                    *reinterpret_cast<uint4 *>(P.p + ((size_t)(n * Ho + oy) * Wo + ox) * P.Cs + P.Co + n0 + 8 * q) = o;
+                for (int i = 0; i < NI; ++i) {
+                    const int y = y0 + i, x = x0 + 16 * w + lr;
+                    if (y >= H || x >= W) continue;
+                    bf16x4 o;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) o[r] = (__bf16)(u[i][j][r] + bv[r]);
+                    *reinterpret_cast<bf16x4 *>(aux.up.p + ((size_t)(n * H + y) * W + x) * aux.up.Cs +
+                                                aux.up.Co + c0) = o;
                 }
             }
         }
-        if (!kConvPersistent || !more) break;
-        tile = next;
+        constexpr int CQ = CN / 8;               // 16-byte groups per pixel
+        // consecutive lanes write consecutive 16-byte groups of a pixel
+        // (whole 64- or 128-byte pixel rows per lane group: measured faster
+        // than the LDS-conflict-free order of sixteen pixels per quarter-wave).
+        // With a fused 1x1 layer the 3x3 output itself is optional (Y.p null)
+        for (int v = t; (UPC == 0 || Y.p) && v < TY * 64 * CQ; v += 256) {
+            const int q = v % CQ, pix = v / CQ;
+            const int y = y0 + pix / 64, x = x0 + (pix & 63);
+            if (y >= H || x >= W) continue;
+            *reinterpret_cast<uint4 *>(Y.p + ((size_t)(n * H + y) * W + x) * Y.Cs + Y.Co + n0 + 8 * q) =
+                *reinterpret_cast<const uint4 *>(lds + pix * SP + 8 * q);
+        }
+        if constexpr (POOL) {
+            // 2 x 2 averages of the tile (TY and the tile origin are even),
+            // summed in the order (y, x), (y, x+1), (y+1, x), (y+1, x+1) like
+            // pool_kernel
+            const int Ho = H >> 1, Wo = W >> 1;
+            for (int v = t; v < (TY / 2) * 32 * CQ; v += 256) {
+                const int q = v % CQ, pp = v / CQ, py = pp / 32, px = pp % 32;
+                const int oy = (y0 >> 1) + py, ox = (x0 >> 1) + px;
+                if (oy >= Ho || ox >= Wo) continue;
+                float s[8] = {};
+#pragma unroll
+                for (int d = 0; d < 4; ++d) {
+                    const int pix = (2 * py + (d >> 1)) * 64 + 2 * px + (d & 1);
+                    const uint4 u = *reinterpret_cast<const uint4 *>(lds + pix * SP + 8 * q);
+                    const bf16_t *e = reinterpret_cast<const bf16_t *>(&u);
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) s[k] += bf2f(e[k]);
+                }
+                uint4 o;
+                bf16_t *oe = reinterpret_cast<bf16_t *>(&o);
+#pragma unroll
+                for (int k = 0; k < 8; ++k) oe[k] = f2bf_rn(0.25f * s[k]);
+                *reinterpret_cast<uint4 *>(P.p + ((size_t)(n * Ho + oy) * Wo + ox) * P.Cs + P.Co + n0 + 8 * q) = o;
+            }
+        }
     }
 }
 

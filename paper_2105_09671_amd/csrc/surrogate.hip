@@ -705,24 +705,8 @@ void launch_c3p(ac_sur *s, int l, View X, View Xlo, int B, int H, int W, View Y,
     const void *kern =
         reinterpret_cast<const void *>(&conv3_patch_kernel<CIN, CN, RW, LOWC, POOL, HEAD, FIRST, UPC>);
     set_lds_limit(kern, lds);
-    // persistent launch: at most one round of resident workgroups (a multiple
-    // of 8, one band of tiles per XCD), each walking its band of tiles
-    static int resident = 0;
-    if (resident == 0) {
-        int dev = 0, cus = 0, per_cu = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, lds) != hipSuccess ||
-            cus * per_cu <= 0) {
-            (void)hipGetLastError();
-            cus = 256;
-            per_cu = 2;
-        }
-        resident = 8 * ((cus * per_cu + 7) / 8);
-    }
     const int ntiles = B * ((H + 4 * RW - 1) / (4 * RW)) * ((W + 63) / 64);
-    dim3 grid(kConvPersistent ? std::min<unsigned>(xcd_grid(ntiles), (unsigned)resident) : xcd_grid(ntiles),
-              L.cout / CN);
+    dim3 grid(xcd_grid(ntiles), L.cout / CN);
     const ConvAux aux{phi, out, s->w32 + s->woff[L_HEAD], s->w32 + s->boff[L_HEAD], s->w1f,
                       bias_of(s, L_E1A), e1a_out, ul >= 0 ? s->wf + s->kwoff[ul] : nullptr,
                       ul >= 0 ? bias_of(s, ul) : nullptr, up};
