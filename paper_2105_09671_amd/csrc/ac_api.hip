@@ -365,20 +365,21 @@ ac_status make_plan3d(int nx, int ny, int nz, int64_t nsteps, size_t elem, const
         const int64_t two_per_cu = 2LL * std::max(dev.cus, 1);
         if (reg && !f64 && xy * ((nz + 31) / 32) < 2 * two_per_cu) {
             // FP32 register tiles on a grid of less than two rounds of
-            // 32-plane segments: S = floor(2 CUs / xy) segments of floor(nz /
-            // S) planes, the remainder in one short extra segment, so no CU
-            // takes more than two long segments.  Measured on MI355X at 256^3,
-            // depth 4: 28 planes 1211 GLUPS against 1112 at 32, 947 at 26 (all
-            // ten segments long) and 905 at 64 (one workgroup per CU); depth 5
-            // (S = 8): 32 planes, its best.
+            // 32-plane segments: S = floor(2 CUs / xy) segments of about equal
+            // length, so that (with each XCD taking a contiguous eighth of the
+            // items) no CU takes more than two segments.  Measured on MI355X at
+            // 256^3, depth 4 (S = 9): 29 planes 1208 GLUPS against 1124 at 32
+            // (eight segments), 876 at 28 (ten: nine long ones crowd seven
+            // XCDs' ranges) and 913 at 43; depth 5 (S = 8): 32 planes, its best.
             const int64_t S = std::max<int64_t>(1, two_per_cu / std::max<int64_t>(xy, 1));
-            LZ = (int)std::max<int64_t>(16, std::min<int64_t>(128, nz / S));
+            LZ = (int)std::max<int64_t>(16, std::min<int64_t>(128, (nz + S - 1) / S));
         } else if (reg && !f64) {
             // longer segments re-stream fewer halo planes, but the last round
             // of resident workgroups may run part-empty: the length in {32, 64,
             // 128} with the least (rounds, rounded up) x (LZ + 1.5 K).
-            // Measured: 512^3 64 planes (1506 GLUPS; 128: 1468, 1.5 rounds),
-            // 1024^3 128 (+2 % over 64)
+            // Measured: 512^3 64 planes (1506 GLUPS against 1468 at 128, which
+            // leaves 1.5 rounds; 1607 with the XCD-aware numbering), 1024^3
+            // 128 (+2 % over 64; 1555 with the XCD-aware numbering)
             double best = 0;
             for (int lz = 32; lz <= 128; lz *= 2) {
                 const int64_t rounds = (xy * ((nz + lz - 1) / lz) + want - 1) / want;

@@ -95,14 +95,22 @@ hipError_t launch_stream3d(const T *src, T *dst, int nx, int ny, int nz, T alpha
 // Register-resident variant (reg3d.h): 64-wide tiles, kReg3dRows rows per wave.
 // SR: the rows beyond a wave are read at a selected LDS address rather than
 // under a branch (reg3d_stream).
+// The grid is one-dimensional over (z segment, xy tile), xy tiles fastest,
+// numbered XCD-aware: workgroup b runs on XCD b % 8 and takes item
+// (b % 8) * per + b / 8, so each XCD works through a contiguous range of
+// neighbouring tiles and the halo the neighbours share (K columns, rows and
+// planes around every tile) is read through one L2.
 template <typename T, int K, bool SR>
 __global__ void __launch_bounds__(512)
 reg3d_kernel(const T *__restrict__ src, T *__restrict__ dst, int nx, int ny, int nz, T alpha, T r,
-             int LZ, int tiles_x)
+             int LZ, int tiles_x, int tiles_xy, int items)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    reg3d_body<T, K, kReg3dRows, SR>(src, dst, nx, ny, nz, alpha, r, LZ, tiles_x, blockIdx.x,
-                                     blockIdx.y, reinterpret_cast<T *>(smem_raw));
+    const int per = (items + 7) >> 3;
+    const int item = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+    if ((int)(blockIdx.x >> 3) >= per || item >= items) return;   // padding workgroup (whole group)
+    reg3d_body<T, K, kReg3dRows, SR>(src, dst, nx, ny, nz, alpha, r, LZ, tiles_x, item % tiles_xy,
+                                     item / tiles_xy, reinterpret_cast<T *>(smem_raw));
 }
 
 template <typename T, int K, bool SR>
@@ -164,11 +172,16 @@ hipError_t launch_reg3d(const T *src, T *dst, int nx, int ny, int nz, T alpha, T
         return hipErrorInvalidValue;
     // xy tiles flush against the domain edges (reg2d_tile_span)
     const int tiles_x = reg2d_tiles_1d(nx, 64, t.K), tiles_y = reg2d_tiles_1d(ny, t.LY, t.K);
-    dim3 grid(tiles_x * tiles_y, (nz + t.LZ - 1) / t.LZ);
+    const int tiles_xy = tiles_x * tiles_y;
+    const int64_t items64 = (int64_t)tiles_xy * ((nz + t.LZ - 1) / t.LZ);
+    if (items64 > INT_MAX - 8) return hipErrorInvalidValue;
+    int items = (int)items64;
+    dim3 grid(8 * ((items + 7) / 8));
     const size_t lds = reg3d_lds_bytes(t.K, t.LY, sizeof(T));
     set_lds_limit(k, lds);
-    void *args[] = {(void *)&src, (void *)&dst, (void *)&nx,  (void *)&ny,   (void *)&nz,
-                    (void *)&alpha, (void *)&r, (void *)&t.LZ, (void *)&tiles_x};
+    void *args[] = {(void *)&src, (void *)&dst, (void *)&nx,   (void *)&ny,       (void *)&nz,
+                    (void *)&alpha, (void *)&r, (void *)&t.LZ, (void *)&tiles_x, (void *)&tiles_xy,
+                    (void *)&items};
     return hipLaunchKernel(k, grid, dim3(64 * (t.LY / kReg3dRows)), args, lds, stream);
 }
 

@@ -204,6 +204,13 @@ def evaluate(net: Surrogate, seeds, T_blocks: int = 20, sample_every: int = 1,
     pred = torch.empty_like(state)
     B = net.batch_max
     net.infer(state[:min(N, B)].contiguous(), pred[:min(N, B)])     # warm-up
+    # warm-up of the other calls the timed loop makes (first-use costs: module
+    # loading, the judge's workspace), on scratch copies
+    dev_ = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.int64)).cuda()
+    scratch = state[:min(N, B)].clone()
+    api.judge2d(pred[:len(scratch)].contiguous(), scratch, h)
+    scratch.index_copy_(0, dev_(np.arange(len(scratch))), pred.index_select(0, dev_(np.arange(len(scratch)))))
+    del scratch
     torch.cuda.synchronize()
     # book-keeping on the host: which grids are trusted, judged, stepped
     trusted = np.ones(N, dtype=bool)
