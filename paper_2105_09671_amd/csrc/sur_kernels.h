@@ -68,35 +68,6 @@ __device__ inline void mma_step_t(const bf16_t *As, const bf16_t *Bs, floatx4 ac
             acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
 }
 
-// Wave tile of TM x TN MFMA tiles (16 x 16 each): wave w of WM x WN owns rows
-// [16 TM (w % WM), +16 TM) and columns [16 TN (w / WM), +16 TN) of the
-// workgroup tile.  Per K step it reads TM + TN fragments for TM * TN MFMAs.
-template <int WM, int WN, int TM, int TN>
-__device__ inline void mma_step_g(const bf16_t *As, const bf16_t *Bs, floatx4 (&acc)[TM][TN]) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int wm = w % WM, wn = w / WM;
-    const int r = lane & 15, kc = (lane >> 4) * 8;
-    bf16x8 a[TM], b[TN];
-#pragma unroll
-    for (int i = 0; i < TM; ++i)
-        a[i] = *reinterpret_cast<const bf16x8 *>(As + (wm * 16 * TM + i * 16 + r) * LP + kc);
-#pragma unroll
-    for (int j = 0; j < TN; ++j)
-        b[j] = *reinterpret_cast<const bf16x8 *>(Bs + (wn * 16 * TN + j * 16 + r) * LP + kc);
-#pragma unroll
-    for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
-}
-
-template <int WM, int WN, int TM, int TN>
-__device__ inline void acc_coord_g(int i, int j, int r, int *row, int *col) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    *row = (w % WM) * 16 * TM + i * 16 + (lane >> 4) * 4 + r;
-    *col = (w / WM) * 16 * TN + j * 16 + (lane & 15);
-}
-
 // M tile of a GEMM launched with ceil(n/8)*8 workgroups along x.  The
 // dispatcher places workgroup g on XCD g mod 8; XCD x gets the x-th contiguous
 // eighth of the M tiles, so output rows that read the same input rows through

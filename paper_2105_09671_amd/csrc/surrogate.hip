@@ -11,9 +11,11 @@
 //   u1  = conv1(up d2)   d1 = relu conv3(cat(u1, e1))              H,     32 ch
 //   out = phi + conv1(d1)
 // A 1x1 conv commutes with nearest upsampling, so u2 and u1 are computed at
-// the low resolution and the epilogue writes each result to its 2x2 block
-// (4x fewer flops).  cat(u, e) is one buffer: u fills channels [0, C), the
-// encoder writes e straight into [C, 2C).
+// the low resolution (4x fewer flops), in the epilogue of the 3x3 layer that
+// produces their input.  cat(u, e) is one buffer in training: a copy kernel
+// writes each u value to its 2x2 block of channels [0, C), the encoder
+// writes e straight into [C, 2C); inference keeps u at the low resolution and
+// the next 3x3 layer reads it through the upsampling.
 //
 // Backward of a replicate-padded conv: with X_pad[p] = X[clamp(p - 1)] the
 // forward is a valid correlation over X_pad, so dX_pad is the full (zero
@@ -32,138 +34,6 @@
 
 namespace ac {
 namespace sur {
-
-// ------------------------------------------------------------ forward ----
-// Y = act(conv(X) + bias).  GEMM rows = output pixels, cols = output
-// channels, K = KS*KS*Cin ordered (tap, ci) like the weights [Cout][tap][Cin].
-// UP: X is at low resolution and each result goes to a 2x2 block of Y.
-// Tile (32 WM) x (32 WN); 32-channel layers use WN = 1 so no MFMA lane idles.
-// HEAD (inference): the layer has 32 output channels, all in one workgroup
-// column and one wave; instead of storing them the epilogue rounds each
-// activation to BF16 (as a store and reload would), applies the 1x1 head and
-// the residual, and writes out[p] = phi[p] + hb + sum_c a_c wh[c].
-template <int KS, bool UP, int WM, int WN, int TM = 2, int TN = 2, bool HEAD = false>
-__global__ void __launch_bounds__(256)
-conv_fwd_kernel(View X, int lgCin, int B, int H, int W, const bf16_t *__restrict__ Wk,
-                const float *__restrict__ bias, int Cout, View Y, int relu,
-                const float *__restrict__ wh, const float *__restrict__ hb,
-                const float *__restrict__ phi, float *__restrict__ out)
-{
-    constexpr int TBM = 16 * TM * WM, TBN = 16 * TN * WN;
-    constexpr int NA = (TBM * 4 + 255) / 256, NB = (TBN * 4 + 255) / 256;
-    __shared__ __align__(16) bf16_t As[TBM * LP];
-    __shared__ __align__(16) bf16_t Bs[TBN * LP];
-    const int Cin = 1 << lgCin, K = KS * KS * Cin, M = B * H * W;
-    const int mt = xcd_tile((M + TBM - 1) / TBM);
-    if (mt * TBM >= M) return;                      // padding workgroup (whole group)
-    const int m0 = mt * TBM, n0 = blockIdx.y * TBN;
-    const int t = threadIdx.x;
-    int arow[NA], akc[NA], pn[NA], py[NA], px[NA];
-    bool aok[NA];
-#pragma unroll
-    for (int u = 0; u < NA; ++u) {
-        const int c = t + 256 * u;
-        arow[u] = c >> 2;
-        akc[u] = (c & 3) * 8;
-        const int m = m0 + arow[u];
-        aok[u] = c < TBM * 4 && m < M;
-        pn[u] = py[u] = px[u] = 0;
-        if (aok[u]) {
-            pn[u] = m / (H * W);
-            const int rem = m - pn[u] * H * W;
-            py[u] = rem / W;
-            px[u] = rem - py[u] * W;
-        }
-    }
-    auto loadA = [&](int u, int k0) -> uint4 {
-        const int k = k0 + akc[u];
-        if (!aok[u] || k >= K) return uint4{0, 0, 0, 0};
-        const int tap = k >> lgCin, ci = k & (Cin - 1);
-        int yy = py[u], xx = px[u];
-        if (KS == 3) {
-            yy = clampi(py[u] + tap / 3 - 1, 0, H - 1);
-            xx = clampi(px[u] + tap % 3 - 1, 0, W - 1);
-        }
-        return *reinterpret_cast<const uint4 *>(X.p + ((size_t)(pn[u] * H + yy) * W + xx) * X.Cs + X.Co + ci);
-    };
-    auto loadB = [&](int u, int k0) -> uint4 {
-        const int c = t + 256 * u, co = n0 + (c >> 2), k = k0 + (c & 3) * 8;
-        if (c >= TBN * 4 || co >= Cout || k >= K) return uint4{0, 0, 0, 0};
-        return *reinterpret_cast<const uint4 *>(Wk + (size_t)co * K + k);
-    };
-    floatx4 acc[TM][TN] = {};
-    uint4 ra[NA], rb[NB];
-#pragma unroll
-    for (int u = 0; u < NA; ++u) ra[u] = loadA(u, 0);
-#pragma unroll
-    for (int u = 0; u < NB; ++u) rb[u] = loadB(u, 0);
-    for (int k0 = 0; k0 < K; k0 += BK) {
-#pragma unroll
-        for (int u = 0; u < NA; ++u)
-            if (t + 256 * u < TBM * 4) *reinterpret_cast<uint4 *>(As + arow[u] * LP + akc[u]) = ra[u];
-#pragma unroll
-        for (int u = 0; u < NB; ++u) {
-            const int c = t + 256 * u;
-            if (c < TBN * 4) *reinterpret_cast<uint4 *>(Bs + (c >> 2) * LP + (c & 3) * 8) = rb[u];
-        }
-        __syncthreads();
-        if (k0 + BK < K) {
-#pragma unroll
-            for (int u = 0; u < NA; ++u) ra[u] = loadA(u, k0 + BK);
-#pragma unroll
-            for (int u = 0; u < NB; ++u) rb[u] = loadB(u, k0 + BK);
-        }
-        mma_step_g<WM, WN, TM, TN>(As, Bs, acc);
-        __syncthreads();
-    }
-    if constexpr (HEAD) {
-        static_assert(WN == 1 && 16 * TN == 32, "head epilogue needs the 32 channels in one wave");
-        // lanes with equal lane / 16 hold the 32 channels of one pixel row
-#pragma unroll
-        for (int i = 0; i < TM; ++i)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                int row = 0, col = 0;
-                float part = 0.f;
-#pragma unroll
-                for (int j = 0; j < TN; ++j) {
-                    acc_coord_g<WM, WN, TM, TN>(i, j, q, &row, &col);
-                    float v = acc[i][j][q] + bias[col];
-                    v = v > 0.f ? v : 0.f;
-                    part += bf2f(f2bf(v)) * wh[col];
-                }
-#pragma unroll
-                for (int m = 1; m < 16; m <<= 1) part += __shfl_xor(part, m, 64);
-                const int mg = m0 + row;
-                if ((threadIdx.x & 15) == 0 && mg < M) out[mg] = phi[mg] + (hb[0] + part);
-            }
-        return;
-    }
-#pragma unroll
-    for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                int row, col;
-                acc_coord_g<WM, WN, TM, TN>(i, j, q, &row, &col);
-                const int mg = m0 + row, cg = n0 + col;
-                if (mg >= M || cg >= Cout) continue;
-                float v = acc[i][j][q] + bias[cg];
-                if (relu) v = v > 0.f ? v : 0.f;
-                const bf16_t o = f2bf(v);
-                if (!UP) {
-                    Y.p[(size_t)mg * Y.Cs + Y.Co + cg] = o;
-                } else {
-                    const int n = mg / (H * W), rem = mg - n * H * W, y = rem / W, x = rem - y * W;
-#pragma unroll
-                    for (int d = 0; d < 4; ++d) {
-                        const size_t pix = ((size_t)n * 2 * H + 2 * y + (d >> 1)) * 2 * W + 2 * x + (d & 1);
-                        Y.p[pix * Y.Cs + Y.Co + cg] = o;
-                    }
-                }
-            }
-}
 
 // ------------------------------------------------------- input gradient ----
 // dX_pad at (y+1, x+1) = sum_{tap, co} dZ[y+1-ky][x+1-kx][co] * W[co][tap][ci]
@@ -679,22 +549,6 @@ const bf16_t *wk_of(const ac_sur *s, int l) { return s->wb + s->kwoff[l]; }
 const bf16_t *wt_of(const ac_sur *s, int l) { return s->wt + s->kwoff[l]; }
 
 // Y = act(conv(X)); H, W: the resolution of X (and Y unless up)
-template <int KS, bool UP, int WM, int WN, int TM = 2, int TN = 2>
-void launch_fwd(ac_sur *s, int l, View X, int lgcin, int B, int H, int W, View Y, bool relu) {
-    const LayerDef &L = kLayers[l];
-    const int M = B * H * W, TBM = 16 * TM * WM, TBN = 16 * TN * WN;
-    dim3 grid(xcd_grid((M + TBM - 1) / TBM), (L.cout + TBN - 1) / TBN);
-    hipLaunchKernelGGL((conv_fwd_kernel<KS, UP, WM, WN, TM, TN>), grid, dim3(256), 0, s->st, X, lgcin, B,
-                       H, W, wk_of(s, l), bias_of(s, l), L.cout, Y, (int)relu,
-                       (const float *)nullptr, (const float *)nullptr, (const float *)nullptr,
-                       (float *)nullptr);
-}
-
-// 3x3 layer (relu) from an LDS patch: Y (and the pooled P, or the head
-// output `out`) from X, with the first LOWC input channels from Xlo at half
-// resolution.
-// FIRST (layer E1B only): the first layer runs inside the patch load from
-// the FP32 input `phi`; e1a_out (may be null) receives its output.
 // ul: the decoder 1x1 layer fused into the epilogue (UPC > 0), writing `up`
 template <int CIN, int CN, int RW, int LOWC, bool POOL, bool HEAD, bool FIRST = false, int UPC = 0>
 void launch_c3p(ac_sur *s, int l, View X, View Xlo, int B, int H, int W, View Y, View P,
@@ -714,19 +568,6 @@ void launch_c3p(ac_sur *s, int l, View X, View Xlo, int B, int H, int W, View Y,
                        s->st, X, Xlo, B, H, W, s->wf + s->kwoff[l], bias_of(s, l), L.cout, Y, P, aux);
 }
 
-// the 1x1 layers (the 3x3 ones run as launch_c3p)
-void conv_fwd(ac_sur *s, int l, View X, int B, int H, int W, View Y, bool relu, bool up) {
-    const LayerDef &L = kLayers[l];
-    const int lg = lg2(L.cin);
-    const bool narrow = L.cout <= 32;          // 128 x 32 tiles
-    if (up) {
-        if (narrow) launch_fwd<1, true, 4, 1>(s, l, X, lg, B, H, W, Y, relu);
-        else launch_fwd<1, true, 2, 2>(s, l, X, lg, B, H, W, Y, relu);
-    } else {
-        if (narrow) launch_fwd<1, false, 4, 1>(s, l, X, lg, B, H, W, Y, relu);
-        else launch_fwd<1, false, 2, 2>(s, l, X, lg, B, H, W, Y, relu);
-    }
-}
 
 template <int KS, int WM, int WN>
 void launch_wgrad(ac_sur *s, View dZ, int cout, View X, int lgcin, int B, int H, int W, float *dW) {
