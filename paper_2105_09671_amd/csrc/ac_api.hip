@@ -327,6 +327,16 @@ ac_status make_plan3d(int nx, int ny, int nz, int64_t nsteps, size_t elem, const
     // FP32, depth 3 / 32x16x32 in FP64; register kernel: depth 4 FP32, 3 FP64
     int K = f64 ? 3 : 4, LX = reg ? 64 : 32, LY = reg ? 32 : (f64 ? 16 : 32), LZ = 32;
     int threads = f64 ? 256 : 512;
+    if (reg && !f64 && !(tune && (tune->tb_depth || tune->tile_y > 0)) &&
+        (int64_t)ac::reg2d_tiles_1d(nx, 64, 4) * ac::reg2d_tiles_1d(ny, 32, 4) * ((nz + 31) / 32) <
+            4LL * std::max(dev.cus, 1)) {
+        // FP32 register tiles on a grid of less than two rounds of depth-4
+        // segments (the short-segment regime below): depth 3 recomputes less
+        // halo per segment.  Measured at 256^3 (A/B on one box): 1255-1258
+        // GLUPS at depth 3 (26-plane segments) against 1208 at depth 4; at
+        // 512^3, outside the regime, depth 3 runs 1086 against 1623-1632
+        K = 3;
+    }
     if (tune) {
         if (tune->tb_depth) K = tune->tb_depth;
         if (tune->tile_x > 0) LX = tune->tile_x;
