@@ -3,21 +3,24 @@
 //
 // A workgroup of 4 waves computes an output tile of TY = 4 RW rows x 64
 // columns of one image and CN output channels (blockIdx.y picks the channel
-// slice).  Wave w owns tile rows RW w .. RW w + RW - 1, i.e. 64 RW pixels = 4 RW
-// A fragments of 16 pixels, times CN / 16 B fragments.
+// slice; every layer here takes all its channels in one slice).  Wave w owns
+// the 16-column strip 16 w .. 16 w + 15 of all TY rows: TY A fragments of 16
+// pixels, times CN / 16 B fragments.
 //
 // K runs over 32-channel chunks of the input and, per chunk, over the 9 taps.
 // For a chunk the workgroup copies the (TY + 2) x 66 pixel patch around its
 // tile (rows and columns clamped to the image: the replicate padding) into
 // LDS, 32 channels per pixel at a pitch of 40 bf16 (80 bytes: sixteen
 // consecutive pixels of one 16-byte channel group then fall on sixteen
-// disjoint 4-bank groups, so a fragment read has no bank conflict).  The A
-// fragment of tap (dy, dx) for the 16 pixels starting at tile column c of row
-// r is at ((r + dy) * 66 + c + dx) * 40 + 8 * (lane / 16) + ...: a per-lane
-// base plus a compile-time offset, so the K loop does no address arithmetic.
-// B fragments (weights) are read from global memory in fragment order
+// disjoint 4-bank groups, so a fragment read has no bank conflict).  The
+// fragment of patch row r, columns c + dx .. c + dx + 15, is at
+// (r * 66 + c + dx) * 40 + 8 * (lane / 16) + ...: a per-lane base plus a
+// compile-time offset, so the K loop does no address arithmetic.  Per column
+// shift dx a wave reads the TY + 2 rows of its strip once and uses row i + dy
+// for tile row i at each row shift dy: one read serves three taps.  B
+// fragments (weights) are read from global memory in fragment order
 // ([chunk][tap][16-channel tile][lane][8]; 1 KiB per wave and fragment,
-// L2-resident), one K step ahead of their use.
+// L2-resident), one or two K steps ahead of their use.
 //
 // Channels may come from two sources: the first LOWC channels from a tensor
 // at half resolution, read at (y / 2, x / 2) (the nearest 2x upsampling of a
@@ -25,9 +28,10 @@
 //
 // Epilogue: bias, relu, rounding to bf16, then the tile is staged in LDS
 // (pitch CN + 8) and written with 16-byte stores; optionally also the 2 x 2
-// average of the tile (the pooled input of the next level), or -- for the
-// last layer, CN = 32 -- the 1x1 head and the residual, out = phi + hb +
-// sum_c a_c wh_c in FP32, in channel order.
+// average of the tile (the pooled input of the next level); or the decoder's
+// 1x1 layer over the staged tile (UPC outputs, no activation), written at
+// this resolution; or -- for the last layer, CN = 32 -- the 1x1 head and the
+// residual, out = phi + hb + sum_c a_c wh_c in FP32, in channel order.
 #pragma once
 
 #include <hip/hip_runtime.h>
