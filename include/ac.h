@@ -204,12 +204,16 @@ typedef struct {
  * z-streamed 7-point tile of ac_step_3d, one item per (instance, xy tile, z
  * segment)), captured in a hipGraph and cached like the 2D batch.  Validation
  * as in ac_step_3d per instance, no two buffers may overlap.  The launch shape
- * comes from `tune` (tb_depth 1..4, tile_x, tile_y, tile_z), else the 3D
- * defaults; nsteps not divisible by tb_depth adds one shorter phase.  Every
- * instance runs the LDS tile body, except with tune->kernel =
- * AC_KERNEL_3D_REG in FP32, where instances at least 64 cells wide run the
- * register tile body on flush 64 x 32 tiles and 32-plane segments.  Result
- * in each phi.  Each instance is stepped exactly as ac_step_3d steps it, bit
+ * comes from `tune` (tb_depth 1..4, tile_x, tile_y, tile_z), else the batch
+ * defaults (FP32: depth 2, segments of about 24 planes; FP64: the 3D
+ * defaults); nsteps not divisible by tb_depth adds one shorter phase.  With
+ * no tile_x / tile_y given, each instance gets its own LDS tile shape (the
+ * one of at most two cells per thread that computes the fewest cells over
+ * its xy extent), and each instance's depth is cut into z segments of equal
+ * length near tile_z.  Every instance runs the LDS tile body, except with
+ * tune->kernel = AC_KERNEL_3D_REG in FP32, where instances at least 64 cells
+ * wide run the register tile body on flush 64 x 32 tiles and 32-plane
+ * segments.  Result in each phi.  Each instance is stepped exactly as ac_step_3d steps it, bit
  * for bit (the update of a cell does not depend on tile shape or depth). */
 ac_status ac_step_batched_3d(const ac_instance3d *inst, int32_t n_inst, int64_t nsteps,
                              int32_t dtype, const ac_tune *tune, ac_batch_info *info,
