@@ -59,13 +59,14 @@ def test_forward_matches_oracle(sur, B, hw):
 
 @pytest.mark.parametrize("B,hw", [(3, 20), (2, 32), (1, 64), (1, 136)])
 def test_infer_matches_forward_and_oracle(sur, B, hw):
-    """The fused inference path (decoder 1x1 outputs kept at low resolution and
+    """The inference path (decoder 1x1 outputs kept at low resolution and
     upsampled inside the next 3x3 layer's patch load; head and residual in the
-    last layer's epilogue) against the unfused forward, which stores the
-    upsampled maps and runs the head as its own kernel: the same products in
-    the same order, so bit for bit equal; and against the oracle to the
-    forward's own bar.  Sizes cover grids narrower than a 64-wide tile, odd
-    sizes at the coarse levels (20 -> 10 -> 5) and ragged tiles (136)."""
+    last layer's epilogue; the first skip tensor dense) against the training
+    forward, which also stores the 3x3 outputs, copies the upsampled 1x1 maps
+    into the concatenations and runs the head as its own kernel: the same
+    products in the same order, so bit for bit equal; and against the oracle
+    to the forward's own bar.  Sizes cover grids narrower than a 64-wide tile,
+    odd sizes at the coarse levels (20 -> 10 -> 5) and ragged tiles (136)."""
     w, phi, _ = _case(62, B, hw)
     net = sur.Surrogate(B, hw)
     net.set_weights(w.astype(np.float32))
@@ -173,3 +174,28 @@ def test_backward_of_external_output_gradient(sur):
     with pytest.raises(ValueError):
         net.backward(1, dU)                         # wrong batch for the gradient tensor
     net.close()
+
+
+def test_infer_full_batch_sampled_against_oracle(sur):
+    """The benchmarked launch: 256 grids of 256^2 in one inference call with
+    the stored trained weights.  One sampled grid against the FP64 oracle (fed
+    the same BF16-rounded weights and input) to the forward's bar, and equal
+    bit for bit to the same grid inferred alone (no result depends on the
+    batch or on where a tile lands)."""
+    import os
+    B, hw, k = 256, 256, 137
+    path = os.path.join(os.path.dirname(__file__), "..", "paper_2105_09671_amd", "weights", "sur256.npz")
+    w = bf16_round(np.load(path)["weights"]).astype(np.float64)
+    phi = bf16_round(inputs.random_field((B, hw, hw), 71, amp=0.9))
+    net = sur.Surrogate(B, hw)
+    net.set_weights(w.astype(np.float32))
+    x = torch.from_numpy(phi).cuda()
+    out = net.infer(x).cpu().numpy()
+    one = net.infer(x[k:k + 1].contiguous()).cpu().numpy()
+    net.close()
+    assert np.all(np.isfinite(out))
+    assert np.array_equal(out[k], one[0])
+    ref = S.forward(w, phi[k:k + 1].astype(np.float64))[0]
+    U, Ur = out[k].astype(np.float64) - phi[k], ref - phi[k]
+    assert _rel(U, Ur) <= 1e-2
+    assert np.max(np.abs(U - Ur)) <= 5e-2 * np.max(np.abs(Ur))
