@@ -42,7 +42,7 @@ CSRC = os.path.join(ROOT, "paper_2105_09671_amd", "csrc")
 TRAFFIC_HEADLINE = (os.path.join(ROOT, "profiles", "traffic_tile2d_reg_circle2048_fp32.json"),
                     [os.path.join(CSRC, f) for f in ("stencil2d.hip", "reg2d.h", "update.h")])
 TRAFFIC_BATCH = (os.path.join(ROOT, "profiles", "traffic_batched_phase_batch512_fp32.json"),
-                 [os.path.join(CSRC, f) for f in ("batched.hip", "reg2d.h", "update.h")])
+                 [os.path.join(CSRC, f) for f in ("batched.hip", "reg2d.h", "reg2w.h", "update.h")])
 
 
 def log(*a):

@@ -36,6 +36,7 @@
 #include <vector>
 
 #include "reg2d.h"
+#include "reg2w.h"
 #include "reg3d.h"
 #include "stream3d.h"
 #include "tile2d.h"
@@ -149,15 +150,24 @@ __device__ void copy_tile(const T *src, T *dst, int nx, int ny, int LX, int LY, 
 }
 
 // One tile of one instance with the single-grid plan's tile body: BODY_REG
-// (registers, 64-wide), BODY_INPLACE (one LDS buffer, 64-wide) or BODY_LDS2
-// (two LDS buffers, width LXC, or LX at run time when LXC = 0).
-enum { BODY_LDS2 = 0, BODY_INPLACE = 1, BODY_REG = 2 };
+// (registers, 64-wide), BODY_INPLACE (one LDS buffer, 64-wide), BODY_LDS2
+// (two LDS buffers, width LXC, or LX at run time when LXC = 0) or BODY_REGW
+// (per item: wide = 1, the 128-wide register tile of reg2w.h, LY / 2 rows, for
+// instances at least 128 wide; wide = 0, the 64-wide one).
+enum { BODY_LDS2 = 0, BODY_INPLACE = 1, BODY_REG = 2, BODY_REGW = 3 };
 
 template <typename T, int LXC, int BODY>
 __device__ __forceinline__ void tile_item(const T *src, T *dst, const BatchInst &I, int LX, int LY,
-                                          int K, int k, int tx, int ty, unsigned char *smem)
+                                          int K, int k, int tx, int ty, int wide, unsigned char *smem)
 {
-    if constexpr (BODY == BODY_REG)
+    if constexpr (BODY == BODY_REGW) {
+        if (wide)
+            reg2w_body<T, kRegWRows>(src, dst, I.nx, I.ny, (T)I.alpha, (T)I.r, K, k, tx, ty,
+                                     reinterpret_cast<T *>(smem));
+        else
+            reg2d_body<T, kRegRows>(src, dst, I.nx, I.ny, (T)I.alpha, (T)I.r, K, k, tx, ty,
+                                    reinterpret_cast<T *>(smem));
+    } else if constexpr (BODY == BODY_REG)
         reg2d_body<T, kRegRows>(src, dst, I.nx, I.ny, (T)I.alpha, (T)I.r, K, k, tx, ty,
                                 reinterpret_cast<T *>(smem));
     else if constexpr (BODY == BODY_INPLACE)
@@ -198,11 +208,12 @@ batched_kernel(const BatchInst *__restrict__ inst, const int4 *__restrict__ item
             if (b < nblocks) {
                 const T *src = static_cast<const T *>((b & 1) ? I.work : I.phi);
                 T *dst = static_cast<T *>((b & 1) ? I.phi : I.work);
-                tile_item<T, LXC, BODY>(src, dst, I, LX, LY, K, k, it.y, it.z, smem_raw);
+                tile_item<T, LXC, BODY>(src, dst, I, LX, LY, K, k, it.y, it.z, it.w, smem_raw);
             } else {   // odd number of single-step phases: the result sits in work
-                copy_tile<T, BODY == BODY_REG>(static_cast<const T *>(I.work),
-                                               static_cast<T *>(I.phi), I.nx, I.ny, LX, LY, K,
-                                               it.y, it.z);
+                const bool wide = BODY == BODY_REGW && it.w;
+                copy_tile<T, BODY == BODY_REG || BODY == BODY_REGW>(
+                    static_cast<const T *>(I.work), static_cast<T *>(I.phi), I.nx, I.ny,
+                    wide ? 128 : LX, wide ? LY / 2 : LY, K, it.y, it.z);
             }
             if (threadIdx.x == 0) s_ticket = next;
             __syncthreads();                      // LDS is reused by the next item
@@ -238,10 +249,12 @@ batched_phase_kernel(const BatchInst *__restrict__ inst, const int4 *__restrict_
     if (!copy) {
         const T *src = static_cast<const T *>((phase & 1) ? I.work : I.phi);
         T *dst = static_cast<T *>((phase & 1) ? I.phi : I.work);
-        tile_item<T, LXC, BODY>(src, dst, I, LX, LY, K, k, it.y, it.z, smem_raw);
+        tile_item<T, LXC, BODY>(src, dst, I, LX, LY, K, k, it.y, it.z, it.w, smem_raw);
     } else {
-        copy_tile<T, BODY == BODY_REG>(static_cast<const T *>(I.work), static_cast<T *>(I.phi),
-                                       I.nx, I.ny, LX, LY, K, it.y, it.z);
+        const bool wide = BODY == BODY_REGW && it.w;
+        copy_tile<T, BODY == BODY_REG || BODY == BODY_REGW>(
+            static_cast<const T *>(I.work), static_cast<T *>(I.phi), I.nx, I.ny, wide ? 128 : LX,
+            wide ? LY / 2 : LY, K, it.y, it.z);
     }
 }
 
@@ -440,6 +453,7 @@ const void *phase_kernel_ptr() { return (const void *)batched_phase_kernel<T, LX
 // the tile body the single-grid plan chose (AC_KERNEL_2D_*)
 int body_of(int plan_kernel) {
     return plan_kernel == AC_KERNEL_2D_REG       ? BODY_REG
+           : plan_kernel == AC_KERNEL_2D_REGW    ? BODY_REGW
            : plan_kernel == AC_KERNEL_2D_INPLACE ? BODY_INPLACE
                                                  : BODY_LDS2;
 }
@@ -447,6 +461,7 @@ int body_of(int plan_kernel) {
 template <typename T>
 const void *phase_kernel_of(int LX, int body) {
     if (body == BODY_REG) return phase_kernel_ptr<T, 64, BODY_REG>();
+    if (body == BODY_REGW) return phase_kernel_ptr<T, 64, BODY_REGW>();
     if (body == BODY_INPLACE) return phase_kernel_ptr<T, 64, BODY_INPLACE>();
     if (LX == 64) return phase_kernel_ptr<T, 64>();
     if (LX == 128) return phase_kernel_ptr<T, 128>();
@@ -456,6 +471,7 @@ const void *phase_kernel_of(int LX, int body) {
 template <typename T>
 const void *kernel_of(int LX, int body) {
     if (body == BODY_REG) return kernel_ptr<T, 64, BODY_REG>();
+    if (body == BODY_REGW) return kernel_ptr<T, 64, BODY_REGW>();
     if (body == BODY_INPLACE) return kernel_ptr<T, 64, BODY_INPLACE>();
     if (LX == 64) return kernel_ptr<T, 64>();
     if (LX == 128) return kernel_ptr<T, 128>();
@@ -505,12 +521,33 @@ ac_status build_plan(Plan &p, const ac_instance2d *inst, int32_t n, int64_t nste
                      const ac_tune &tune, const std::vector<double> &alpha,
                      const std::vector<double> &r, const DevInfo &dev) {
     const size_t elem = elem_size(dtype);
-    // launch shape: the single-grid tiled plan for the same tune (forced tiled)
+    // launch shape: the single-grid tiled plan for the same tune (forced tiled).
+    // kernel AC_KERNEL_2D_REGW: register tiles 128 wide (and half as tall, the
+    // same waves) for instances at least 128 wide, 64 wide for the others; the
+    // plan is made for the 64-wide tile
     ac_tune t = tune;
+    if (!t.tb_depth && !t.tile_x && !t.tile_y && !t.kernel) {
+        // default: depth 8, 128-wide register tiles for the instances at least
+        // 128 wide, 64-wide ones of twice the height for the others; FP32 128
+        // x 96 (12 waves), FP64 128 x 64 (8 waves).  Measured on the 512-grid
+        // batch: FP32 2797-2813 GLUPS against 2686-2700 with 64 x 128 tiles
+        // for every instance (128 x 64: 2673-2684, 128 x 128: 2013); FP64 1682
+        // against 1571-1575 (128 x 96: 1216)
+        t.kernel = AC_KERNEL_2D_REGW;
+        t.tb_depth = 8;
+        t.tile_y = dtype == AC_F32 ? 96 : 64;
+    }
+    const bool wide = t.kernel == AC_KERNEL_2D_REGW;
+    if (wide) {
+        t.kernel = AC_KERNEL_2D_REG;
+        if (t.tile_x == 128) t.tile_x = 64;
+        if (t.tile_y > 0) t.tile_y *= 2;                 // given as the wide tile's height
+    }
     if (t.tile_x == 0) t.tile_x = 64;
-    // default: depth 8 on 64 x 128 register tiles (8 waves), fastest measured
-    // on the 512-grid batch in both precisions (FP32 2692 GLUPS, FP64 1539;
-    // depth 7 on 64 x 128: 2602 / 1489; depth 8 on 64 x 192: 2625 / 1482)
+    // other shapes fill in from depth 8 on 64 x 128 register tiles (8 waves),
+    // the fastest 64-wide tile on the 512-grid batch in both precisions (FP32
+    // 2692 GLUPS, FP64 1539; depth 7 on 64 x 128: 2602 / 1489; depth 8 on
+    // 64 x 192: 2625 / 1482)
     if (t.tile_y == 0) t.tile_y = 128;
     if (t.tb_depth == 0) t.tb_depth = 8;
     ac_plan tp;
@@ -518,6 +555,8 @@ ac_status build_plan(Plan &p, const ac_instance2d *inst, int32_t n, int64_t nste
     if (s != AC_OK) return s;
     if (tp.kernel == AC_KERNEL_2D_REGW)
         return fail(AC_ERR_UNSUPPORTED, "batches run 64-wide tiles (kernel %d is 128 wide)", tp.kernel);
+    if (wide && tp.kernel != AC_KERNEL_2D_REG)
+        return fail(AC_ERR_UNSUPPORTED, "128-wide batch tiles need the register tile body");
     const int LX = tp.tile_x, LY = tp.tile_y, K = tp.tb_depth;
     const int OX = LX - 2 * K, OY = LY - 2 * K;
     std::vector<BatchInst> hi(n);
@@ -526,10 +565,13 @@ ac_status build_plan(Plan &p, const ac_instance2d *inst, int32_t n, int64_t nste
         hi[i] = BatchInst{inst[i].phi, inst[i].work, inst[i].nx, inst[i].ny, alpha[i], r[i]};
         // register tiles sit flush against the domain edges (reg2d.h)
         const bool reg = tp.kernel == AC_KERNEL_2D_REG;
-        const int tx = reg ? reg2d_tiles_1d(inst[i].nx, LX, K) : (inst[i].nx + OX - 1) / OX;
-        const int ty = reg ? reg2d_tiles_1d(inst[i].ny, LY, K) : (inst[i].ny + OY - 1) / OY;
+        const int w = wide && inst[i].nx >= 128 ? 1 : 0;
+        const int tx = w ? reg2d_tiles_1d(inst[i].nx, 128, K)
+                       : reg ? reg2d_tiles_1d(inst[i].nx, LX, K) : (inst[i].nx + OX - 1) / OX;
+        const int ty = w ? reg2d_tiles_1d(inst[i].ny, LY / 2, K)
+                       : reg ? reg2d_tiles_1d(inst[i].ny, LY, K) : (inst[i].ny + OY - 1) / OY;
         for (int y = 0; y < ty; ++y)
-            for (int x = 0; x < tx; ++x) items.push_back(int4{i, x, y, 0});
+            for (int x = 0; x < tx; ++x) items.push_back(int4{i, x, y, w});
     }
     const Chunks c = plan_chunks(nsteps, K);
     // tickets and finished-item counts are 32-bit and monotonic over the call
@@ -537,8 +579,10 @@ ac_status build_plan(Plan &p, const ac_instance2d *inst, int32_t n, int64_t nste
         return fail(AC_ERR_UNSUPPORTED, "%zu tiles x %lld phases exceed the 32-bit work counters",
                     items.size(), (long long)c.n);
     // workgroup size and LDS follow the tile body the plan chose
-    const void *kern = select_kernel(dtype, LX, tp.kernel);
-    const size_t lds = (size_t)tp.lds_bytes;
+    const int body_kernel = wide ? AC_KERNEL_2D_REGW : tp.kernel;
+    const void *kern = select_kernel(dtype, LX, body_kernel);
+    const size_t lds = wide ? std::max((size_t)tp.lds_bytes, tile2d_regw_lds_bytes(LY / 2, elem))
+                            : (size_t)tp.lds_bytes;
     const int threads = tp.threads;
     set_lds_limit(kern, lds);
     int per_cu = 0;
@@ -600,7 +644,7 @@ ac_status build_plan(Plan &p, const ac_instance2d *inst, int32_t n, int64_t nste
     if (g_persistent) {
         le = hipLaunchKernel(kern, dim3(grid), dim3(threads), args, lds, cs);
     } else {
-        const void *pk = select_phase_kernel(dtype, LX, tp.kernel);
+        const void *pk = select_phase_kernel(dtype, LX, body_kernel);
         set_lds_limit(pk, lds);
         for (int b = 0; b <= nblocks && le == hipSuccess; ++b) {
             const int copy = b == nblocks;
@@ -626,8 +670,8 @@ ac_status build_plan(Plan &p, const ac_instance2d *inst, int32_t n, int64_t nste
     p.info.grid = g_persistent ? grid : phase_grid;
     p.info.items = p.n_items;
     p.info.tb_depth = K;
-    p.info.tile_x = LX;
-    p.info.tile_y = LY;
+    p.info.tile_x = wide ? 128 : LX;                    // wide: the tile of the wide instances
+    p.info.tile_y = wide ? LY / 2 : LY;
     p.info.blocks = nblocks;
     p.info.copy_back = cb;
     p.info.lds_bytes = (int64_t)lds;

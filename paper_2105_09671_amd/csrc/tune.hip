@@ -88,7 +88,8 @@ static std::vector<ac_tune> cands2d() {
     // two-buffer LDS tile
     const int tiles[][3] = {{64, 64, AC_KERNEL_2D_REG},     {64, 128, AC_KERNEL_2D_REG},
                             {64, 192, AC_KERNEL_2D_REG},    {128, 32, AC_KERNEL_2D_REGW},
-                            {128, 64, AC_KERNEL_2D_REGW},   {128, 128, AC_KERNEL_2D_REGW},
+                            {128, 64, AC_KERNEL_2D_REGW},   {128, 96, AC_KERNEL_2D_REGW},
+                            {128, 128, AC_KERNEL_2D_REGW},
                             {64, 64, AC_KERNEL_2D_INPLACE}, {64, 128, AC_KERNEL_2D_INPLACE},
                             {128, 64, AC_KERNEL_2D_TILED}};
     for (int k : {3, 4, 5, 6, 7, 8})

@@ -46,7 +46,8 @@ def mode(request, api):
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 @pytest.mark.parametrize("nsteps,tune", [(37, None), (37, dict(tb_depth=3, tile_x=64, tile_y=32)),
                                          (5, dict(tb_depth=1, tile_x=64, tile_y=32)),
-                                         (1, None), (8, dict(tb_depth=8, tile_x=128, tile_y=64))])
+                                         (1, None), (8, dict(tb_depth=8, tile_x=128, tile_y=64)),
+                                         (37, dict(kernel=6)), (9, dict(kernel=6, tb_depth=4, tile_y=32))])
 def test_batch_matches_single_and_oracle(api, mode, dtype, nsteps, tune):
     fields, prm = _small_batch()
     fields = [f.astype(NP[dtype]) for f in fields]
@@ -89,14 +90,16 @@ def test_batch_order_and_replay(api):
         assert D.rel_linf(v.cpu().numpy(), ref) <= 1e-5
 
 
-def test_wide_register_tiles_are_refused_for_batches(api):
-    """Batches run 64-wide tiles (instances may be narrower than 128); asking
-    for the 128-wide register kernel is an error, not a silent substitute."""
+def test_wide_batch_tiles_need_register_tiles(api):
+    """Kernel AC_KERNEL_2D_REGW in a batch means 128-wide register tiles for
+    the instances at least 128 wide and 64-wide ones for the rest (covered by
+    the parity test above); a shape the 64-wide register tile cannot take is
+    an error, not a silent substitute."""
     from paper_2105_09671_amd import _lib as L
     fields, prm = _small_batch(44)
     b = api.Batch([f.astype(np.float32) for f in fields], prm)
     with pytest.raises(L.AcError):
-        b.step(10, tune=dict(tb_depth=2, tile_x=128, tile_y=32, kernel=6))
+        b.step(10, tune=dict(tb_depth=2, tile_x=32, tile_y=32, kernel=6))
 
 
 def test_barrier_timeout_is_reported_and_recovers(api):
