@@ -39,8 +39,11 @@ NSTEPS = 20000
 REG3D_MAX_DEPTH = 8     # FP32
 CSRC = os.path.join(ROOT, "paper_2105_09671_amd", "csrc")
 # stored HBM-traffic counters: (summary file, the kernel sources they were taken on)
-TRAFFIC_HEADLINE = (os.path.join(ROOT, "profiles", "traffic_tile2d_reg_circle2048_fp32.json"),
-                    [os.path.join(CSRC, f) for f in ("stencil2d.hip", "reg2d.h", "update.h")])
+TRAFFIC_HEADLINE = {   # by the plan's kernel: 64-wide or 128-wide register tiles
+    4: (os.path.join(ROOT, "profiles", "traffic_tile2d_reg_circle2048_fp32.json"),
+        [os.path.join(CSRC, f) for f in ("stencil2d.hip", "reg2d.h", "update.h")]),
+    6: (os.path.join(ROOT, "profiles", "traffic_tile2d_regw_circle2048_fp32.json"),
+        [os.path.join(CSRC, f) for f in ("stencil2d.hip", "reg2d.h", "reg2w.h", "update.h")])}
 TRAFFIC_BATCH = (os.path.join(ROOT, "profiles", "traffic_batched_phase_batch512_fp32.json"),
                  [os.path.join(CSRC, f) for f in ("batched.hip", "reg2d.h", "reg2w.h", "update.h")])
 
@@ -73,9 +76,11 @@ def timed(fn, reps: int):
     return ts[len(ts) // 2]
 
 
-def measured_traffic(which=TRAFFIC_HEADLINE):
+def measured_traffic(which):
     """HBM bytes per launch from stored rocprofv3 counters, if they were taken on
     the current source of the kernel; else None."""
+    if which is None:
+        return None
     path, srcs = which
     if not os.path.exists(path):
         return None
@@ -473,7 +478,7 @@ def main():
     avg_launch = sec / launches
     alg_bytes = 2 * 4 * cells * NSTEPS / plan["launches"]
     achieved = alg_bytes / avg_launch / 1e9
-    traffic = measured_traffic()
+    traffic = measured_traffic(TRAFFIC_HEADLINE.get(plan["kernel"]))
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             # the true HBM fraction: counter bytes per launch / launch time

@@ -102,12 +102,16 @@ static const TileRate kRegF64[] = {
     {6, 64, 1136, 1444}, {6, 128, 1152, 1363}, {6, 192, 1063, 1410},
     {7, 64, 1190, 1442}, {7, 128, 1212, 1568}, {7, 192, 1119, 1625},
     {8, 64, 1152, 1437}, {8, 128, 1067, 1629}, {8, 192, 955, 1665}};
-// 128-wide register tiles (two columns per lane)
+// 128-wide register tiles (two columns per lane).  The 96-row tiles (12
+// waves) were measured later, in one run with the 128-row ones: `round` as
+// measured, `steady` scaled by the 128-row tile's table value over its
+// measurement in that run (the 16384^2 rates of that run are 7-12 % lower
+// than this table's throughout)
 static const TileRate kRegWF32[] = {
-    {5, 32, 1566, 2254}, {5, 64, 1770, 2360}, {5, 128, 1430, 2419},
-    {6, 32, 1589, 2414}, {6, 64, 1947, 2970}, {6, 128, 1620, 3103},
-    {7, 32, 1687, 2326}, {7, 64, 1995, 2910}, {7, 128, 1669, 3230},
-    {8, 32, 1474, 2073}, {8, 64, 1789, 3054}, {8, 128, 1801, 3455}};
+    {5, 32, 1566, 2254}, {5, 64, 1770, 2360}, {5, 96, 1724, 2501}, {5, 128, 1430, 2419},
+    {6, 32, 1589, 2414}, {6, 64, 1947, 2970}, {6, 96, 1924, 3038}, {6, 128, 1620, 3103},
+    {7, 32, 1687, 2326}, {7, 64, 1995, 2910}, {7, 96, 1980, 3093}, {7, 128, 1669, 3230},
+    {8, 32, 1474, 2073}, {8, 64, 1789, 3054}, {8, 96, 2149, 3265}, {8, 128, 1801, 3455}};
 static const TileRate kRegWF64[] = {
     {5, 32, 954, 1251}, {5, 64, 1000, 1344}, {5, 128, 708, 1059},
     {6, 32, 1109, 1337}, {6, 64, 1157, 1623}, {6, 128, 841, 1226},

@@ -18,8 +18,10 @@ def test_more_than_one_gpu_is_refused():
 def test_traffic_records_are_complete():
     sys.path.insert(0, ROOT)
     import bench
-    for path, srcs in (bench.TRAFFIC_HEADLINE, bench.TRAFFIC_BATCH):
-        if path == bench.TRAFFIC_BATCH[0] and not os.path.exists(path):
+    records = list(bench.TRAFFIC_HEADLINE.values()) + [bench.TRAFFIC_BATCH]
+    assert any(os.path.exists(path) for path, _ in bench.TRAFFIC_HEADLINE.values())
+    for path, srcs in records:
+        if not os.path.exists(path):
             continue
         with open(path) as f:
             t = json.load(f)
