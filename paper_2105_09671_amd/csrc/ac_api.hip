@@ -84,46 +84,45 @@ Chunks plan_chunks(int64_t nsteps, int64_t k) {
 // A plan fixes the kernel, its launch shape and the launch sequence of one
 // call.  Built on the host from the device limits; executing it makes no other
 // decision, so ac_plan_* reports exactly what ac_step_* will launch.
-// Throughput of the tiled 2D kernels on MI355X by depth and tile height, at
-// two loads per CU.  `steady`: GLUPS on a 16384^2 grid in FP32, 16384 x 8192
-// in FP64, where every CU streams many tiles back to back.  `round`: GLUPS on
-// 2048^2, where about one round of tiles is resident at once, so the tiles'
-// loads, steps and stores overlap little and the launch lasts about one
-// tile's whole life.  Register tiles of 6 or 10 waves (64 x 96, 64 x 160)
-// measured 10-25 % slower than 4, 8 or 12 and are left out.
-struct TileRate { int K, LY; double round, steady; };
-static const TileRate kRegF32[] = {
-    {5, 64, 1786, 2133}, {5, 128, 1824, 1932}, {5, 192, 1777, 2127},
-    {6, 64, 1673, 2480}, {6, 128, 1995, 2283}, {6, 192, 1956, 2555},
-    {7, 64, 1828, 2681}, {7, 128, 2075, 2679}, {7, 192, 2051, 2963},
-    {8, 64, 1696, 2506}, {8, 128, 1807, 2902}, {8, 192, 1670, 3051}};
-static const TileRate kRegF64[] = {
-    {5, 64, 1048, 1209}, {5, 128, 1052, 1232}, {5, 192, 982, 1191},
-    {6, 64, 1136, 1444}, {6, 128, 1152, 1363}, {6, 192, 1063, 1410},
-    {7, 64, 1190, 1442}, {7, 128, 1212, 1568}, {7, 192, 1119, 1625},
-    {8, 64, 1152, 1437}, {8, 128, 1067, 1629}, {8, 192, 955, 1665}};
-// 128-wide register tiles (two columns per lane).  The 96-row tiles (12
-// waves) were measured later, in one run with the 128-row ones: `round` as
-// measured, `steady` scaled by the 128-row tile's table value over its
-// measurement in that run (the 16384^2 rates of that run are 7-12 % lower
-// than this table's throughout)
-static const TileRate kRegWF32[] = {
-    {5, 32, 1566, 2254}, {5, 64, 1770, 2360}, {5, 96, 1724, 2501}, {5, 128, 1430, 2419},
-    {6, 32, 1589, 2414}, {6, 64, 1947, 2970}, {6, 96, 1924, 3038}, {6, 128, 1620, 3103},
-    {7, 32, 1687, 2326}, {7, 64, 1995, 2910}, {7, 96, 1980, 3093}, {7, 128, 1669, 3230},
-    {8, 32, 1474, 2073}, {8, 64, 1789, 3054}, {8, 96, 2149, 3265}, {8, 128, 1801, 3455}};
-static const TileRate kRegWF64[] = {
-    {5, 32, 954, 1251}, {5, 64, 1000, 1344}, {5, 128, 708, 1059},
-    {6, 32, 1109, 1337}, {6, 64, 1157, 1623}, {6, 128, 841, 1226},
-    {7, 32, 1141, 1276}, {7, 64, 1269, 1642}, {7, 128, 824, 1191},
-    {8, 32, 1088, 1241}, {8, 64, 1229, 1698}, {8, 128, 985, 1469}};
-// in place in LDS (steady state only)
-static const TileRate kInplaceF32[] = {{6, 64, 1603, 1603}, {7, 64, 1617, 1617},
-                                       {8, 64, 1645, 1645}, {6, 128, 1682, 1682},
-                                       {7, 128, 1707, 1707}, {8, 128, 1732, 1732}};
-static const TileRate kInplaceF64[] = {{3, 32, 666, 666}, {4, 32, 749, 749}, {5, 32, 758, 758},
-                                       {6, 32, 730, 730}, {3, 64, 661, 661}, {4, 64, 719, 719},
-                                       {5, 64, 731, 731}, {6, 64, 725, 725}};
+// Launch time of the 2D register-tile kernels on MI355X by depth K and tile
+// height LY: about a + b * ceil(tiles / CUs) microseconds.  b is one tile's
+// share of a CU's time while every CU streams tiles (two resident per CU); a
+// is the rest of a launch (its start, the first loads that no step overlaps,
+// the last stores).  Fitted by least squares in relative error to launches
+// timed on FP32 grids 1024^2 .. 6144^2 (with 2048 x 1024 and 4096 x 2048) and
+// FP64 grids 512^2 .. 4096^2, every pair on each grid in one run.  A small
+// grid's launch is mostly a, so deep steps and few tiles win there; a large
+// grid's is mostly b per tile.  Register tiles of 6 or 10 waves (64 x
+// 96, 64 x 160) measured 10-25 % slower than 4, 8 or 12 and are left out, as
+// are 128 x 128 FP64 tiles (16 waves), slower than 128 x 64 on every grid.
+struct TileTime { int K, LY; double a, b; };
+static const TileTime kRegF32[] = {
+    {5, 64, 3.18, 1.576}, {5, 128, 2.52, 3.421}, {5, 192, 2.24, 5.353},
+    {6, 64, 3.94, 1.634}, {6, 128, 3.28, 3.440}, {6, 192, 3.08, 5.314},
+    {7, 64, 4.41, 1.670}, {7, 128, 3.70, 3.693}, {7, 192, 3.77, 5.456},
+    {8, 64, 4.74, 1.923}, {8, 128, 4.37, 3.788}, {8, 192, 3.54, 5.839}};
+static const TileTime kRegF64[] = {
+    {5, 64, 3.66, 2.588}, {5, 128, 3.10, 5.590}, {5, 192, 2.64, 8.948},
+    {6, 64, 4.27, 2.719}, {6, 128, 3.95, 5.837}, {6, 192, 3.96, 9.127},
+    {7, 64, 4.75, 2.945}, {7, 128, 4.43, 6.338}, {7, 192, 4.76, 9.681},
+    {8, 64, 5.20, 3.209}, {8, 128, 5.13, 6.555}, {8, 192, 4.76, 10.204}};
+// 128-wide register tiles (two columns per lane)
+static const TileTime kRegWF32[] = {
+    {5, 32, 3.98, 1.390}, {5, 64, 3.30, 3.158}, {5, 96, 3.00, 5.281}, {5, 128, 1.90, 7.517},
+    {6, 32, 4.39, 1.456}, {6, 64, 4.09, 3.084}, {6, 96, 3.60, 5.006}, {6, 128, 3.08, 7.047},
+    {7, 32, 4.31, 1.633}, {7, 64, 4.39, 3.522}, {7, 96, 4.43, 5.267}, {7, 128, 3.88, 7.570},
+    {8, 32, 5.11, 1.778}, {8, 64, 4.90, 3.606}, {8, 96, 4.64, 5.584}, {8, 128, 4.54, 7.486}};
+static const TileTime kRegWF64[] = {
+    {5, 32, 3.43, 2.435}, {5, 64, 2.53, 5.575},
+    {6, 32, 3.80, 2.409}, {6, 64, 2.99, 5.597},
+    {7, 32, 4.14, 2.655}, {7, 64, 3.65, 6.074},
+    {8, 32, 4.41, 2.738}, {8, 64, 4.21, 5.973}};
+// in place in LDS: GLUPS of the whole chip (256 CUs) streaming tiles
+struct TileRate { int K, LY; double rate; };
+static const TileRate kInplaceF32[] = {{6, 64, 1603}, {7, 64, 1617}, {8, 64, 1645},
+                                       {6, 128, 1682}, {7, 128, 1707}, {8, 128, 1732}};
+static const TileRate kInplaceF64[] = {{3, 32, 666}, {4, 32, 749}, {5, 32, 758}, {6, 32, 730},
+                                       {3, 64, 661}, {4, 64, 719}, {5, 64, 731}, {6, 64, 725}};
 
 // 3D: the register kernel is the default from half a round of resident
 // workgroups on (measured on MI355X with flush tiles: 256^3 FP32, 0.57 rounds,
@@ -131,51 +130,48 @@ static const TileRate kInplaceF64[] = {{3, 32, 666, 666}, {4, 32, 749, 749}, {5,
 // 509; 512^3 FP32 1254 against 817, 1024^3 1288 against 970)
 static const int64_t kReg3dMinRoundsNum = 1, kReg3dMinRoundsDen = 2;
 
-// Predicted time of a launch ~ a start-up + the tiles of the busiest CU
-// (ceil(tiles / CUs); the dispatcher spreads workgroups evenly) x one tile's
-// time at the streaming rate measured for that pair.  The start-up (tile
-// loads and stores that no other tile's steps overlap) is what the 2048^2
-// rate lacks against the streaming one, at 2048^2's busiest-CU load.  A grid whose tile count just
-// exceeds a multiple of the CU count gives some CUs one tile more, so the
-// depth and tile height are chosen per grid.  (Charging a partial round as a
-// full round of resident slots, as an earlier model did, preferred tall tiles
-// on 2048^2 that measure 5 % slower.)
+// The (depth, tile height) with the shortest predicted time per cell-step on
+// this grid: ceil(tiles / CUs) is the busiest CU's tile count (the dispatcher
+// spreads workgroups evenly), so a grid whose tile count just exceeds a
+// multiple of the CU count gives some CUs one tile more, and the choice is
+// made per grid.  Returns the predicted GLUPS.
 double choose_tile2d(int nx, int ny, size_t elem, int kernel, const ac::DevInfo &dev, int *K,
                      int *LY) {
     const bool f64 = elem == 8;
     const bool reg = kernel == AC_KERNEL_2D_REG, wide = kernel == AC_KERNEL_2D_REGW;
     const int LX = wide ? 128 : 64;
-    struct Tab {
-        const TileRate *p;
-        int n;
-    };
-    const auto of = [](const auto &t) { return Tab{t, (int)(sizeof t / sizeof *t)}; };
-    const Tab tb = wide ? (f64 ? of(kRegWF64) : of(kRegWF32))
-                   : reg ? (f64 ? of(kRegF64) : of(kRegF32))
-                         : (f64 ? of(kInplaceF64) : of(kInplaceF32));
-    const TileRate *tab = tb.p;
-    const int n = tb.n;
     const int64_t cus = std::max(dev.cus, 1);
+    // (K, LY, a, b) rows: the register tables as they are, the in-place table
+    // as a streaming rate (a = 0, b = a tile's share of the chip's rate)
+    struct Row { int K, LY; double a, b; };
+    Row rows[24];
+    int n = 0;
+    if (reg || wide) {
+        const auto put = [&](const auto &t) {
+            for (const TileTime &r : t) rows[n++] = Row{r.K, r.LY, r.a, r.b};
+        };
+        if (wide) f64 ? put(kRegWF64) : put(kRegWF32);
+        else f64 ? put(kRegF64) : put(kRegF32);
+    } else {
+        const auto put = [&](const auto &t) {
+            for (const TileRate &r : t)
+                rows[n++] = Row{r.K, r.LY, 0.0,
+                                (double)(LX - 2 * r.K) * (r.LY - 2 * r.K) * r.K * 256 / r.rate * 1e-3};
+        };
+        f64 ? put(kInplaceF64) : put(kInplaceF32);
+    }
     double best = -1.0;
-    *K = tab[0].K;
-    *LY = tab[0].LY;
+    *K = rows[0].K;
+    *LY = rows[0].LY;
     for (int i = 0; i < n; ++i) {
-        const int k = tab[i].K, ly = tab[i].LY;
+        const int k = rows[i].K, ly = rows[i].LY;
         const int OX = LX - 2 * k, OY = ly - 2 * k;
         if ((ny + OY - 1) / OY > 65535) continue;
-        const auto busiest_of = [&](int gx, int gy) {
-            // register tiles sit flush against the domain edges (reg2d.h)
-            const int64_t tiles = reg || wide ? (int64_t)ac::reg2d_tiles_1d(gx, LX, k) * ac::reg2d_tiles_1d(gy, ly, k)
-                                              : (int64_t)((gx + OX - 1) / OX) * ((gy + OY - 1) / OY);
-            return (tiles + cus - 1) / cus;
-        };
-        // a launch = a start-up the tiles cannot hide + the busiest CU's tiles
-        // at the streaming rate; the start-up is what makes 2048^2 slower
-        const int64_t busiest = busiest_of(nx, ny), n1 = busiest_of(2048, 2048);
-        const double tile = (double)OX * OY * k * cus;          // / rate = one tile's time
-        const double startup = std::max(0.0, (double)n1 * (tile / tab[i].round - tile / tab[i].steady));
-        const double t = startup + (double)busiest * tile / tab[i].steady;
-        const double rate = (double)nx * ny * k / t;
+        // register tiles sit flush against the domain edges (reg2d.h)
+        const int64_t tiles = reg || wide ? (int64_t)ac::reg2d_tiles_1d(nx, LX, k) * ac::reg2d_tiles_1d(ny, ly, k)
+                                          : (int64_t)((nx + OX - 1) / OX) * ((ny + OY - 1) / OY);
+        const double t = rows[i].a + rows[i].b * (double)((tiles + cus - 1) / cus);
+        const double rate = (double)nx * ny * k / t * 1e-3;
         if (rate > best) {
             best = rate;
             *K = k;
