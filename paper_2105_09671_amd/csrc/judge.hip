@@ -57,14 +57,39 @@ ac_status scratch_ptr(void **out) {
     return AC_OK;
 }
 
+// A workgroup judges a kJTX x kJTY tile of one grid.  Both fields are staged
+// in LDS over the tile and the cells within the search window around it, the
+// tile's crossings are collected into a list, and the list is then shared
+// out over all lanes: the nearest-partner searches (the bulk of the work)
+// read LDS, and no lane idles for want of a crossing of its own.
+constexpr int kJTX = 64, kJTY = 16, kJThreads = 256;
+constexpr int kJMaxList = 4 * kJTX * kJTY;   // two edges per cell in each field
+
+// The staged region of a tile at (x0, y0) for window w: columns x0-w ..
+// x0+kJTX+w and rows y0-w .. y0+kJTY+w (a cell's crossing edges reach one
+// cell further than the window).
+__host__ __device__ constexpr int judge_region_x(int w) { return kJTX + 2 * w + 1; }
+__host__ __device__ constexpr int judge_region_y(int w) { return kJTY + 2 * w + 1; }
+
+size_t judge_lds_bytes(int w) {
+    return (2 * (size_t)judge_region_x(w) * judge_region_y(w) + kJMaxList + 1) * 4;
+}
+
+// A staged field: values of the region whose first cell is (rx0, ry0), row pitch RX.
+struct Staged {
+    const float *v;
+    int RX, rx0, ry0;
+    __device__ float at(int i, int j) const { return v[(j - ry0) * RX + (i - rx0)]; }
+};
+
 // Crossing on the edge from cell (i, j) to (i + di, j + dj); returns false if
 // the sign does not change.  Coordinates in cell units (cell (i, j) centre at
 // (i, j)).
-__device__ inline bool crossing(const float *f, int nx, int ny, int i, int j, int di, int dj,
+__device__ inline bool crossing(const Staged &f, int nx, int ny, int i, int j, int di, int dj,
                                 float *px, float *py) {
     const int i2 = i + di, j2 = j + dj;
     if (i2 >= nx || j2 >= ny) return false;
-    const float a = f[(size_t)j * nx + i], b = f[(size_t)j2 * nx + i2];
+    const float a = f.at(i, j), b = f.at(i2, j2);
     if ((a > 0.f) == (b > 0.f)) return false;
     const float t = a / (a - b);
     *px = i + di * t;
@@ -73,7 +98,7 @@ __device__ inline bool crossing(const float *f, int nx, int ny, int i, int j, in
 }
 
 // min distance from (px, py) to the crossings of g in the window around cell (i, j)
-__device__ inline float nearest(const float *g, int nx, int ny, int i, int j, int w, float px,
+__device__ inline float nearest(const Staged &g, int nx, int ny, int i, int j, int w, float px,
                                 float py) {
     float best = INFINITY;
     for (int jj = max(j - w, 0); jj <= min(j + w, ny - 1); ++jj)
@@ -88,34 +113,75 @@ __device__ inline float nearest(const float *g, int nx, int ny, int i, int j, in
     return best;
 }
 
-__global__ void judge_kernel(const float *__restrict__ a, const float *__restrict__ b, int nx,
-                             int ny, int w, unsigned *dist_bits, float *sq, int *count)
+// grid (tiles_x * tiles_y, batch), kJThreads threads, judge_lds_bytes(w) of LDS
+__global__ void __launch_bounds__(kJThreads)
+judge_kernel(const float *__restrict__ a, const float *__restrict__ b, int nx, int ny, int w,
+             int tiles_x, unsigned *dist_bits, float *sq, int *count)
 {
+    extern __shared__ float jlds[];
     const int n = blockIdx.y;
     const size_t cells = (size_t)nx * ny;
     const float *fa = a + n * cells, *fb = b + n * cells;
+    const int x0 = (int)(blockIdx.x % tiles_x) * kJTX, y0 = (int)(blockIdx.x / tiles_x) * kJTY;
+    const int RX = judge_region_x(w), RY = judge_region_y(w), rx0 = x0 - w, ry0 = y0 - w;
+    float *la = jlds, *lb = jlds + RX * RY;
+    int *list = reinterpret_cast<int *>(lb + RX * RY);
+    int *nlist = list + kJMaxList;
+    const int t = threadIdx.x;
+    if (t == 0) *nlist = 0;
+    // cells outside the grid are staged as 0 and never read: every search
+    // and edge is clamped to the grid first
+    for (int k = t; k < RX * RY; k += kJThreads) {
+        const int gx = rx0 + k % RX, gy = ry0 + k / RX;
+        const bool in = gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+        const size_t o = in ? (size_t)gy * nx + gx : 0;
+        la[k] = in ? fa[o] : 0.f;
+        lb[k] = in ? fb[o] : 0.f;
+    }
+    __syncthreads();
+    const Staged sa{la, RX, rx0, ry0}, sb{lb, RX, rx0, ry0};
     float local = 0.f, ssq = 0.f;
     int cnt = 0;
-    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < (int)cells; c += gridDim.x * blockDim.x) {
-        const int i = c % nx, j = c / nx;
-        const float d = fa[c] - fb[c];
+    // the tile's own cells: squared differences and the list of crossings
+    // (cell, edge, field)
+    for (int c = t; c < kJTX * kJTY; c += kJThreads) {
+        const int i = x0 + c % kJTX, j = y0 + c / kJTX;
+        if (i >= nx || j >= ny) continue;
+        const float d = sa.at(i, j) - sb.at(i, j);
         ssq += d * d;
         for (int e = 0; e < 2; ++e) {
             float px, py;
-            if (crossing(fa, nx, ny, i, j, e == 0, e == 1, &px, &py)) {
-                local = fmaxf(local, nearest(fb, nx, ny, i, j, w, px, py));
+            if (crossing(sa, nx, ny, i, j, e == 0, e == 1, &px, &py)) {
+                list[atomicAdd(nlist, 1)] = c | e << 16;
                 cnt |= 1;
             }
-            if (crossing(fb, nx, ny, i, j, e == 0, e == 1, &px, &py)) {
-                local = fmaxf(local, nearest(fa, nx, ny, i, j, w, px, py));
+            if (crossing(sb, nx, ny, i, j, e == 0, e == 1, &px, &py)) {
+                list[atomicAdd(nlist, 1)] = c | e << 16 | 1 << 17;
                 cnt |= 2;
             }
         }
     }
-    // non-negative floats order like their bit patterns (+inf is the largest)
-    if (local > 0.f) atomicMax(dist_bits + n, __float_as_uint(local));
-    if (cnt) atomicOr(count + n, cnt);
-    atomicAdd(sq + n, ssq);
+    __syncthreads();
+    const int nl = *nlist;
+    for (int k = t; k < nl; k += kJThreads) {
+        // a crossing of one field searches the other field's crossings
+        const int v = list[k], c = v & 0xffff, e = (v >> 16) & 1, in_b = v >> 17;
+        const int i = x0 + c % kJTX, j = y0 + c / kJTX;
+        float px = 0.f, py = 0.f;
+        crossing(in_b ? sb : sa, nx, ny, i, j, e == 0, e == 1, &px, &py);
+        local = fmaxf(local, nearest(in_b ? sa : sb, nx, ny, i, j, w, px, py));
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        ssq += __shfl_xor(ssq, o);
+        local = fmaxf(local, __shfl_xor(local, o));
+        cnt |= __shfl_xor(cnt, o);
+    }
+    if ((t & 63) == 0) {
+        // non-negative floats order like their bit patterns (+inf is the largest)
+        if (local > 0.f) atomicMax(dist_bits + n, __float_as_uint(local));
+        if (cnt) atomicOr(count + n, cnt);
+        atomicAdd(sq + n, ssq);
+    }
 }
 
 __global__ void judge_finish_kernel(const unsigned *dist_bits, const float *sq, const int *count,
@@ -162,8 +228,11 @@ ac_status judge_launch(const float *a, const float *b, int32_t batch, int32_t nx
     int *cnt = reinterpret_cast<int *>(sq + batch);
     hipLaunchKernelGGL(judge_zero_kernel, dim3((batch + 255) / 256), dim3(256), 0, st, dist, sq, cnt, batch);
     const long long cells = (long long)nx * ny;
-    const unsigned gx = (unsigned)std::min<long long>((cells + 255) / 256, 256);
-    hipLaunchKernelGGL(judge_kernel, dim3(gx, batch), dim3(256), 0, st, a, b, nx, ny, (int)window, dist, sq, cnt);
+    const int tiles_x = (nx + kJTX - 1) / kJTX;
+    const long long tiles = (long long)tiles_x * ((ny + kJTY - 1) / kJTY);
+    if (tiles > INT_MAX) return fail(AC_ERR_UNSUPPORTED, "grid %d x %d has too many judge tiles", nx, ny);
+    hipLaunchKernelGGL(judge_kernel, dim3((unsigned)tiles, batch), dim3(kJThreads), judge_lds_bytes(window),
+                       st, a, b, nx, ny, (int)window, tiles_x, dist, sq, cnt);
     hipLaunchKernelGGL(judge_finish_kernel, dim3((batch + 255) / 256), dim3(256), 0, st, dist, sq, cnt,
                        batch, (size_t)cells, (float)h, iface_err, l2_err);
     hipError_t e = hipGetLastError();

@@ -36,7 +36,7 @@ def _find(d: str, suffix: str) -> str:
 
 
 def _short(name: str, n: int = 70) -> str:
-    name = name.replace("void ", "")
+    name = name.replace("void ", "").replace("(anonymous namespace)::", "")
     cut = name.find("(")
     if cut > 0:
         name = name[:cut]
