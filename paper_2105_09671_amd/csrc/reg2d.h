@@ -127,22 +127,47 @@ __device__ __forceinline__ void reg2d_substep(const T (&in)[RCH], T (&out)[RCH],
     for (int q = 0; q < RCH; ++q) reg2d_row<T, RCH, EX, EY>(q, in, out, hu, hd, x, nx, y0, ny, alpha, r);
 }
 
-// One fused step of a tile: publish the wave's first and last row to the LDS
-// row exchange xb ([2 parities][2 rows][NW waves][64 lanes], parity s & 1),
-// meet at the barrier, read the neighbours' rows, step `in` into `out`.
+// The LDS row exchange of a tile: [2 parities][NW waves][first, last row][64
+// lanes] (the 128-wide tile's blocks hold four rows).  A lane addresses it
+// through `own`, its slot in its wave's block for one parity: the previous
+// wave's block sits one block (per_wave values) below, the next wave's one
+// above, so every access is an immediate offset from an address the step
+// loop keeps (no address arithmetic per step).
+template <typename T>
+struct RowExchange {
+    T *own0, *own1;               // per parity
+    const T *prev0, *prev1;       // own - per_wave, or own for the tile's first wave
+    bool has_prev, has_next;
+    __device__ RowExchange(T *xb, int per_wave) {
+        const int tx = threadIdx.x & 63;
+        const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        const int NW = blockDim.x >> 6;
+        has_prev = w > 0;
+        has_next = w + 1 < NW;
+        own0 = xb + w * per_wave + tx;
+        own1 = own0 + NW * per_wave;
+        prev0 = has_prev ? own0 - per_wave : own0;
+        prev1 = has_prev ? own1 - per_wave : own1;
+    }
+    // selects, not an indexed array: a runtime parity stays in registers
+    __device__ T *own(int p) const { return p ? own1 : own0; }
+    __device__ const T *prev(int p) const { return p ? prev1 : prev0; }
+};
+
+// One fused step of a tile: publish the wave's first and last row to the row
+// exchange (parity p), meet at the barrier, read the neighbours' rows (the
+// tile's first and last wave use their own edge rows there: the Neumann
+// mirror where the tile edge is the domain edge), step `in` into `out`.
 template <typename T, int RCH, int EX, bool EY>
-__device__ __forceinline__ void reg2d_step(const T (&in)[RCH], T (&out)[RCH], int s, int x, int nx,
-                                           int y0, int ny, T alpha, T r, T *xb)
+__device__ __forceinline__ void reg2d_step(const T (&in)[RCH], T (&out)[RCH], const RowExchange<T> &xe,
+                                           int p, int x, int nx, int y0, int ny, T alpha, T r)
 {
-    const int tx = threadIdx.x & 63;
-    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int NW = blockDim.x >> 6;
-    T *b = xb + (s & 1) * 2 * NW * 64;
-    b[w * 64 + tx] = in[0];
-    b[(NW + w) * 64 + tx] = in[RCH - 1];
+    T *own = xe.own(p);
+    own[0] = in[0];
+    own[64] = in[RCH - 1];
     __syncthreads();
-    const T hu = w > 0 ? b[(NW + w - 1) * 64 + tx] : in[0];
-    const T hd = w + 1 < NW ? b[(w + 1) * 64 + tx] : in[RCH - 1];
+    const T hu = xe.has_prev ? xe.prev(p)[64] : in[0];
+    const T hd = xe.has_next ? own[128] : in[RCH - 1];
     reg2d_substep<T, RCH, EX, EY>(in, out, hu, hd, x, nx, y0, ny, alpha, r);
 }
 
@@ -151,21 +176,22 @@ __device__ __forceinline__ void reg2d_step(const T (&in)[RCH], T (&out)[RCH], in
 // u -> v: the two register sets alternate and no value is moved.  FP64 steps
 // through one spare set and copies back, since a second full set of 16 double
 // rows would not fit the 128 VGPRs a 1024-thread workgroup allows.  xb: the
-// LDS row exchange (reg2d_step).
+// LDS row exchange, 4 * NW * 64 values.
 template <typename T, int RCH, int EX, bool EY>
 __device__ __forceinline__ void reg2d_steps(T (&v)[RCH], int x, int nx, int y0, int ny, T alpha, T r,
                                             int ksteps, T *xb)
 {
+    const RowExchange<T> xe(xb, 128);
     T u[RCH];
     int s = 0;
     if constexpr (sizeof(T) == 4) {
         for (; s + 1 < ksteps; s += 2) {
-            reg2d_step<T, RCH, EX, EY>(v, u, s, x, nx, y0, ny, alpha, r, xb);
-            reg2d_step<T, RCH, EX, EY>(u, v, s + 1, x, nx, y0, ny, alpha, r, xb);
+            reg2d_step<T, RCH, EX, EY>(v, u, xe, 0, x, nx, y0, ny, alpha, r);
+            reg2d_step<T, RCH, EX, EY>(u, v, xe, 1, x, nx, y0, ny, alpha, r);
         }
     }
     for (; s < ksteps; ++s) {
-        reg2d_step<T, RCH, EX, EY>(v, u, s, x, nx, y0, ny, alpha, r, xb);
+        reg2d_step<T, RCH, EX, EY>(v, u, xe, s & 1, x, nx, y0, ny, alpha, r);
 #pragma unroll
         for (int q = 0; q < RCH; ++q) v[q] = u[q];
     }

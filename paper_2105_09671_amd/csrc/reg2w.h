@@ -68,33 +68,30 @@ __device__ __forceinline__ void reg2w_row(int q, const T (&ia)[RCH], const T (&i
 }
 
 // One fused step of a wide tile, (ia, ib) -> (oa, ob): publish the wave's
-// first and last rows to the LDS exchange xb, [2 parities][first, last][a, b]
-// [NW waves][64 lanes], meet at the barrier, read the rows next to the wave's
-// own (the tile's first and last wave use their own edge rows there: the
-// Neumann mirror where the tile edge is the domain edge), step every row.
+// first and last rows to the row exchange (reg2d.h's RowExchange with blocks
+// of four rows: first a, first b, last a, last b; parity p), meet at the
+// barrier, read the rows next to the wave's own (the tile's first and last
+// wave use their own edge rows there: the Neumann mirror where the tile edge
+// is the domain edge), step every row.
 template <typename T, int RCH, int EX, bool EY>
 __device__ __forceinline__ void reg2w_step(const T (&ia)[RCH], const T (&ib)[RCH], T (&oa)[RCH],
-                                           T (&ob)[RCH], int s, int y0, int ny, T alpha, T r,
-                                           T *xb)
+                                           T (&ob)[RCH], const RowExchange<T> &xe, int p, int y0,
+                                           int ny, T alpha, T r)
 {
-    const int tx = threadIdx.x & 63;
-    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int NW = blockDim.x >> 6;
-    T *bf = xb + (s & 1) * 4 * NW * 64;   // first rows: a at [w], b at [NW + w]
-    T *bl = bf + 2 * NW * 64;             // last rows
-    bf[w * 64 + tx] = ia[0];
-    bf[(NW + w) * 64 + tx] = ib[0];
-    bl[w * 64 + tx] = ia[RCH - 1];
-    bl[(NW + w) * 64 + tx] = ib[RCH - 1];
+    T *own = xe.own(p);
+    own[0] = ia[0];
+    own[64] = ib[0];
+    own[128] = ia[RCH - 1];
+    own[192] = ib[RCH - 1];
     __syncthreads();
     T hua = ia[0], hub = ib[0], hda = ia[RCH - 1], hdb = ib[RCH - 1];
-    if (w > 0) {
-        hua = bl[(w - 1) * 64 + tx];
-        hub = bl[(NW + w - 1) * 64 + tx];
+    if (xe.has_prev) {
+        hua = xe.prev(p)[128];
+        hub = xe.prev(p)[192];
     }
-    if (w + 1 < NW) {
-        hda = bf[(w + 1) * 64 + tx];
-        hdb = bf[(NW + w + 1) * 64 + tx];
+    if (xe.has_next) {
+        hda = own[256];
+        hdb = own[320];
     }
 #pragma unroll
     for (int q = 0; q < RCH; ++q)
@@ -102,19 +99,22 @@ __device__ __forceinline__ void reg2w_step(const T (&ia)[RCH], const T (&ib)[RCH
 }
 
 // The fused steps of one wide tile for one edge variant, two per trip so the
-// two register sets alternate and no value is moved.
+// two register sets alternate and no value is moved.  xb: the row exchange,
+// 8 * NW * 64 values.
 template <typename T, int RCH, int EX, bool EY>
 __device__ __forceinline__ void reg2w_steps(T (&va)[RCH], T (&vb)[RCH], int y0, int ny, T alpha,
                                             T r, int ksteps, T *xb)
 {
+    const RowExchange<T> xe(xb, 256);
     T ua[RCH], ub[RCH];
     int s = 0;
     for (; s + 1 < ksteps; s += 2) {
-        reg2w_step<T, RCH, EX, EY>(va, vb, ua, ub, s, y0, ny, alpha, r, xb);
-        reg2w_step<T, RCH, EX, EY>(ua, ub, va, vb, s + 1, y0, ny, alpha, r, xb);
+        reg2w_step<T, RCH, EX, EY>(va, vb, ua, ub, xe, 0, y0, ny, alpha, r);
+        reg2w_step<T, RCH, EX, EY>(ua, ub, va, vb, xe, 1, y0, ny, alpha, r);
     }
     if (s < ksteps) {
-        reg2w_step<T, RCH, EX, EY>(va, vb, ua, ub, s, y0, ny, alpha, r, xb);
+        // the last step follows an odd one (or is the only step)
+        reg2w_step<T, RCH, EX, EY>(va, vb, ua, ub, xe, 0, y0, ny, alpha, r);
 #pragma unroll
         for (int q = 0; q < RCH; ++q) {
             va[q] = ua[q];
