@@ -39,7 +39,7 @@ constexpr int kRegRows = 16;
 template <typename T>
 hipError_t launch_tile2d_reg(const T *src, T *dst, int nx, int ny, T alpha, T r, const Tile2D &t,
                              int ksteps, hipStream_t stream);
-// LDS of the register kernel's row exchange: [2 parities][2 rows][waves][64]
+// LDS of the register kernel's row exchange: [2 parities][waves][2 rows][64]
 inline size_t tile2d_reg_lds_bytes(int LY, size_t elem) {
     return (size_t)4 * (LY / kRegRows) * 64 * elem;
 }
