@@ -63,8 +63,10 @@ typedef enum { AC_F32 = 0, AC_F64 = 1 } ac_dtype;
  *   kernel    0 = choose; 2D: AC_KERNEL_2D_TILED / _INPLACE / _REG / _REGW
  *             (_REG needs tile_x = 64 and tile_y a multiple of 16 up to 256,
  *             _REGW tile_x = 128 (its default), tile_y a multiple of 8 up to
- *             128 and nx >= 128, _INPLACE tile_x = 64; batches take 64-wide
- *             tiles only); 3D: AC_KERNEL_3D_STREAM / _REG (_REG needs tile_x =
+ *             128 and nx >= 128, _INPLACE tile_x = 64; in a batch, _REGW
+ *             gives the instances at least 128 wide 128 x tile_y tiles and
+ *             the others 64 x 2*tile_y ones, every other kernel 64-wide
+ *             tiles); 3D: AC_KERNEL_3D_STREAM / _REG (_REG needs tile_x =
  *             64, tile_y a multiple of 4 up to 32 and tb_depth <= 8 in
  *             FP32, <= 6 in FP64)
  * Any valid choice gives bitwise the same result: every cell is always
@@ -175,7 +177,9 @@ typedef struct {
  * holds, tiles taken from ticket counters, a bounded-wait phase barrier per
  * temporal block; a timeout ends the kernel early and is reported by
  * ac_check).  The launch shape comes from `tune`, else from the autotuner's
- * table (ac_autotune_batched), else 64 x 128 tiles (FP64: 64 x 64).  A call
+ * table (ac_autotune_batched), else depth 8 with 128-wide register tiles of
+ * 96 rows (FP64: 64) for instances at least 128 cells wide and 64-wide ones
+ * of twice the height for narrower instances.  A call
  * longer than 2048 temporal blocks runs, in the graph mode, as repeated
  * 2048-block graphs plus a remainder.  Each instance gets exactly what
  * ac_step_2d computes for it, bit for bit. */
