@@ -89,34 +89,34 @@ Chunks plan_chunks(int64_t nsteps, int64_t k) {
 // share of a CU's time while every CU streams tiles (two resident per CU); a
 // is the rest of a launch (its start, the first loads that no step overlaps,
 // the last stores).  Fitted by least squares in relative error to launches
-// timed on FP32 grids 1024^2 .. 6144^2 (with 2048 x 1024 and 4096 x 2048) and
-// FP64 grids 512^2 .. 4096^2, every pair on each grid in one run.  A small
+// timed on FP32 grids 512^2 .. 16384^2 (with 2048 x 1024 and 4096 x 2048) and
+// FP64 grids 512^2 .. 16384 x 8192, every pair on each grid in one run.  A small
 // grid's launch is mostly a, so deep steps and few tiles win there; a large
 // grid's is mostly b per tile.  Register tiles of 6 or 10 waves (64 x
 // 96, 64 x 160) measured 10-25 % slower than 4, 8 or 12 and are left out, as
 // are 128 x 128 FP64 tiles (16 waves), slower than 128 x 64 on every grid.
 struct TileTime { int K, LY; double a, b; };
 static const TileTime kRegF32[] = {
-    {5, 64, 3.18, 1.576}, {5, 128, 2.52, 3.421}, {5, 192, 2.24, 5.353},
-    {6, 64, 3.94, 1.634}, {6, 128, 3.28, 3.440}, {6, 192, 3.08, 5.314},
-    {7, 64, 4.41, 1.670}, {7, 128, 3.70, 3.693}, {7, 192, 3.77, 5.456},
-    {8, 64, 4.74, 1.923}, {8, 128, 4.37, 3.788}, {8, 192, 3.54, 5.839}};
+    {5, 64, 3.16, 1.624}, {5, 128, 2.33, 3.540}, {5, 192, 1.94, 5.460},
+    {6, 64, 3.79, 1.676}, {6, 128, 3.09, 3.521}, {6, 192, 2.82, 5.391},
+    {7, 64, 4.18, 1.752}, {7, 128, 3.38, 3.800}, {7, 192, 3.34, 5.602},
+    {8, 64, 4.52, 1.951}, {8, 128, 3.96, 3.906}, {8, 192, 3.36, 5.891}};
 static const TileTime kRegF64[] = {
-    {5, 64, 3.66, 2.588}, {5, 128, 3.10, 5.590}, {5, 192, 2.64, 8.948},
-    {6, 64, 4.27, 2.719}, {6, 128, 3.95, 5.837}, {6, 192, 3.96, 9.127},
-    {7, 64, 4.75, 2.945}, {7, 128, 4.43, 6.338}, {7, 192, 4.76, 9.681},
-    {8, 64, 5.20, 3.209}, {8, 128, 5.13, 6.555}, {8, 192, 4.76, 10.204}};
+    {5, 64, 2.74, 2.768}, {5, 128, 2.10, 5.931}, {5, 192, 1.41, 9.449},
+    {6, 64, 3.49, 2.750}, {6, 128, 2.87, 6.165}, {6, 192, 2.85, 9.403},
+    {7, 64, 3.93, 2.959}, {7, 128, 3.46, 6.514}, {7, 192, 3.67, 9.905},
+    {8, 64, 4.34, 3.204}, {8, 128, 4.20, 6.662}, {8, 192, 3.74, 10.211}};
 // 128-wide register tiles (two columns per lane)
 static const TileTime kRegWF32[] = {
-    {5, 32, 3.98, 1.390}, {5, 64, 3.30, 3.158}, {5, 96, 3.00, 5.281}, {5, 128, 1.90, 7.517},
-    {6, 32, 4.39, 1.456}, {6, 64, 4.09, 3.084}, {6, 96, 3.60, 5.006}, {6, 128, 3.08, 7.047},
-    {7, 32, 4.31, 1.633}, {7, 64, 4.39, 3.522}, {7, 96, 4.43, 5.267}, {7, 128, 3.88, 7.570},
-    {8, 32, 5.11, 1.778}, {8, 64, 4.90, 3.606}, {8, 96, 4.64, 5.584}, {8, 128, 4.54, 7.486}};
+    {5, 32, 3.59, 1.417}, {5, 64, 2.79, 3.274}, {5, 96, 2.37, 5.398}, {5, 128, 1.44, 7.557},
+    {6, 32, 3.97, 1.497}, {6, 64, 3.60, 3.147}, {6, 96, 3.10, 5.065}, {6, 128, 2.46, 7.239},
+    {7, 32, 4.08, 1.636}, {7, 64, 3.73, 3.607}, {7, 96, 3.60, 5.407}, {7, 128, 2.85, 7.961},
+    {8, 32, 4.53, 1.778}, {8, 64, 4.13, 3.735}, {8, 96, 3.91, 5.655}, {8, 128, 3.68, 7.760}};
 static const TileTime kRegWF64[] = {
-    {5, 32, 3.43, 2.435}, {5, 64, 2.53, 5.575},
-    {6, 32, 3.80, 2.409}, {6, 64, 2.99, 5.597},
-    {7, 32, 4.14, 2.655}, {7, 64, 3.65, 6.074},
-    {8, 32, 4.41, 2.738}, {8, 64, 4.21, 5.973}};
+    {5, 32, 3.00, 2.407}, {5, 64, 1.73, 5.657},
+    {6, 32, 3.33, 2.358}, {6, 64, 2.39, 5.487},
+    {7, 32, 3.55, 2.627}, {7, 64, 2.81, 6.005},
+    {8, 32, 3.82, 2.621}, {8, 64, 3.20, 5.882}};
 // in place in LDS: GLUPS of the whole chip (256 CUs) streaming tiles
 struct TileRate { int K, LY; double rate; };
 static const TileRate kInplaceF32[] = {{6, 64, 1603}, {7, 64, 1617}, {8, 64, 1645},
