@@ -98,18 +98,22 @@ batch_compact_kernel(const int4 *__restrict__ items, int n_items, const int *__r
 // End of a phase for this workgroup: publish its `mine` finished items and wait
 // until `target` items are finished in total.  Returns false once any
 // workgroup has given up waiting (after spin_limit polls or wall_limit ticks
-// of the constant-rate clock).
+// of the constant-rate clock).  Release fence, relaxed add, relaxed polls,
+// then one acquire fence: the counter's adds form one release sequence, so
+// the fences order every workgroup's stores before every other's loads.  An
+// acquire on each poll would invalidate the XCD's L2 at every poll, under the
+// workgroups still computing there.
 __device__ __forceinline__ bool phase_sync(unsigned *done, unsigned mine, unsigned target, int *err,
                                            long long spin_limit, long long wall_limit) {
     __shared__ int s_ok;
     __syncthreads();
     if (threadIdx.x == 0) {
-        __threadfence();   // publish this workgroup's stores device-wide
-        if (mine) atomicAdd(done, mine);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");   // publish this workgroup's stores
+        if (mine) __hip_atomic_fetch_add(done, mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         int ok = 1;
         long long spins = 0;
         const long long t0 = wall_clock64();
-        while (__hip_atomic_load(done, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        while (__hip_atomic_load(done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
             if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { ok = 0; break; }
             if (++spins > spin_limit || wall_clock64() - t0 > wall_limit) {
                 atomicExch(err, 1);
@@ -118,7 +122,7 @@ __device__ __forceinline__ bool phase_sync(unsigned *done, unsigned mine, unsign
             }
             __builtin_amdgcn_s_sleep(4);
         }
-        __threadfence();   // see every other workgroup's stores
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // see every other workgroup's stores
         s_ok = ok;
     }
     __syncthreads();
